@@ -1,0 +1,176 @@
+"""CPU oracle for sparse assembly -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never imports it and shares no code with it.
+
+``assemble`` wraps the plain-C definition in ``fsparse_oracle.c`` (serial,
+one thread); ``brute`` holds an independent pure-Python dense accumulation
+used to pin the C oracle on tiny inputs.  ``backward`` and ``reassemble``
+are the definitions of the derivative of the assembled values with respect
+to the triplet values and of re-assembly with new values.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fsparse_oracle.c")
+_LIB = os.path.join(_HERE, "libfsparse_oracle.so")
+
+OK, E_INDEX, E_ARG, E_NOMEM = 0, 1, 2, 3
+
+
+class OracleIndexError(ValueError):
+    """An index below 1, or above m / n when those are given."""
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (serial, no fast-math, no contraction)."""
+    if force or not os.path.exists(_LIB) or (
+            os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                        "-std=c99", "-shared", "-fPIC", _SRC, "-o", tmp],
+                       check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        i64 = ctypes.c_int64
+        for name, vt in (("oracle_assemble_f64", np.float64),
+                         ("oracle_assemble_f32", np.float32)):
+            vp = np.ctypeslib.ndpointer(vt, flags="C_CONTIGUOUS")
+            f = getattr(lib, name)
+            f.restype = ctypes.c_int
+            f.argtypes = [i32p, i32p, vp, i64, i64, i64, i32p, i32p, vp,
+                          ctypes.c_void_p, ctypes.POINTER(i64)]
+        lib.oracle_dims.restype = ctypes.c_int
+        lib.oracle_dims.argtypes = [i32p, i32p, i64, ctypes.POINTER(i64),
+                                    ctypes.POINTER(i64)]
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class Result:
+    jcS: np.ndarray      # int32 [n+1]
+    irS: np.ndarray      # int32 [nnz]
+    prS: np.ndarray      # value dtype [nnz]
+    slot: np.ndarray     # int32 [len]
+    m: int
+    n: int
+
+    @property
+    def nnz(self) -> int:
+        return int(self.jcS[-1])
+
+
+def dims(ii, jj):
+    """(m, n) = largest row / column index; raises on an index below 1."""
+    lib = _load()
+    ii = np.ascontiguousarray(ii, dtype=np.int32)
+    jj = np.ascontiguousarray(jj, dtype=np.int32)
+    m, n = ctypes.c_int64(), ctypes.c_int64()
+    st = lib.oracle_dims(ii, jj, ii.shape[0], ctypes.byref(m),
+                         ctypes.byref(n))
+    if st == E_INDEX:
+        raise OracleIndexError("index below 1")
+    if st != OK:
+        raise RuntimeError("oracle_dims failed: %d" % st)
+    return int(m.value), int(n.value)
+
+
+def assemble(ii, jj, ss, m: Optional[int] = None, n: Optional[int] = None,
+             ) -> Result:
+    """S = sparse(ii, jj, ss, m, n) by the plain definition (see the C file)."""
+    lib = _load()
+    ii = np.ascontiguousarray(ii, dtype=np.int32)
+    jj = np.ascontiguousarray(jj, dtype=np.int32)
+    ss = np.ascontiguousarray(ss)
+    if ss.dtype not in (np.float64, np.float32):
+        ss = ss.astype(np.float64)
+    L = ii.shape[0]
+    assert jj.shape[0] == L and ss.shape[0] == L
+    if m is None or n is None:
+        dm, dn = dims(ii, jj)
+        m = dm if m is None else m
+        n = dn if n is None else n
+    jcS = np.zeros(n + 1, dtype=np.int32)
+    irS = np.zeros(max(L, 1), dtype=np.int32)
+    prS = np.zeros(max(L, 1), dtype=ss.dtype)
+    slot = np.zeros(max(L, 1), dtype=np.int32)
+    nnz = ctypes.c_int64()
+    f = (lib.oracle_assemble_f64 if ss.dtype == np.float64
+         else lib.oracle_assemble_f32)
+    st = f(ii, jj, ss, L, m, n, jcS, irS, prS,
+           slot.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nnz))
+    if st == E_INDEX:
+        raise OracleIndexError("index out of range")
+    if st != OK:
+        raise RuntimeError("oracle assemble failed: %d" % st)
+    k = int(nnz.value)
+    return Result(jcS, irS[:k].copy(), prS[:k].copy(), slot[:L].copy(),
+                  int(m), int(n))
+
+
+def reassemble(res: Result, ii, jj, ss) -> np.ndarray:
+    """Values of a re-assembly with new ``ss`` on the same index pairs.
+
+    By definition this is a fresh assembly of the same triplets; the pattern
+    does not depend on the values, so only prS is returned.
+    """
+    return assemble(ii, jj, ss, res.m, res.n).prS
+
+
+def backward(slot, grad_prS) -> np.ndarray:
+    """d(prS)/d(ss) applied to an upstream gradient.
+
+    prS[t] = sum over k with slot[k] = t of ss[k] (Section 2.2, eq. (2.3)),
+    so d prS[t] / d ss[k] = [slot[k] = t] and grad_ss[k] = grad_prS[slot[k]].
+    """
+    return np.asarray(grad_prS)[np.asarray(slot)]
+
+
+def assemble_columns(ii, jj, ss, m: int, n: int, cols: Sequence[int],
+                     full_jcS: Optional[np.ndarray] = None):
+    """Exact oracle output for a sample of (zero-based) columns only.
+
+    Keeping only the triplets whose column is sampled keeps their relative
+    k order, and the sum for a pair only involves that pair's triplets, so
+    the per-column row lists and values are exactly those of the full
+    assembly.  Returns {col: (rows, values)} and, if ``full_jcS`` is given,
+    the global slot of every kept triplet.
+    """
+    cols = np.asarray(sorted(set(int(c) for c in cols)), dtype=np.int64)
+    jj = np.asarray(jj)
+    keep = np.isin(jj - 1, cols)
+    kidx = np.nonzero(keep)[0]
+    sub = assemble(np.asarray(ii)[keep], jj[keep], np.asarray(ss)[keep], m, n)
+    out = {}
+    for c in cols:
+        a, b = sub.jcS[c], sub.jcS[c + 1]
+        out[int(c)] = (sub.irS[a:b].copy(), sub.prS[a:b].copy())
+    gslot = None
+    if full_jcS is not None:
+        cj = jj[keep].astype(np.int64) - 1
+        gslot = (np.asarray(full_jcS)[cj].astype(np.int64)
+                 + (sub.slot.astype(np.int64) - sub.jcS[cj]))
+    return out, kidx, gslot
+
+
+from . import brute  # noqa: E402  (pure Python, no C)

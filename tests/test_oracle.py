@@ -1,0 +1,326 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+These tests never touch the HIP path.  Each pin is chosen so that a
+plausible mistake in the oracle (a dropped or reordered term of the fold, a
+wrong row/column offset, transposed operands, a wrong pair grouping, a lost
+-0.0 / zero-sum entry) fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+import workloads as W
+from golden.load import load
+
+EX = load("worked_example.txt")
+
+
+def i32(a):
+    return np.asarray(a, dtype=np.int32)
+
+
+# ---------------------------------------------------------------------------
+# worked example printed in the paper (Section 2.1, Section 2.3.4)
+# ---------------------------------------------------------------------------
+def test_worked_example_unordered_input():
+    r = oracle.assemble(i32(EX["example_i"]), i32(EX["example_j"]),
+                        EX["example_s"])
+    assert (r.m, r.n) == (4, 4)             # implicit size, Section 2.1
+    np.testing.assert_array_equal(r.prS, EX["prS"])
+    np.testing.assert_array_equal(r.irS, EX["irS"])
+    np.testing.assert_array_equal(r.jcS, EX["jcS"])
+    np.testing.assert_array_equal(r.slot, EX["example_irank"])
+    # JJ[irank[k]] = jj[k] is column sorted and indexed by jcS
+    JJ = np.repeat(np.arange(1, 5), np.diff(r.jcS))
+    np.testing.assert_array_equal(JJ, EX["example_JJ"])
+    np.testing.assert_array_equal(JJ[r.slot], EX["example_j"])
+
+
+def test_worked_example_sorted_input():
+    r = oracle.assemble(i32(EX["sorted_i"]), i32(EX["sorted_j"]),
+                        EX["sorted_s"])
+    np.testing.assert_array_equal(r.prS, EX["prS"])
+    np.testing.assert_array_equal(r.irS, EX["irS"])
+    np.testing.assert_array_equal(r.jcS, EX["jcS"])
+    np.testing.assert_array_equal(r.slot, EX["sorted_irank"])
+
+
+def test_worked_example_brute():
+    jc, ir, pr, sl = brute.assemble(EX["example_i"], EX["example_j"],
+                                    EX["example_s"], 4, 4)
+    np.testing.assert_array_equal(pr, EX["prS"])
+    np.testing.assert_array_equal(ir, EX["irS"])
+    np.testing.assert_array_equal(jc, EX["jcS"])
+    np.testing.assert_array_equal(sl, EX["example_irank"])
+
+
+def test_transposed_operands_differ():
+    # swapping rows and columns assembles S^T, which is not S
+    r = oracle.assemble(i32(EX["example_j"]), i32(EX["example_i"]),
+                        EX["example_s"])
+    assert not np.array_equal(r.irS, EX["irS"])
+
+
+# ---------------------------------------------------------------------------
+# brute force on tiny inputs, bit for bit
+# ---------------------------------------------------------------------------
+def _tiny_case(rng, dtype):
+    m = int(rng.integers(1, 13))
+    n = int(rng.integers(1, 13))
+    L = int(rng.integers(0, 65))
+    # heavy duplication: draw from a small sub-range sometimes
+    hm = int(rng.integers(1, m + 1))
+    hn = int(rng.integers(1, n + 1))
+    ii = rng.integers(1, hm + 1, size=L).astype(np.int32)
+    jj = rng.integers(1, hn + 1, size=L).astype(np.int32)
+    kind = rng.integers(0, 4)
+    if kind == 0:
+        ss = rng.standard_normal(L)
+    elif kind == 1:
+        ss = rng.integers(-3, 4, size=L).astype(np.float64)   # cancellations
+    elif kind == 2:
+        ss = rng.choice([0.0, -0.0, 1e16, -1e16, 1.0, 0.1], size=L)
+    else:
+        ss = rng.standard_normal(L) * 10.0 ** rng.integers(-8, 9, size=L)
+    return ii, jj, ss.astype(dtype), m, n
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_oracle_matches_brute_force(dtype):
+    rng = np.random.default_rng(20150101)
+    for _ in range(400):
+        ii, jj, ss, m, n = _tiny_case(rng, dtype)
+        r = oracle.assemble(ii, jj, ss, m, n)
+        jc, ir, pr, sl = brute.assemble(ii, jj, ss, m, n)
+        np.testing.assert_array_equal(r.jcS, jc)
+        np.testing.assert_array_equal(r.irS, ir)
+        assert r.prS.dtype == pr.dtype
+        assert r.prS.tobytes() == pr.tobytes()      # bit-exact, incl. -0.0
+        np.testing.assert_array_equal(r.slot, sl)
+
+
+# ---------------------------------------------------------------------------
+# summation order and zero handling
+# ---------------------------------------------------------------------------
+def test_fold_is_increasing_k():
+    # (0 + 1) + 1e16 rounds to 1e16, then - 1e16 gives 0; any other order
+    # that starts from the large terms gives 1
+    r = oracle.assemble(i32([2, 2, 2]), i32([1, 1, 1]),
+                        np.array([1.0, 1e16, -1e16]), 2, 1)
+    assert r.prS.tolist() == [0.0]
+    r = oracle.assemble(i32([2, 2, 2]), i32([1, 1, 1]),
+                        np.array([1e16, -1e16, 1.0]), 2, 1)
+    assert r.prS.tolist() == [1.0]
+
+
+def test_fold_in_float32():
+    # 2^-25 is below half an ulp of 1.0f, so the f32 fold never moves, while
+    # rounding the f64 sum to f32 would (8 * 2^-25 = 2^-22 > ulp/2)
+    ss = np.array([1.0] + [2.0 ** -25] * 8, dtype=np.float32)
+    r = oracle.assemble(i32([1] * 9), i32([1] * 9), ss, 1, 1)
+    assert r.prS.dtype == np.float32
+    assert r.prS[0] == np.float32(1.0)
+    assert np.float32(ss.astype(np.float64).sum()) != np.float32(1.0)
+
+
+def test_negative_zero_and_cancellation_kept():
+    # a pair whose only contribution is -0.0 starts from +0.0 -> +0.0;
+    # a pair that cancels exactly keeps its (explicit zero) entry
+    r = oracle.assemble(i32([1, 2, 2]), i32([1, 1, 1]),
+                        np.array([-0.0, 3.0, -3.0]), 2, 1)
+    assert r.nnz == 2
+    assert not math.copysign(1.0, r.prS[0]) < 0
+    assert r.prS[1] == 0.0
+
+
+def test_single_pair_serial_sum():
+    rng = np.random.default_rng(7)
+    ss = rng.standard_normal(1000)
+    r = oracle.assemble(i32([5] * 1000), i32([3] * 1000), ss, 9, 4)
+    acc = 0.0
+    for v in ss:
+        acc = acc + v
+    assert r.nnz == 1 and r.prS[0] == acc
+    assert r.irS.tolist() == [4]
+    assert r.jcS.tolist() == [0, 0, 0, 1, 1]
+
+
+def test_no_duplicates_is_a_permutation():
+    rng = np.random.default_rng(3)
+    m, n = 50, 40
+    keys = rng.permutation(m * n)[:1500]
+    ii = (keys % m + 1).astype(np.int32)
+    jj = (keys // m + 1).astype(np.int32)
+    ss = rng.standard_normal(keys.shape[0])
+    r = oracle.assemble(ii, jj, ss, m, n)
+    assert r.nnz == keys.shape[0]
+    np.testing.assert_array_equal(r.prS[r.slot], ss)
+
+
+# ---------------------------------------------------------------------------
+# dimensions and errors (Section 2.2, appendix pre-processing)
+# ---------------------------------------------------------------------------
+def test_len_zero():
+    r = oracle.assemble(i32([]), i32([]), np.array([]))
+    assert (r.m, r.n, r.nnz) == (0, 0, 0) and r.jcS.tolist() == [0]
+    r = oracle.assemble(i32([]), i32([]), np.array([]), 2, 3)
+    assert r.jcS.tolist() == [0, 0, 0, 0]
+
+
+def test_given_dims_larger_than_max():
+    r = oracle.assemble(i32([1, 2]), i32([2, 2]), np.array([1.0, 2.0]), 5, 4)
+    assert r.jcS.tolist() == [0, 0, 2, 2, 2]
+    assert r.irS.tolist() == [0, 1]
+
+
+@pytest.mark.parametrize("ii,jj,m,n", [
+    ([0, 1], [1, 1], None, None), ([1, 1], [1, -2], None, None),
+    ([3, 1], [1, 1], 2, 2), ([1, 1], [1, 3], 2, 2)])
+def test_bad_index_raises(ii, jj, m, n):
+    with pytest.raises(oracle.OracleIndexError):
+        oracle.assemble(i32(ii), i32(jj), np.ones(2), m, n)
+
+
+# ---------------------------------------------------------------------------
+# library routine and paper generator
+# ---------------------------------------------------------------------------
+def test_pattern_against_numpy_unique_and_scipy():
+    scipy_sparse = pytest.importorskip("scipy.sparse")
+    t = W.uniform(20000, 300, 200, seed=5)
+    r = oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
+    key = (t.jj.astype(np.int64) - 1) * t.m + (t.ii - 1)
+    u, inv = np.unique(key, return_inverse=True)
+    np.testing.assert_array_equal(r.irS, u % t.m)
+    np.testing.assert_array_equal(r.slot, inv)
+    A = scipy_sparse.coo_matrix((t.ss, (t.ii - 1, t.jj - 1)),
+                                shape=(t.m, t.n)).tocsc()
+    A.sum_duplicates()
+    np.testing.assert_array_equal(r.jcS, A.indptr)
+    np.testing.assert_array_equal(r.irS, A.indices)
+    np.testing.assert_allclose(r.prS, A.data, rtol=1e-12, atol=1e-12)
+
+
+def test_ransparse_counts_are_exact():
+    siz, nzr, rep = 300, 6, 7
+    t = W.ransparse(siz, nzr, rep, seed=11)
+    assert t.L == siz * nzr * rep
+    r = oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
+    assert np.all(r.prS == np.round(r.prS))
+    assert r.prS.sum() == t.L
+    assert np.all(r.prS % rep == 0)          # every pick is repeated nrep times
+    key = (t.jj.astype(np.int64) - 1) * t.m + (t.ii - 1)
+    u, cnt = np.unique(key, return_counts=True)
+    np.testing.assert_array_equal(r.prS, cnt.astype(np.float64))
+    # each row has nnz_row picks, so between 1 and nnz_row entries per row
+    per_row = np.bincount(r.irS, minlength=siz)
+    assert per_row.min() >= 1 and per_row.max() <= nzr
+
+
+# ---------------------------------------------------------------------------
+# finite-element meshes: closed forms and P1 properties
+# ---------------------------------------------------------------------------
+def _csc_to_dense_pattern(r):
+    P = np.zeros((r.m, r.n), dtype=bool)
+    for c in range(r.n):
+        P[r.irS[r.jcS[c]:r.jcS[c + 1]], c] = True
+    return P
+
+
+@pytest.mark.parametrize("s", [2, 3, 5, 17])
+def test_fem2d_closed_form_and_symmetry(s):
+    t = W.fem2d(s, 0.2, seed=s)
+    L, nnz = W.fem2d_counts(s)
+    assert t.L == L
+    r = oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
+    assert r.nnz == nnz
+    _check_symmetric(r)
+
+
+@pytest.mark.parametrize("s", [2, 3, 6])
+def test_fem3d_closed_form_and_symmetry(s):
+    t = W.fem3d(s, 0.15, seed=s)
+    L, nnz = W.fem3d_counts(s)
+    assert t.L == L
+    r = oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
+    assert r.nnz == nnz
+    _check_symmetric(r)
+    # 3D interior diagonal collects 24 tetrahedra x 1 = 24 contributions
+    cnt = np.bincount(r.slot, minlength=r.nnz)
+    assert cnt.max() == (24 if s >= 3 else 6)
+
+
+def _check_symmetric(r):
+    D = np.zeros((r.m, r.n))
+    P = np.zeros((r.m, r.n), dtype=bool)
+    for c in range(r.n):
+        rows = r.irS[r.jcS[c]:r.jcS[c + 1]]
+        D[rows, c] = r.prS[r.jcS[c]:r.jcS[c + 1]]
+        P[rows, c] = True
+    assert np.array_equal(P, P.T)
+    # bitwise symmetric: (i,j) and (j,i) get the same terms in the same order
+    assert D.tobytes() == np.ascontiguousarray(D.T).tobytes()
+    # constants are in the kernel of the Laplacian: row sums vanish
+    assert np.abs(D.sum(axis=1)).max() <= 1e-12 * np.abs(D).max()
+
+
+# ---------------------------------------------------------------------------
+# invariants on a larger random input
+# ---------------------------------------------------------------------------
+def test_invariants_and_sampled_columns():
+    t = W.uniform(200000, 3000, 2000, seed=9)
+    t.ss = np.round(t.ss * 8)          # small integers: sums are exact
+    r = oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
+    jc = r.jcS.astype(np.int64)
+    assert jc[0] == 0 and jc[-1] == r.nnz and np.all(np.diff(jc) >= 0)
+    for c in range(t.n):
+        rows = r.irS[jc[c]:jc[c + 1]]
+        assert np.all(np.diff(rows) > 0)
+    assert r.irS.min() >= 0 and r.irS.max() < t.m
+    assert np.array_equal(np.unique(r.slot), np.arange(r.nnz))
+    np.testing.assert_array_equal(r.irS[r.slot], t.ii - 1)
+    assert np.all(jc[t.jj - 1] <= r.slot) and np.all(r.slot < jc[t.jj])
+    colsum_p = np.add.reduceat(r.prS, jc[:-1][np.diff(jc) > 0])
+    colsum_s = np.bincount(t.jj - 1, weights=t.ss, minlength=t.n)
+    np.testing.assert_array_equal(colsum_p, colsum_s[np.diff(jc) > 0])
+    # sampled columns give exactly the full answer on those columns
+    cols = [0, 5, 17, 1999]
+    out, kidx, gslot = oracle.assemble_columns(t.ii, t.jj, t.ss, t.m, t.n,
+                                               cols, full_jcS=r.jcS)
+    for c in cols:
+        np.testing.assert_array_equal(out[c][0], r.irS[jc[c]:jc[c + 1]])
+        np.testing.assert_array_equal(out[c][1], r.prS[jc[c]:jc[c + 1]])
+    np.testing.assert_array_equal(gslot, r.slot[kidx])
+
+
+# ---------------------------------------------------------------------------
+# backward: derivative of the assembled values
+# ---------------------------------------------------------------------------
+def test_backward_definition_fd_and_scatter():
+    torch = pytest.importorskip("torch")
+    t = W.fem2d(6, 0.2, seed=4)
+    r = oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
+    rng = np.random.default_rng(1)
+    w = rng.standard_normal(r.nnz)
+    g = oracle.backward(r.slot, w)
+    # central finite differences of loss(ss) = sum(w * prS(ss))
+    for k in rng.choice(t.L, size=40, replace=False):
+        h = 1e-3 * max(1.0, abs(t.ss[k]))
+        sp = t.ss.copy(); sp[k] += h
+        sm = t.ss.copy(); sm[k] -= h
+        lp = float(np.dot(w, oracle.reassemble(r, t.ii, t.jj, sp)))
+        lm = float(np.dot(w, oracle.reassemble(r, t.ii, t.jj, sm)))
+        assert abs((lp - lm) / (2 * h) - g[k]) <= 1e-8 * max(1.0, abs(g[k]))
+    # dense scatter reference gradient through torch autograd (CPU, fp64)
+    s = torch.tensor(t.ss, requires_grad=True)
+    D = torch.zeros(t.m * t.n, dtype=torch.float64)
+    lin = torch.tensor((t.jj.astype(np.int64) - 1) * t.m + (t.ii - 1))
+    D = D.index_add(0, lin, s)
+    Wd = torch.zeros(t.m * t.n, dtype=torch.float64)
+    pos = torch.tensor(np.repeat(np.arange(t.n), np.diff(r.jcS)) * t.m
+                       + r.irS)
+    Wd[pos] = torch.tensor(w)
+    (D * Wd).sum().backward()
+    assert s.grad.numpy().tobytes() == g.tobytes()
