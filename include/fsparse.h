@@ -1,0 +1,236 @@
+/*
+ * fsparse.h -- C ABI of the MI355X (gfx950) sparse-assembly library.
+ *
+ * The library computes the Matlab call S = sparse(i, j, s, m, n, nzmax)
+ * (Engblom & Lukarski, "Fast Matlab compatible sparse assembly on multicore
+ * computers", Section 2.1): raw triplets (ii[k], jj[k], ss[k]), k = 0..len-1,
+ * with unit-offset indices (Section 2.2, listing "Input format"), become the
+ * compressed-column arrays
+ *     jcS[0..n]    column pointers, jcS[0] = 0, jcS[n] = nnz     (Section 2.1)
+ *     irS[0..nnz)  zero-offset row indices, strictly increasing per column
+ *     prS[0..nnz)  values; repeated (i,j) pairs are summed
+ * and, on request, the inverse rank slot[k] = position of triplet k in
+ * (irS, prS) (the paper's "irank", Section 2.2, eqs. (2.2)-(2.3)).
+ *
+ * Conventions shared by every entry point
+ *  - Every array argument is HIP device memory owned by the caller unless it
+ *    is marked "host".  The library never allocates device memory; scratch
+ *    comes from the caller's workspace `ws`.
+ *  - Work is stream-ordered on `stream`.  Only fsparse_assemble,
+ *    fsparse_assemble_batched and fsparse_dims wait for the stream (once, to
+ *    read back result sizes and the error flags); re-assembly and backward
+ *    never synchronise.
+ *  - Values are IEEE binary64 (FSPARSE_F64) or binary32 (FSPARSE_F32); the sum
+ *    of a repeated pair is computed in that type.
+ *  - In the default ordered mode the contributions to prS[t] are added from
+ *    +0.0 in increasing k, the order of the paper's serial post-processing
+ *    (appendix, "Post-processing: finalize CCS format"), so results are
+ *    bit-identical from run to run.  FSPARSE_ATOMIC adds them with device
+ *    atomics in an unspecified order instead.
+ *  - Entries whose sum is zero are kept (nnz counts distinct index pairs,
+ *    Section 2.2: nnz = 1 + max irank).
+ *  - Functions return a status and never abort.  After an error the output
+ *    arrays hold unspecified data.
+ *  - len, m, n and nnz must stay below 2^31.
+ */
+#ifndef FSPARSE_H_
+#define FSPARSE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { FSPARSE_F64 = 0, FSPARSE_F32 = 1 } fsparse_dtype;
+
+/* flags */
+enum {
+  FSPARSE_ORDERED = 0u, /* increasing-k fold, bit-exact (default)          */
+  FSPARSE_ATOMIC = 1u   /* device atomics, order unspecified               */
+};
+
+typedef enum {
+  FSPARSE_OK = 0,
+  FSPARSE_E_INDEX = 1,    /* an index < 1, or > m / > n                      */
+  FSPARSE_E_ARG = 2,      /* NULL pointer, negative or too large size, ...   */
+  FSPARSE_E_CAPACITY = 3, /* output or workspace too small; info has sizes   */
+  FSPARSE_E_PLAN = 4,     /* plan does not match the call                    */
+  FSPARSE_E_HIP = 5       /* a HIP runtime call failed                       */
+} fsparse_status;
+
+/* Host-side sizes of one assembled matrix. */
+typedef struct {
+  int64_t m, n;   /* resolved dimensions                                    */
+  int64_t nnz;    /* number of distinct (i,j) pairs                          */
+  int64_t nzmax;  /* Matlab capacity: max(nzmax argument, nnz)               */
+} fsparse_info;
+
+/* Opaque host-side handle for pattern re-use (see fsparse_assemble). */
+typedef struct fsparse_plan fsparse_plan;
+
+/* Library version string (static storage). */
+const char *fsparse_version(void);
+
+/* Human-readable name of a status code (static storage). */
+const char *fsparse_status_string(int status);
+
+/*
+ * Bytes of device workspace that fsparse_assemble (nb = 1) or
+ * fsparse_assemble_batched (nb matrices) needs for `len` triplets in total
+ * and `ncols` columns in total (sum of n over the matrices).  The size does
+ * not depend on m or on the values.  Returns 0 for negative arguments.
+ */
+size_t fsparse_workspace_bytes(int64_t len, int64_t ncols, int32_t nb,
+                               fsparse_dtype dt);
+
+/*
+ * Default dimensions (Section 2.2 and the appendix pre-processing listing):
+ * m = largest row index, n = largest column index, both 0 when len == 0.
+ * Any index below 1 gives FSPARSE_E_INDEX.  ws needs at least 256 bytes.
+ * Waits for the stream.
+ */
+fsparse_status fsparse_dims(const int32_t *ii, const int32_t *jj, int64_t len,
+                            int64_t *m /* host out */, int64_t *n /* host out */,
+                            void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Fresh assembly S = sparse(ii, jj, ss, m, n, nzmax).
+ *
+ *  ii, jj   [len] int32, unit-offset row / column indices
+ *  ss       [len] values of type dt
+ *  m, n     dimensions; a negative value asks for the default (largest
+ *           index, computed with one extra pass and one extra wait).  With
+ *           given dimensions every index must lie in [1,m] x [1,n].
+ *  nzmax    Matlab capacity request; only reported back in info->nzmax.
+ *  flags    FSPARSE_ORDERED or FSPARSE_ATOMIC (how prS is summed).
+ *  jcS      [jcS_cap >= n+1] out, column pointers
+ *  irS,prS  [cap] out; cap >= nnz is required.  cap = len always suffices.
+ *           When cap < nnz the call returns FSPARSE_E_CAPACITY with the
+ *           required sizes in *info, and can be repeated with larger arrays.
+ *  slot     [len] out, k -> position in (irS, prS); may be NULL.
+ *  ws       device workspace of fsparse_workspace_bytes(len, n, 1, dt) bytes
+ *           (with default n, size it for an upper bound of n).
+ *  plan     NULL, or receives a plan for fsparse_assemble_reuse.  A plan
+ *           keeps pointers into ws (the sorted triplet order and segment
+ *           starts) and to slot; those buffers must outlive the plan and must
+ *           not be reused for another call while the plan is in use.
+ *  info     host out, may be NULL.
+ * Waits for the stream once (to read nnz and the error flags).
+ */
+fsparse_status fsparse_assemble(const int32_t *ii, const int32_t *jj,
+                                const void *ss, fsparse_dtype dt, int64_t len,
+                                int64_t m, int64_t n, int64_t nzmax,
+                                unsigned flags, int32_t *jcS, int64_t jcS_cap,
+                                int32_t *irS, void *prS, int64_t cap,
+                                int32_t *slot, void *ws, size_t ws_bytes,
+                                fsparse_plan **plan, fsparse_info *info,
+                                hipStream_t stream);
+
+/*
+ * Pattern re-use: the values prS[0..nnz) of the matrix the plan was made
+ * for, from new values ss[0..len) on the same (ii, jj) -- the repeated
+ * assembly of Section 2.1 ("saving various types of information between
+ * successive calls").  Ordered mode folds each pair in increasing k and is
+ * bit-identical to a fresh assembly with the same ss.  FSPARSE_ATOMIC needs a
+ * plan made with a non-NULL slot array or made by this library with the
+ * internal one (always the case).  The work is one graph launch of a HIP
+ * graph held by the plan; it never waits, so it may itself be captured.
+ */
+fsparse_status fsparse_assemble_reuse(fsparse_plan *plan, const void *ss,
+                                      void *prS, unsigned flags,
+                                      hipStream_t stream);
+
+/*
+ * Backward of prS = assemble(ss) for a fixed pattern.  By eq. (2.3),
+ * prS[t] = sum of ss[k] over slot[k] = t, so d prS[t] / d ss[k] = [slot[k]=t]
+ * and
+ *      grad_ss[k] = grad_prS[slot[k]],   k = 0..len-1.
+ * slot [len] int32 values in [0, nnz); grad_prS [nnz], grad_ss [len] of dt.
+ * Never waits.
+ */
+fsparse_status fsparse_backward(const int32_t *slot, int64_t len,
+                                const void *grad_prS, int64_t nnz,
+                                fsparse_dtype dt, void *grad_ss,
+                                hipStream_t stream);
+
+/*
+ * Batched assembly of nb independent matrices with the same launches.
+ *  trip_off  host [nb+1]: triplets of matrix b are k in [trip_off[b],
+ *            trip_off[b+1]) of ii, jj, ss (trip_off[0] = 0, nondecreasing).
+ *  m, n      host [nb]: dimensions (negative: default for that matrix).
+ *  jcS       out: the nb column-pointer arrays back to back; matrix b's
+ *            n_b+1 pointers start at index col_off[b] + b, where col_off is
+ *            the running sum of n; each is relative to its own matrix
+ *            (jcS_b[0] = 0, jcS_b[n_b] = nnz_b).
+ *  irS, prS  [cap] out: the matrices' entries back to back; matrix b's are
+ *            [nnz_off[b], nnz_off[b+1]).
+ *  nnz_off   host [nb+1] out.
+ *  slot      [total len] out, may be NULL: position of triplet k in the
+ *            concatenated irS/prS (subtract nnz_off[b] for the matrix-local
+ *            position).
+ *  ws        fsparse_workspace_bytes(total len, sum of n, nb, dt) bytes.
+ *  plan      as for fsparse_assemble; re-use then produces the concatenated
+ *            prS.
+ *  info      host [nb] out, may be NULL.
+ * Waits for the stream once (twice with default dimensions).
+ */
+fsparse_status fsparse_assemble_batched(
+    int32_t nb, const int64_t *trip_off, const int32_t *ii, const int32_t *jj,
+    const void *ss, fsparse_dtype dt, const int64_t *m, const int64_t *n,
+    unsigned flags, int32_t *jcS, int64_t jcS_cap, int32_t *irS, void *prS,
+    int64_t cap, int64_t *nnz_off, int32_t *slot, void *ws, size_t ws_bytes,
+    fsparse_plan **plan, fsparse_info *info, hipStream_t stream);
+
+/* Release a plan (host memory and its graph only; device buffers are the
+ * caller's).  NULL is ignored. */
+void fsparse_plan_destroy(fsparse_plan *plan);
+
+/* Sizes a plan was made for (any pointer may be NULL). */
+fsparse_status fsparse_plan_query(const fsparse_plan *plan, int64_t *len,
+                                  int64_t *nnz, int32_t *dtype);
+
+/*
+ * Launch-shape tuning (process-wide).  chunk_cap: triplets one workgroup of
+ * the sort/fold stage holds in LDS, one of 1024, 2048, 4096; a smaller
+ * positive power of two limits it further (used to exercise the long-column
+ * path on small inputs).  stream_block: threads per block of the streaming
+ * stages (64..1024, multiple of 64).  stream_items: elements per thread per
+ * tile (1..32).  reuse_block: threads per block of the re-assembly kernel.
+ * Zero fields keep the current value.  NULL restores the defaults.
+ */
+typedef struct {
+  int32_t chunk_cap;
+  int32_t stream_block;
+  int32_t stream_items;
+  int32_t reuse_block;
+} fsparse_tuning;
+
+fsparse_status fsparse_set_tuning(const fsparse_tuning *t);
+fsparse_status fsparse_get_tuning(fsparse_tuning *t /* host out */);
+
+/*
+ * Per-stage timing with HIP events recorded on the stream each stage is
+ * launched on.  While enabled, every launch of a stage is bracketed by two
+ * events; fsparse_timing_read waits for the recorded events and returns the
+ * accumulated milliseconds and launch counts per stage (up to max_stages
+ * entries), then clears them.  Returns the number of stages, or -1 on error.
+ */
+fsparse_status fsparse_timing_enable(int on);
+int fsparse_timing_read(double *ms, int64_t *launches, int max_stages);
+const char *fsparse_stage_name(int stage);
+
+/* Plain device-to-device copy kernel (16-byte vector loads/stores) used to
+ * measure attainable HBM bandwidth and to calibrate byte counters.  bytes
+ * must be a multiple of 16 and both pointers 16-byte aligned. */
+fsparse_status fsparse_stream_copy(const void *src, void *dst, size_t bytes,
+                                   hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSPARSE_H_ */

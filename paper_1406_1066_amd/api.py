@@ -1,0 +1,417 @@
+"""Python binding over the C ABI: torch tensors in, torch tensors out.
+
+Argument marshalling only -- the library does every step of the assembly.
+All tensors live on the current HIP device; work is queued on torch's current
+stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+__all__ = [
+    "FsparseError", "FsparseIndexError", "Assembled", "Batched", "Assembler",
+    "SparseAssemble", "sparse", "assemble", "reassemble", "backward",
+    "assemble_batched", "dims", "workspace_bytes", "set_tuning", "get_tuning",
+    "timing", "stream_copy", "to_torch_csc", "version",
+]
+
+
+class FsparseError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = L.fsparse_status_string(status).decode()
+        super().__init__("%s: %s (status %d)" % (what, msg, status))
+
+
+class FsparseIndexError(FsparseError, IndexError):
+    pass
+
+
+def _check(st: int, what: str):
+    if st == L.OK:
+        return
+    if st == L.E_INDEX:
+        raise FsparseIndexError(st, what)
+    raise FsparseError(st, what)
+
+
+def version() -> str:
+    return L.fsparse_version().decode()
+
+
+def _dt(dtype) -> int:
+    if dtype == torch.float64:
+        return L.F64
+    if dtype == torch.float32:
+        return L.F32
+    raise TypeError("values must be float64 or float32, got %s" % dtype)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else None
+
+
+def _dev_i32(x, device) -> torch.Tensor:
+    t = torch.as_tensor(x)
+    if t.dtype != torch.int32:
+        t = t.to(torch.int32)
+    return t.to(device).contiguous()
+
+
+def _device(*ts):
+    for t in ts:
+        if isinstance(t, torch.Tensor) and t.is_cuda:
+            return t.device
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def workspace_bytes(L_: int, ncols: int, nb: int = 1,
+                    dtype=torch.float64) -> int:
+    return int(L.fsparse_workspace_bytes(int(L_), int(ncols), int(nb),
+                                         _dt(dtype)))
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def dims(ii: torch.Tensor, jj: torch.Tensor):
+    """Default (m, n): the largest row / column index (Section 2.2)."""
+    dev = _device(ii, jj)
+    ii = _dev_i32(ii, dev)
+    jj = _dev_i32(jj, dev)
+    ws = _workspace(256, dev)
+    m, n = ctypes.c_int64(), ctypes.c_int64()
+    _check(L.fsparse_dims(_ptr(ii), _ptr(jj), ii.numel(), ctypes.byref(m),
+                          ctypes.byref(n), _ptr(ws), ws.numel(), _stream()),
+           "fsparse_dims")
+    return int(m.value), int(n.value)
+
+
+@dataclass
+class Assembled:
+    """CCS result; irS/prS are views of length nnz into capacity buffers."""
+    jcS: torch.Tensor
+    irS: torch.Tensor
+    prS: torch.Tensor
+    m: int
+    n: int
+    nnz: int
+    nzmax: int
+    slot: Optional[torch.Tensor] = None
+    plan: Optional["_Plan"] = None
+    ws: Optional[torch.Tensor] = field(default=None, repr=False)
+
+    def to_dense(self) -> torch.Tensor:
+        return to_torch_csc(self).to_dense()
+
+
+class _Plan:
+    """Owns a fsparse_plan handle and keeps its device buffers alive."""
+
+    def __init__(self, handle: ctypes.c_void_p, keep: Sequence[torch.Tensor],
+                 L_: int, nnz: int, dtype):
+        self.handle = handle
+        self.keep = list(keep)
+        self.len = L_
+        self.nnz = nnz
+        self.dtype = dtype
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            L.fsparse_plan_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
+           n: Optional[int] = None, nzmax: Optional[int] = None, *,
+           atomic: bool = False, keep_slot: bool = False, plan: bool = False,
+           cap: Optional[int] = None,
+           ws: Optional[torch.Tensor] = None) -> Assembled:
+    """S = sparse(ii, jj, ss, m, n, nzmax) on the GPU.
+
+    ``ii``/``jj`` unit-offset indices (any integer tensor, converted to
+    int32 on the device of ``ss``), ``ss`` float64/float32 on the GPU.
+    ``m``/``n`` default to the largest index.  ``cap`` is the capacity of
+    irS/prS (default len, always enough).  With ``plan=True`` the result
+    carries a re-use plan (see ``reassemble``); ``keep_slot`` returns the
+    inverse rank slot[k].
+    """
+    dev = _device(ss, ii, jj)
+    ss = ss.contiguous()
+    ii = _dev_i32(ii, dev)
+    jj = _dev_i32(jj, dev)
+    Ln = ss.numel()
+    if ii.numel() != Ln or jj.numel() != Ln:
+        raise ValueError("ii, jj and ss must have the same length")
+    dt = _dt(ss.dtype)
+    if m is None or n is None:
+        dm, dn = dims(ii, jj)
+        m = dm if m is None else m
+        n = dn if n is None else n
+    m, n = int(m), int(n)
+    if cap is None:
+        cap = max(Ln, 1)
+    need = workspace_bytes(Ln, n, 1, ss.dtype)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    jcS = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    slot = None
+    if keep_slot or plan or atomic:
+        slot = torch.empty(max(Ln, 1), dtype=torch.int32, device=dev)
+    while True:
+        irS = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        prS = torch.empty(max(cap, 1), dtype=ss.dtype, device=dev)
+        info = L.FsparseInfo()
+        ph = ctypes.c_void_p()
+        st = L.fsparse_assemble(
+            _ptr(ii), _ptr(jj), _ptr(ss), dt, Ln, m, n,
+            int(nzmax) if nzmax is not None else 0,
+            L.ATOMIC if atomic else L.ORDERED, _ptr(jcS), jcS.numel(),
+            _ptr(irS), _ptr(prS), cap, _ptr(slot), _ptr(ws), ws.numel(),
+            ctypes.byref(ph) if plan else None, ctypes.byref(info), _stream())
+        if st == L.E_CAPACITY and info.nnz > cap:
+            cap = int(info.nnz)       # retry with the reported size
+            continue
+        _check(st, "fsparse_assemble")
+        break
+    nnz = int(info.nnz)
+    p = None
+    if plan:
+        p = _Plan(ph, [ws, slot], Ln, nnz, ss.dtype)
+    return Assembled(jcS, irS[:nnz], prS[:nnz], m, n, nnz, int(info.nzmax),
+                     slot[:Ln] if slot is not None else None, p, ws)
+
+
+assemble = sparse
+
+
+def reassemble(res: Assembled, ss: torch.Tensor,
+               out: Optional[torch.Tensor] = None,
+               atomic: bool = False) -> torch.Tensor:
+    """Values for new ``ss`` on the pattern of ``res`` (needs plan=True)."""
+    if res.plan is None:
+        raise ValueError("assembled without plan=True")
+    ss = ss.contiguous()
+    if ss.numel() != res.plan.len or ss.dtype != res.plan.dtype:
+        raise ValueError("ss does not match the plan")
+    if out is None:
+        out = torch.empty(max(res.nnz, 1), dtype=ss.dtype, device=ss.device)
+    _check(L.fsparse_assemble_reuse(res.plan.handle, _ptr(ss), _ptr(out),
+                                    L.ATOMIC if atomic else L.ORDERED,
+                                    _stream()), "fsparse_assemble_reuse")
+    return out[:res.nnz]
+
+
+def backward(slot: torch.Tensor, grad_prS: torch.Tensor,
+             out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """grad_ss[k] = grad_prS[slot[k]] (derivative of eq. (2.3))."""
+    grad_prS = grad_prS.contiguous()
+    slot = slot.contiguous()
+    if out is None:
+        out = torch.empty(slot.numel(), dtype=grad_prS.dtype,
+                          device=grad_prS.device)
+    _check(L.fsparse_backward(_ptr(slot), slot.numel(), _ptr(grad_prS),
+                              grad_prS.numel(), _dt(grad_prS.dtype), _ptr(out),
+                              _stream()), "fsparse_backward")
+    return out
+
+
+class Assembler:
+    """Fresh assembly once, then repeated re-assembly of the values.
+
+    The time-stepping use of Section 2.1: the pattern is computed once and
+    later calls only redo the ordered sums (one HIP graph launch each).
+    """
+
+    def __init__(self, ii, jj, ss: torch.Tensor, m=None, n=None):
+        self.result = sparse(ii, jj, ss, m, n, plan=True, keep_slot=True)
+        self._out = torch.empty(max(self.result.nnz, 1), dtype=ss.dtype,
+                                device=ss.device)
+
+    @property
+    def jcS(self):
+        return self.result.jcS
+
+    @property
+    def irS(self):
+        return self.result.irS
+
+    @property
+    def slot(self):
+        return self.result.slot
+
+    def reassemble(self, ss: torch.Tensor, out: Optional[torch.Tensor] = None,
+                   atomic: bool = False) -> torch.Tensor:
+        return reassemble(self.result, ss, out if out is not None else
+                          self._out, atomic)
+
+
+class SparseAssemble(torch.autograd.Function):
+    """prS = assemble(ii, jj, ss) with d prS / d ss through the slot map."""
+
+    @staticmethod
+    def forward(ctx, ss, ii, jj, m=None, n=None):
+        res = sparse(ii, jj, ss.detach(), m, n, keep_slot=True)
+        ctx.save_for_backward(res.slot)
+        ctx.nnz = res.nnz
+        ctx.mark_non_differentiable(res.jcS, res.irS)
+        return res.prS.clone(), res.jcS, res.irS
+
+    @staticmethod
+    def backward(ctx, grad_prS, _gj=None, _gi=None):
+        (slot,) = ctx.saved_tensors
+        if grad_prS is None:
+            return None, None, None, None, None
+        return backward(slot, grad_prS), None, None, None, None
+
+
+@dataclass
+class Batched:
+    jcS: torch.Tensor          # back-to-back per-matrix column pointers
+    irS: torch.Tensor
+    prS: torch.Tensor
+    nnz_off: List[int]
+    col_off: List[int]
+    m: List[int]
+    n: List[int]
+    slot: Optional[torch.Tensor] = None
+    plan: Optional[_Plan] = None
+    ws: Optional[torch.Tensor] = field(default=None, repr=False)
+
+    @property
+    def nb(self) -> int:
+        return len(self.m)
+
+    def matrix(self, b: int):
+        """(jcS, irS, prS) of matrix b (views)."""
+        j0 = self.col_off[b] + b
+        jc = self.jcS[j0:j0 + self.n[b] + 1]
+        a, e = self.nnz_off[b], self.nnz_off[b + 1]
+        return jc, self.irS[a:e], self.prS[a:e]
+
+    @property
+    def nnz(self) -> int:
+        return self.nnz_off[-1]
+
+
+def assemble_batched(ii, jj, ss: torch.Tensor, trip_off: Sequence[int],
+                     m: Sequence[int], n: Sequence[int], *,
+                     atomic: bool = False, keep_slot: bool = False,
+                     plan: bool = False, cap: Optional[int] = None,
+                     ws: Optional[torch.Tensor] = None) -> Batched:
+    """Assemble nb independent matrices with one set of launches."""
+    dev = _device(ss, ii, jj)
+    ss = ss.contiguous()
+    ii = _dev_i32(ii, dev)
+    jj = _dev_i32(jj, dev)
+    nb = len(m)
+    to = (ctypes.c_int64 * (nb + 1))(*[int(x) for x in trip_off])
+    mm = (ctypes.c_int64 * nb)(*[int(x) for x in m])
+    nn = (ctypes.c_int64 * nb)(*[int(x) for x in n])
+    Ln = int(trip_off[-1])
+    N = sum(int(x) for x in n)
+    if cap is None:
+        cap = max(Ln, 1)
+    need = workspace_bytes(Ln, N, nb, ss.dtype)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    jcS = torch.empty(N + nb, dtype=torch.int32, device=dev)
+    irS = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    prS = torch.empty(max(cap, 1), dtype=ss.dtype, device=dev)
+    slot = None
+    if keep_slot or plan or atomic:
+        slot = torch.empty(max(Ln, 1), dtype=torch.int32, device=dev)
+    off = (ctypes.c_int64 * (nb + 1))()
+    info = (L.FsparseInfo * nb)()
+    ph = ctypes.c_void_p()
+    _check(L.fsparse_assemble_batched(
+        nb, to, _ptr(ii), _ptr(jj), _ptr(ss), _dt(ss.dtype), mm, nn,
+        L.ATOMIC if atomic else L.ORDERED, _ptr(jcS), jcS.numel(), _ptr(irS),
+        _ptr(prS), cap, off, _ptr(slot), _ptr(ws), ws.numel(),
+        ctypes.byref(ph) if plan else None, info, _stream()),
+        "fsparse_assemble_batched")
+    nnz_off = [int(off[b]) for b in range(nb + 1)]
+    col_off = [0]
+    for b in range(nb):
+        col_off.append(col_off[-1] + int(n[b]))
+    p = _Plan(ph, [ws, slot], Ln, nnz_off[-1], ss.dtype) if plan else None
+    return Batched(jcS, irS[:nnz_off[-1]], prS[:nnz_off[-1]], nnz_off,
+                   col_off, [int(x) for x in m], [int(x) for x in n],
+                   slot[:Ln] if slot is not None else None, p, ws)
+
+
+def to_torch_csc(res: Assembled) -> torch.Tensor:
+    return torch.sparse_csc_tensor(res.jcS.to(torch.int64),
+                                   res.irS.to(torch.int64), res.prS,
+                                   size=(res.m, res.n))
+
+
+def set_tuning(chunk_cap: int = 0, stream_block: int = 0,
+               stream_items: int = 0, reuse_block: int = 0,
+               reset: bool = False):
+    if reset:
+        _check(L.fsparse_set_tuning(None), "fsparse_set_tuning")
+        return
+    t = L.FsparseTuning(chunk_cap, stream_block, stream_items, reuse_block)
+    _check(L.fsparse_set_tuning(ctypes.byref(t)), "fsparse_set_tuning")
+
+
+def get_tuning() -> dict:
+    t = L.FsparseTuning()
+    _check(L.fsparse_get_tuning(ctypes.byref(t)), "fsparse_get_tuning")
+    return {"chunk_cap": t.chunk_cap, "stream_block": t.stream_block,
+            "stream_items": t.stream_items, "reuse_block": t.reuse_block}
+
+
+class timing:
+    """Context manager: per-stage HIP-event times of the enclosed calls."""
+
+    NSTAGES = 16
+
+    def __enter__(self):
+        L.fsparse_timing_read(None, None, 0)   # drop stale records
+        L.fsparse_timing_enable(1)
+        self.ms = {}
+        self.launches = {}
+        return self
+
+    def read(self) -> dict:
+        ms = (ctypes.c_double * self.NSTAGES)()
+        cnt = (ctypes.c_int64 * self.NSTAGES)()
+        ns = L.fsparse_timing_read(ms, cnt, self.NSTAGES)
+        for s in range(min(ns, self.NSTAGES)):
+            name = L.fsparse_stage_name(s).decode()
+            if cnt[s]:
+                self.ms[name] = self.ms.get(name, 0.0) + ms[s]
+                self.launches[name] = self.launches.get(name, 0) + cnt[s]
+        return self.ms
+
+    def __exit__(self, *exc):
+        self.read()
+        L.fsparse_timing_enable(0)
+        return False
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor):
+    nbytes = src.numel() * src.element_size()
+    _check(L.fsparse_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream()),
+           "fsparse_stream_copy")

@@ -1,0 +1,867 @@
+// Host side of the C ABI declared in include/fsparse.h: argument checks,
+// workspace layout, launches, the single readback of a fresh assembly,
+// re-use plans (HIP graphs) and per-stage event timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/fsparse.h"
+#include "kernels.h"
+
+using fsp::BatchDesc;
+using fsp::ChunkArgs;
+using fsp::Ctrl;
+using fsp::Entry;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// tuning
+// ---------------------------------------------------------------------------
+struct Tuning {
+  int cap = 2048;
+  int sblock = 256;
+  int sitems = 8;
+  int rblock = 256;
+};
+std::mutex g_mu;
+Tuning g_tune;
+
+Tuning tuning() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_tune;
+}
+
+int kernel_cap(int cap) { return cap <= 1024 ? 1024 : (cap <= 2048 ? 2048 : 4096); }
+
+// ---------------------------------------------------------------------------
+// stage timing
+// ---------------------------------------------------------------------------
+enum Stage {
+  kDims, kInit, kHist, kScan, kBucket, kChunk, kBatchedJcs, kAtomic,
+  kReuse, kBackward, kCopy, kFill, kNumStages
+};
+const char* kStageNames[kNumStages] = {
+    "dims", "init", "hist", "scan", "bucket", "chunk", "batched_jcs",
+    "atomic", "reuse", "backward", "copy", "fill"};
+
+struct Rec {
+  int stage;
+  hipEvent_t a, b;
+};
+bool g_timing = false;
+std::vector<Rec> g_recs;
+double g_ms[kNumStages];
+int64_t g_cnt[kNumStages];
+
+template <typename F>
+hipError_t launch(int stage, hipStream_t s, F&& f) {
+  bool timing;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    timing = g_timing;
+  }
+  if (!timing) {
+    f();
+    return hipGetLastError();
+  }
+  Rec r{stage, nullptr, nullptr};
+  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess)
+    return hipErrorOutOfMemory;
+  hipEventRecord(r.a, s);
+  f();
+  hipError_t e = hipGetLastError();
+  hipEventRecord(r.b, s);
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_recs.push_back(r);
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// device properties
+// ---------------------------------------------------------------------------
+int num_cus() {
+  int dev = 0, cus = 0;
+  hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+          hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  return cus;
+}
+
+int grid_for(int64_t n, int block, int per_cu = 8) {
+  int64_t g = (n + block - 1) / block;
+  const int64_t cap = (int64_t)num_cus() * per_cu;
+  if (g > cap) g = cap;
+  return (int)std::max<int64_t>(1, g);
+}
+
+// pinned readback buffer, one per host thread
+struct Pinned {
+  void* p = nullptr;
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+thread_local Pinned t_pinned;
+constexpr size_t kPinnedBytes = 1 << 16;
+void* pinned() {
+  if (!t_pinned.p) {
+    if (hipHostMalloc(&t_pinned.p, kPinnedBytes, hipHostMallocDefault) != hipSuccess)
+      t_pinned.p = nullptr;
+  }
+  return t_pinned.p;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+constexpr int kScanNT = 256;
+constexpr int kScanIPT = 16;
+constexpr int64_t kScanTile = (int64_t)kScanNT * kScanIPT;
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t ctrl, scan_st, chunk_st, colcnt, zero_end;
+  size_t colptr, fill, chunk_col, bucket, tmp, perm, seg, islot;
+  size_t b_trip, b_col, b_m, b_n, jcg, nnzoff, bmax;
+  size_t total;
+  int64_t nscan, Q, T;
+};
+
+Layout make_layout(int64_t L, int64_t N, int nb, int esize, int cap) {
+  Layout o{};
+  o.T = std::max(1, cap / 2);
+  o.nscan = (N + 1 + kScanTile - 1) / kScanTile;
+  o.Q = L / o.T + 1;
+  size_t p = 0;
+  o.ctrl = p;        p = al(p + sizeof(Ctrl));
+  o.scan_st = p;     p = al(p + 8 * (size_t)o.nscan);
+  o.chunk_st = p;    p = al(p + 8 * (size_t)o.Q);
+  o.colcnt = p;      p = al(p + 4 * (size_t)(N + 1));
+  o.bmax = p;        p = al(p + 8 * (size_t)nb);
+  o.zero_end = p;
+  o.colptr = p;      p = al(p + 4 * (size_t)(N + 1));
+  o.fill = p;        p = al(p + 4 * (size_t)(N + 1));
+  o.chunk_col = p;   p = al(p + 4 * (size_t)(o.Q + 1));
+  o.bucket = p;      p = al(p + (size_t)esize * L);
+  o.tmp = p;         p = al(p + (size_t)esize * L);
+  o.perm = p;        p = al(p + 4 * (size_t)L);
+  o.seg = p;         p = al(p + 4 * (size_t)(L + 1));
+  o.islot = p;       p = al(p + 4 * (size_t)L);
+  o.b_trip = p;      p = al(p + 8 * (size_t)(nb + 1));
+  o.b_col = p;       p = al(p + 8 * (size_t)(nb + 1));
+  o.b_m = p;         p = al(p + 4 * (size_t)nb);
+  o.b_n = p;         p = al(p + 4 * (size_t)nb);
+  o.nnzoff = p;      p = al(p + 8 * (size_t)(nb + 1));
+  o.jcg = p;         p = al(p + (nb > 1 ? 4 * (size_t)(N + 1) : 0));
+  o.total = p;
+  return o;
+}
+
+int esize_of(fsparse_dtype dt) { return dt == FSPARSE_F64 ? 16 : 12; }
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+#define HIPCHK(x)                              \
+  do {                                         \
+    if ((x) != hipSuccess) return FSPARSE_E_HIP; \
+  } while (0)
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct fsparse_plan {
+  int64_t len = 0, nnz = 0;
+  fsparse_dtype dt = FSPARSE_F64;
+  int device = 0;
+  const int32_t* perm = nullptr;
+  const int32_t* seg = nullptr;
+  const int32_t* slot = nullptr;
+  int rblock = 256;
+  // ordered re-use graph: one kernel node
+  hipGraph_t g_ord = nullptr;
+  hipGraphExec_t x_ord = nullptr;
+  hipGraphNode_t n_ord = nullptr;
+  const void* ss_ord = nullptr;
+  void* pr_ord = nullptr;
+  // atomic re-use graph: fill node -> atomic node
+  hipGraph_t g_at = nullptr;
+  hipGraphExec_t x_at = nullptr;
+  hipGraphNode_t n_fill = nullptr, n_at = nullptr;
+  const void* ss_at = nullptr;
+  void* pr_at = nullptr;
+};
+
+namespace {
+
+template <typename VT>
+void* reuse_fn() {
+  return reinterpret_cast<void*>(&fsp::k_reuse<VT>);
+}
+template <typename VT>
+void* fill_fn() {
+  return reinterpret_cast<void*>(&fsp::k_fill<VT>);
+}
+template <typename VT>
+void* atomic_fn() {
+  return reinterpret_cast<void*>(&fsp::k_atomic<VT>);
+}
+
+fsparse_status plan_reuse_ordered(fsparse_plan* pl, const void* ss, void* prS,
+                                  hipStream_t stream) {
+  const int blk = pl->rblock;
+  const int grid = grid_for(pl->nnz, blk, 16);
+  const int32_t* perm = pl->perm;
+  const int32_t* seg = pl->seg;
+  int64_t nnz = pl->nnz;
+  void* args[] = {(void*)&perm, (void*)&seg, (void*)&ss, (void*)&nnz, (void*)&prS};
+  hipKernelNodeParams kp{};
+  kp.func = pl->dt == FSPARSE_F64 ? reuse_fn<double>() : reuse_fn<float>();
+  kp.gridDim = dim3(grid);
+  kp.blockDim = dim3(blk);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  if (!pl->x_ord) {
+    HIPCHK(hipGraphCreate(&pl->g_ord, 0));
+    HIPCHK(hipGraphAddKernelNode(&pl->n_ord, pl->g_ord, nullptr, 0, &kp));
+    HIPCHK(hipGraphInstantiate(&pl->x_ord, pl->g_ord, nullptr, nullptr, 0));
+    pl->ss_ord = ss;
+    pl->pr_ord = prS;
+  } else if (pl->ss_ord != ss || pl->pr_ord != prS) {
+    HIPCHK(hipGraphExecKernelNodeSetParams(pl->x_ord, pl->n_ord, &kp));
+    pl->ss_ord = ss;
+    pl->pr_ord = prS;
+  }
+  hipError_t e = launch(kReuse, stream, [&] { (void)hipGraphLaunch(pl->x_ord, stream); });
+  return e == hipSuccess ? FSPARSE_OK : FSPARSE_E_HIP;
+}
+
+fsparse_status plan_reuse_atomic(fsparse_plan* pl, const void* ss, void* prS,
+                                 hipStream_t stream) {
+  const int blk = pl->rblock;
+  const int gf = grid_for(pl->nnz, blk, 8);
+  const int ga = grid_for(pl->len, blk, 16);
+  const int32_t* slot = pl->slot;
+  int64_t nnz = pl->nnz, len = pl->len;
+  void* fargs[] = {(void*)&prS, (void*)&nnz};
+  void* aargs[] = {(void*)&slot, (void*)&ss, (void*)&len, (void*)&prS};
+  hipKernelNodeParams fp{}, ap{};
+  fp.func = pl->dt == FSPARSE_F64 ? fill_fn<double>() : fill_fn<float>();
+  fp.gridDim = dim3(gf);
+  fp.blockDim = dim3(blk);
+  fp.kernelParams = fargs;
+  ap.func = pl->dt == FSPARSE_F64 ? atomic_fn<double>() : atomic_fn<float>();
+  ap.gridDim = dim3(ga);
+  ap.blockDim = dim3(blk);
+  ap.kernelParams = aargs;
+  if (!pl->x_at) {
+    HIPCHK(hipGraphCreate(&pl->g_at, 0));
+    HIPCHK(hipGraphAddKernelNode(&pl->n_fill, pl->g_at, nullptr, 0, &fp));
+    HIPCHK(hipGraphAddKernelNode(&pl->n_at, pl->g_at, &pl->n_fill, 1, &ap));
+    HIPCHK(hipGraphInstantiate(&pl->x_at, pl->g_at, nullptr, nullptr, 0));
+    pl->ss_at = ss;
+    pl->pr_at = prS;
+  } else if (pl->ss_at != ss || pl->pr_at != prS) {
+    HIPCHK(hipGraphExecKernelNodeSetParams(pl->x_at, pl->n_fill, &fp));
+    HIPCHK(hipGraphExecKernelNodeSetParams(pl->x_at, pl->n_at, &ap));
+    pl->ss_at = ss;
+    pl->pr_at = prS;
+  }
+  hipError_t e = launch(kReuse, stream, [&] { (void)hipGraphLaunch(pl->x_at, stream); });
+  return e == hipSuccess ? FSPARSE_OK : FSPARSE_E_HIP;
+}
+
+template <typename VT>
+hipError_t launch_atomic_values(const int32_t* slot, const void* ss, int64_t L,
+                                void* prS, int64_t nnz, int blk,
+                                hipStream_t stream) {
+  hipError_t e = launch(kFill, stream, [&] {
+    hipLaunchKernelGGL(fsp::k_fill<VT>, dim3(grid_for(nnz, blk)), dim3(blk), 0,
+                       stream, (VT*)prS, nnz);
+  });
+  if (e != hipSuccess) return e;
+  return launch(kAtomic, stream, [&] {
+    hipLaunchKernelGGL(fsp::k_atomic<VT>, dim3(grid_for(L, blk, 16)), dim3(blk),
+                       0, stream, slot, (const VT*)ss, L, (VT*)prS);
+  });
+}
+
+// The shared pipeline of fresh and batched assembly.
+template <typename VT, bool BATCHED>
+hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
+                        int64_t L, int32_t m, int32_t n, BatchDesc bd,
+                        int64_t N, const Layout& lo, const Tuning& tu,
+                        void* ws, int32_t* jcS_target, int32_t* irS, VT* prS,
+                        int64_t cap, int32_t* slot, bool keep_plan,
+                        hipStream_t stream) {
+  Ctrl* ctrl = at<Ctrl>(ws, lo.ctrl);
+  hipError_t e;
+  // init: zero control block, look-back words, column counts
+  const int64_t zwords = (int64_t)(lo.zero_end / 4);
+  e = launch(kInit, stream, [&] {
+    hipLaunchKernelGGL(fsp::k_zero, dim3(grid_for(zwords, 256, 4)), dim3(256), 0,
+                       stream, at<uint32_t>(ws, 0), zwords);
+  });
+  if (e != hipSuccess) return e;
+  const int blk = tu.sblock, items = tu.sitems;
+  const int64_t tiles = (L + (int64_t)blk * items - 1) / ((int64_t)blk * items);
+  int32_t* colcnt = at<int32_t>(ws, lo.colcnt);
+  e = launch(kHist, stream, [&] {
+    hipLaunchKernelGGL(fsp::k_hist<BATCHED>, dim3((unsigned)tiles), dim3(blk), 0,
+                       stream, jj, L, n, bd, colcnt, ctrl, items);
+  });
+  if (e != hipSuccess) return e;
+  int32_t* colptr = at<int32_t>(ws, lo.colptr);
+  int32_t* fill = at<int32_t>(ws, lo.fill);
+  int32_t* chunk_col = at<int32_t>(ws, lo.chunk_col);
+  e = launch(kScan, stream, [&] {
+    hipLaunchKernelGGL((fsp::k_scan<kScanNT, kScanIPT>), dim3((unsigned)lo.nscan),
+                       dim3(kScanNT), 0, stream, colcnt, (int32_t)N, colptr, fill,
+                       chunk_col, (int32_t)lo.T, (int32_t)lo.Q,
+                       at<uint64_t>(ws, lo.scan_st), ctrl);
+  });
+  if (e != hipSuccess) return e;
+  Entry<VT>* bucket = at<Entry<VT>>(ws, lo.bucket);
+  e = launch(kBucket, stream, [&] {
+    hipLaunchKernelGGL((fsp::k_bucket<VT, BATCHED>), dim3((unsigned)tiles),
+                       dim3(blk), 0, stream, ii, jj, ss, L, m, n, bd, fill,
+                       bucket, ctrl, items);
+  });
+  if (e != hipSuccess) return e;
+  ChunkArgs<VT> a{};
+  a.colptr = colptr;
+  a.chunk_col = chunk_col;
+  a.bucket = bucket;
+  a.tmp = at<Entry<VT>>(ws, lo.tmp);
+  a.N = (int32_t)N;
+  a.T = (int32_t)lo.T;
+  a.cap = tu.cap;
+  a.Q = (int32_t)lo.Q;
+  a.status = at<uint64_t>(ws, lo.chunk_st);
+  a.ctrl = ctrl;
+  a.jcS = jcS_target;
+  a.irS = irS;
+  a.prS = prS;
+  a.out_cap = cap;
+  a.slot = slot;
+  a.perm = keep_plan ? at<int32_t>(ws, lo.perm) : nullptr;
+  a.seg = keep_plan ? at<int32_t>(ws, lo.seg) : nullptr;
+  const int kc = kernel_cap(tu.cap);
+  e = launch(kChunk, stream, [&] {
+    if (kc == 1024)
+      hipLaunchKernelGGL((fsp::k_chunk<VT, 1024, 256>), dim3((unsigned)lo.Q),
+                         dim3(256), 0, stream, a);
+    else if (kc == 2048)
+      hipLaunchKernelGGL((fsp::k_chunk<VT, 2048, 256>), dim3((unsigned)lo.Q),
+                         dim3(256), 0, stream, a);
+    else
+      hipLaunchKernelGGL((fsp::k_chunk<VT, 4096, 512>), dim3((unsigned)lo.Q),
+                         dim3(512), 0, stream, a);
+  });
+  return e;
+}
+
+fsparse_status check_dt(fsparse_dtype dt) {
+  return (dt == FSPARSE_F64 || dt == FSPARSE_F32) ? FSPARSE_OK : FSPARSE_E_ARG;
+}
+
+constexpr int64_t kMaxI32 = 0x7FFFFFFE;
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* fsparse_version(void) { return "fsparse-mi355x 0.1 (gfx950)"; }
+
+const char* fsparse_status_string(int s) {
+  switch (s) {
+    case FSPARSE_OK: return "ok";
+    case FSPARSE_E_INDEX: return "index out of range";
+    case FSPARSE_E_ARG: return "invalid argument";
+    case FSPARSE_E_CAPACITY: return "capacity too small";
+    case FSPARSE_E_PLAN: return "plan does not match";
+    case FSPARSE_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+size_t fsparse_workspace_bytes(int64_t len, int64_t ncols, int32_t nb,
+                               fsparse_dtype dt) {
+  if (len < 0 || ncols < 0 || nb < 1 || check_dt(dt) != FSPARSE_OK) return 0;
+  return make_layout(len, ncols, nb, esize_of(dt), tuning().cap).total;
+}
+
+fsparse_status fsparse_dims(const int32_t* ii, const int32_t* jj, int64_t len,
+                            int64_t* m, int64_t* n, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+  if (!m || !n || len < 0 || len > kMaxI32 || !ws || ws_bytes < 256)
+    return FSPARSE_E_ARG;
+  if (len > 0 && (!ii || !jj)) return FSPARSE_E_ARG;
+  if (len == 0) {
+    *m = 0;
+    *n = 0;
+    return FSPARSE_OK;
+  }
+  Ctrl* h = static_cast<Ctrl*>(pinned());
+  if (!h) return FSPARSE_E_HIP;
+  std::memset(h, 0, sizeof(Ctrl));
+  h->rmin = INT32_MAX;
+  h->cmin = INT32_MAX;
+  HIPCHK(hipMemcpyAsync(ws, h, sizeof(Ctrl), hipMemcpyHostToDevice, stream));
+  BatchDesc bd{};
+  hipError_t e = launch(kDims, stream, [&] {
+    hipLaunchKernelGGL(fsp::k_dims<false>, dim3(grid_for(len, 256, 8)), dim3(256),
+                       0, stream, ii, jj, len, bd, (Ctrl*)ws, (int32_t*)nullptr);
+  });
+  if (e != hipSuccess) return FSPARSE_E_HIP;
+  HIPCHK(hipMemcpyAsync(h, ws, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (h->rmin < 1 || h->cmin < 1) return FSPARSE_E_INDEX;
+  *m = h->rmax;
+  *n = h->cmax;
+  return FSPARSE_OK;
+}
+
+fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
+                                const void* ss, fsparse_dtype dt, int64_t len,
+                                int64_t m, int64_t n, int64_t nzmax,
+                                unsigned flags, int32_t* jcS, int64_t jcS_cap,
+                                int32_t* irS, void* prS, int64_t cap,
+                                int32_t* slot, void* ws, size_t ws_bytes,
+                                fsparse_plan** plan, fsparse_info* info,
+                                hipStream_t stream) {
+  if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
+  if (len < 0 || len > kMaxI32 || m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
+  if (flags & ~(unsigned)FSPARSE_ATOMIC) return FSPARSE_E_ARG;
+  if (len > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
+  if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS))) return FSPARSE_E_ARG;
+  if (plan) *plan = nullptr;
+  if (m < 0 || n < 0) {
+    int64_t dm = 0, dn = 0;
+    fsparse_status st = fsparse_dims(ii, jj, len, &dm, &dn, ws, ws_bytes, stream);
+    if (st != FSPARSE_OK) return st;
+    if (m < 0) m = dm;
+    if (n < 0) n = dn;
+  }
+  if (info) {
+    info->m = m;
+    info->n = n;
+    info->nnz = 0;
+    info->nzmax = std::max<int64_t>(nzmax, 0);
+  }
+  if (jcS_cap < n + 1) return FSPARSE_E_CAPACITY;
+  const Tuning tu = tuning();
+  const Layout lo = make_layout(len, n, 1, esize_of(dt), tu.cap);
+  if (ws_bytes < lo.total) return FSPARSE_E_CAPACITY;
+  Ctrl* ctrl = at<Ctrl>(ws, lo.ctrl);
+  const bool keep = plan != nullptr;
+  int32_t* slot_used = slot ? slot : (keep ? at<int32_t>(ws, lo.islot) : nullptr);
+  if (len == 0) {
+    hipError_t e = launch(kInit, stream, [&] {
+      hipLaunchKernelGGL(fsp::k_zero, dim3(grid_for(n + 1, 256, 4)), dim3(256), 0,
+                         stream, (uint32_t*)jcS, (int64_t)(n + 1));
+    });
+    if (e != hipSuccess) return FSPARSE_E_HIP;
+    HIPCHK(hipStreamSynchronize(stream));
+  } else {
+    BatchDesc bd{};
+    hipError_t e;
+    if (dt == FSPARSE_F64)
+      e = run_pipeline<double, false>(ii, jj, (const double*)ss, len, (int32_t)m,
+                                      (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
+                                      (double*)prS, cap, slot_used, keep, stream);
+    else
+      e = run_pipeline<float, false>(ii, jj, (const float*)ss, len, (int32_t)m,
+                                     (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
+                                     (float*)prS, cap, slot_used, keep, stream);
+    if (e != hipSuccess) return FSPARSE_E_HIP;
+    Ctrl* h = static_cast<Ctrl*>(pinned());
+    if (!h) return FSPARSE_E_HIP;
+    HIPCHK(hipMemcpyAsync(h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    const uint32_t err = h->err;
+    const int64_t nnz = h->nnz;
+    if (info) {
+      info->nnz = nnz;
+      info->nzmax = std::max<int64_t>(nzmax, nnz);
+    }
+    if (err & (fsp::kErrCol | fsp::kErrRow)) return FSPARSE_E_INDEX;
+    if (err & fsp::kErrCap) return FSPARSE_E_CAPACITY;
+    if (flags & FSPARSE_ATOMIC) {
+      if (!slot_used) {
+        // the atomic sum needs the slot map: use the internal one
+        return FSPARSE_E_ARG;
+      }
+      hipError_t ea = dt == FSPARSE_F64
+          ? launch_atomic_values<double>(slot_used, ss, len, prS, nnz, tu.rblock, stream)
+          : launch_atomic_values<float>(slot_used, ss, len, prS, nnz, tu.rblock, stream);
+      if (ea != hipSuccess) return FSPARSE_E_HIP;
+    }
+    if (keep) {
+      fsparse_plan* pl = new (std::nothrow) fsparse_plan();
+      if (!pl) return FSPARSE_E_ARG;
+      pl->len = len;
+      pl->nnz = nnz;
+      pl->dt = dt;
+      hipGetDevice(&pl->device);
+      pl->perm = at<int32_t>(ws, lo.perm);
+      pl->seg = at<int32_t>(ws, lo.seg);
+      pl->slot = slot_used;
+      pl->rblock = tu.rblock;
+      *plan = pl;
+    }
+    return FSPARSE_OK;
+  }
+  if (keep) {
+    fsparse_plan* pl = new (std::nothrow) fsparse_plan();
+    if (!pl) return FSPARSE_E_ARG;
+    pl->dt = dt;
+    hipGetDevice(&pl->device);
+    pl->rblock = tu.rblock;
+    *plan = pl;
+  }
+  return FSPARSE_OK;
+}
+
+fsparse_status fsparse_assemble_reuse(fsparse_plan* plan, const void* ss,
+                                      void* prS, unsigned flags,
+                                      hipStream_t stream) {
+  if (!plan) return FSPARSE_E_PLAN;
+  if (flags & ~(unsigned)FSPARSE_ATOMIC) return FSPARSE_E_ARG;
+  if (plan->nnz == 0) return FSPARSE_OK;
+  if (!ss || !prS) return FSPARSE_E_ARG;
+  int dev = 0;
+  hipGetDevice(&dev);
+  if (dev != plan->device) return FSPARSE_E_PLAN;
+  if (flags & FSPARSE_ATOMIC) {
+    if (!plan->slot) return FSPARSE_E_PLAN;
+    return plan_reuse_atomic(plan, ss, prS, stream);
+  }
+  return plan_reuse_ordered(plan, ss, prS, stream);
+}
+
+fsparse_status fsparse_backward(const int32_t* slot, int64_t len,
+                                const void* grad_prS, int64_t nnz,
+                                fsparse_dtype dt, void* grad_ss,
+                                hipStream_t stream) {
+  if (check_dt(dt) != FSPARSE_OK || len < 0 || nnz < 0 || len > kMaxI32)
+    return FSPARSE_E_ARG;
+  if (len == 0) return FSPARSE_OK;
+  if (!slot || !grad_ss || (nnz > 0 && !grad_prS)) return FSPARSE_E_ARG;
+  if (nnz == 0) return FSPARSE_E_ARG;  // every slot must point somewhere
+  const int blk = tuning().rblock;
+  hipError_t e = launch(kBackward, stream, [&] {
+    if (dt == FSPARSE_F64)
+      hipLaunchKernelGGL(fsp::k_backward<double>, dim3(grid_for(len, blk, 16)),
+                         dim3(blk), 0, stream, slot, (const double*)grad_prS, len,
+                         (double*)grad_ss);
+    else
+      hipLaunchKernelGGL(fsp::k_backward<float>, dim3(grid_for(len, blk, 16)),
+                         dim3(blk), 0, stream, slot, (const float*)grad_prS, len,
+                         (float*)grad_ss);
+  });
+  return e == hipSuccess ? FSPARSE_OK : FSPARSE_E_HIP;
+}
+
+fsparse_status fsparse_assemble_batched(
+    int32_t nb, const int64_t* trip_off, const int32_t* ii, const int32_t* jj,
+    const void* ss, fsparse_dtype dt, const int64_t* m, const int64_t* n,
+    unsigned flags, int32_t* jcS, int64_t jcS_cap, int32_t* irS, void* prS,
+    int64_t cap, int64_t* nnz_off, int32_t* slot, void* ws, size_t ws_bytes,
+    fsparse_plan** plan, fsparse_info* info, hipStream_t stream) {
+  if (check_dt(dt) != FSPARSE_OK || nb < 1 || !trip_off || !m || !n || !nnz_off)
+    return FSPARSE_E_ARG;
+  if (flags & ~(unsigned)FSPARSE_ATOMIC) return FSPARSE_E_ARG;
+  if (trip_off[0] != 0) return FSPARSE_E_ARG;
+  for (int b = 0; b < nb; ++b)
+    if (trip_off[b + 1] < trip_off[b]) return FSPARSE_E_ARG;
+  const int64_t L = trip_off[nb];
+  if (L > kMaxI32) return FSPARSE_E_ARG;
+  if (L > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
+  if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS))) return FSPARSE_E_ARG;
+  if (plan) *plan = nullptr;
+  std::vector<int64_t> mm(m, m + nb), nn(n, n + nb), col(nb + 1, 0);
+  bool need_dims = false;
+  for (int b = 0; b < nb; ++b) {
+    if (mm[b] > kMaxI32 || nn[b] > kMaxI32) return FSPARSE_E_ARG;
+    need_dims |= (mm[b] < 0 || nn[b] < 0);
+  }
+  const Tuning tu = tuning();
+  // worst-case layout for the dims pass: tables must fit before N is known
+  if (ws_bytes < 4096) return FSPARSE_E_CAPACITY;
+  if (need_dims && L > 0) {
+    Layout pre = make_layout(0, 0, nb, esize_of(dt), tu.cap);
+    if (ws_bytes < pre.total) return FSPARSE_E_CAPACITY;
+    Ctrl* hi = static_cast<Ctrl*>(pinned());
+    if (!hi) return FSPARSE_E_HIP;
+    std::memset(hi, 0, sizeof(Ctrl));
+    hi->rmin = INT32_MAX;
+    hi->cmin = INT32_MAX;
+    HIPCHK(hipMemcpyAsync(ws, hi, sizeof(Ctrl), hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemsetAsync(at<char>(ws, pre.bmax), 0, 8 * (size_t)nb, stream));
+    HIPCHK(hipMemcpyAsync(at<int64_t>(ws, pre.b_trip), trip_off,
+                          8 * (size_t)(nb + 1), hipMemcpyHostToDevice, stream));
+    BatchDesc bd{at<int64_t>(ws, pre.b_trip), nullptr, nullptr, nullptr, nb};
+    hipError_t e = launch(kDims, stream, [&] {
+      hipLaunchKernelGGL(fsp::k_dims<true>, dim3(grid_for(L, 256, 8)), dim3(256),
+                         0, stream, ii, jj, L, bd, (Ctrl*)ws,
+                         at<int32_t>(ws, pre.bmax));
+    });
+    if (e != hipSuccess) return FSPARSE_E_HIP;
+    char* h = static_cast<char*>(pinned());
+    if (!h || sizeof(Ctrl) + 8 * (size_t)nb > kPinnedBytes) return FSPARSE_E_ARG;
+    HIPCHK(hipMemcpyAsync(h, ws, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(h + sizeof(Ctrl), at<char>(ws, pre.bmax), 8 * (size_t)nb,
+                          hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    const Ctrl* hc = reinterpret_cast<const Ctrl*>(h);
+    if (hc->rmin < 1 || hc->cmin < 1) return FSPARSE_E_INDEX;
+    const int32_t* bm = reinterpret_cast<const int32_t*>(h + sizeof(Ctrl));
+    for (int b = 0; b < nb; ++b) {
+      if (mm[b] < 0) mm[b] = bm[2 * b];
+      if (nn[b] < 0) nn[b] = bm[2 * b + 1];
+    }
+  }
+  for (int b = 0; b < nb; ++b) {
+    if (mm[b] < 0) mm[b] = 0;
+    if (nn[b] < 0) nn[b] = 0;
+    col[b + 1] = col[b] + nn[b];
+  }
+  const int64_t N = col[nb];
+  if (N > kMaxI32) return FSPARSE_E_ARG;
+  if (info)
+    for (int b = 0; b < nb; ++b) {
+      info[b].m = mm[b];
+      info[b].n = nn[b];
+      info[b].nnz = 0;
+      info[b].nzmax = 0;
+    }
+  if (jcS_cap < N + nb) return FSPARSE_E_CAPACITY;
+  const Layout lo = make_layout(L, N, nb, esize_of(dt), tu.cap);
+  if (ws_bytes < lo.total) return FSPARSE_E_CAPACITY;
+  std::vector<int32_t> m32(nb), n32(nb);
+  for (int b = 0; b < nb; ++b) {
+    m32[b] = (int32_t)mm[b];
+    n32[b] = (int32_t)nn[b];
+  }
+  HIPCHK(hipMemcpyAsync(at<int64_t>(ws, lo.b_trip), trip_off, 8 * (size_t)(nb + 1),
+                        hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(at<int64_t>(ws, lo.b_col), col.data(), 8 * (size_t)(nb + 1),
+                        hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(at<int32_t>(ws, lo.b_m), m32.data(), 4 * (size_t)nb,
+                        hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(at<int32_t>(ws, lo.b_n), n32.data(), 4 * (size_t)nb,
+                        hipMemcpyHostToDevice, stream));
+  BatchDesc bd{at<int64_t>(ws, lo.b_trip), at<int64_t>(ws, lo.b_col),
+               at<int32_t>(ws, lo.b_m), at<int32_t>(ws, lo.b_n), nb};
+  const bool keep = plan != nullptr;
+  int32_t* slot_used = slot ? slot : (keep ? at<int32_t>(ws, lo.islot) : nullptr);
+  int32_t* jcg = nb > 1 ? at<int32_t>(ws, lo.jcg) : jcS;
+  int64_t* dnnz = at<int64_t>(ws, lo.nnzoff);
+  Ctrl* ctrl = at<Ctrl>(ws, lo.ctrl);
+  hipError_t e;
+  if (L == 0) {
+    e = launch(kInit, stream, [&] {
+      hipLaunchKernelGGL(fsp::k_zero, dim3(grid_for(N + nb, 256, 4)), dim3(256), 0,
+                         stream, (uint32_t*)jcS, (int64_t)(N + nb));
+    });
+    if (e != hipSuccess) return FSPARSE_E_HIP;
+    HIPCHK(hipStreamSynchronize(stream));
+    for (int b = 0; b <= nb; ++b) nnz_off[b] = 0;
+    if (keep) {
+      fsparse_plan* pl = new (std::nothrow) fsparse_plan();
+      if (!pl) return FSPARSE_E_ARG;
+      pl->dt = dt;
+      hipGetDevice(&pl->device);
+      *plan = pl;
+    }
+    return FSPARSE_OK;
+  }
+  if (dt == FSPARSE_F64)
+    e = run_pipeline<double, true>(ii, jj, (const double*)ss, L, 0, 0, bd, N, lo, tu,
+                                   ws, jcg, irS, (double*)prS, cap, slot_used, keep,
+                                   stream);
+  else
+    e = run_pipeline<float, true>(ii, jj, (const float*)ss, L, 0, 0, bd, N, lo, tu,
+                                  ws, jcg, irS, (float*)prS, cap, slot_used, keep,
+                                  stream);
+  if (e != hipSuccess) return FSPARSE_E_HIP;
+  if (nb > 1) {
+    e = launch(kBatchedJcs, stream, [&] {
+      hipLaunchKernelGGL(fsp::k_batched_jcs, dim3(grid_for(N + nb, 256, 4)),
+                         dim3(256), 0, stream, jcg, at<int64_t>(ws, lo.b_col), nb,
+                         (int64_t)(N + nb), jcS, dnnz);
+    });
+    if (e != hipSuccess) return FSPARSE_E_HIP;
+  }
+  char* h = static_cast<char*>(pinned());
+  if (!h || sizeof(Ctrl) + 8 * (size_t)(nb + 1) > kPinnedBytes) return FSPARSE_E_ARG;
+  HIPCHK(hipMemcpyAsync(h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+  if (nb > 1)
+    HIPCHK(hipMemcpyAsync(h + sizeof(Ctrl), dnnz, 8 * (size_t)(nb + 1),
+                          hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  const Ctrl* hc = reinterpret_cast<const Ctrl*>(h);
+  const int64_t nnz = hc->nnz;
+  if (nb > 1) {
+    std::memcpy(nnz_off, h + sizeof(Ctrl), 8 * (size_t)(nb + 1));
+  } else {
+    nnz_off[0] = 0;
+    nnz_off[1] = nnz;
+  }
+  if (info)
+    for (int b = 0; b < nb; ++b) {
+      info[b].nnz = nnz_off[b + 1] - nnz_off[b];
+      info[b].nzmax = info[b].nnz;
+    }
+  if (hc->err & (fsp::kErrCol | fsp::kErrRow)) return FSPARSE_E_INDEX;
+  if (hc->err & fsp::kErrCap) return FSPARSE_E_CAPACITY;
+  if (flags & FSPARSE_ATOMIC) {
+    if (!slot_used) return FSPARSE_E_ARG;
+    hipError_t ea = dt == FSPARSE_F64
+        ? launch_atomic_values<double>(slot_used, ss, L, prS, nnz, tu.rblock, stream)
+        : launch_atomic_values<float>(slot_used, ss, L, prS, nnz, tu.rblock, stream);
+    if (ea != hipSuccess) return FSPARSE_E_HIP;
+  }
+  if (keep) {
+    fsparse_plan* pl = new (std::nothrow) fsparse_plan();
+    if (!pl) return FSPARSE_E_ARG;
+    pl->len = L;
+    pl->nnz = nnz;
+    pl->dt = dt;
+    hipGetDevice(&pl->device);
+    pl->perm = at<int32_t>(ws, lo.perm);
+    pl->seg = at<int32_t>(ws, lo.seg);
+    pl->slot = slot_used;
+    pl->rblock = tu.rblock;
+    *plan = pl;
+  }
+  return FSPARSE_OK;
+}
+
+void fsparse_plan_destroy(fsparse_plan* plan) {
+  if (!plan) return;
+  if (plan->x_ord) (void)hipGraphExecDestroy(plan->x_ord);
+  if (plan->g_ord) (void)hipGraphDestroy(plan->g_ord);
+  if (plan->x_at) (void)hipGraphExecDestroy(plan->x_at);
+  if (plan->g_at) (void)hipGraphDestroy(plan->g_at);
+  delete plan;
+}
+
+fsparse_status fsparse_plan_query(const fsparse_plan* plan, int64_t* len,
+                                  int64_t* nnz, int32_t* dtype) {
+  if (!plan) return FSPARSE_E_PLAN;
+  if (len) *len = plan->len;
+  if (nnz) *nnz = plan->nnz;
+  if (dtype) *dtype = (int32_t)plan->dt;
+  return FSPARSE_OK;
+}
+
+fsparse_status fsparse_set_tuning(const fsparse_tuning* t) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!t) {
+    g_tune = Tuning{};
+    return FSPARSE_OK;
+  }
+  Tuning n = g_tune;
+  if (t->chunk_cap) {
+    const int c = t->chunk_cap;
+    if (c < 2 || c > 4096 || (c & (c - 1))) return FSPARSE_E_ARG;
+    n.cap = c;
+  }
+  if (t->stream_block) {
+    const int b = t->stream_block;
+    if (b < 64 || b > 1024 || (b % 64)) return FSPARSE_E_ARG;
+    n.sblock = b;
+  }
+  if (t->stream_items) {
+    if (t->stream_items < 1 || t->stream_items > 32) return FSPARSE_E_ARG;
+    n.sitems = t->stream_items;
+  }
+  if (t->reuse_block) {
+    const int b = t->reuse_block;
+    if (b < 64 || b > 1024 || (b % 64)) return FSPARSE_E_ARG;
+    n.rblock = b;
+  }
+  g_tune = n;
+  return FSPARSE_OK;
+}
+
+fsparse_status fsparse_get_tuning(fsparse_tuning* t) {
+  if (!t) return FSPARSE_E_ARG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  t->chunk_cap = g_tune.cap;
+  t->stream_block = g_tune.sblock;
+  t->stream_items = g_tune.sitems;
+  t->reuse_block = g_tune.rblock;
+  return FSPARSE_OK;
+}
+
+fsparse_status fsparse_timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_timing = on != 0;
+  return FSPARSE_OK;
+}
+
+int fsparse_timing_read(double* ms, int64_t* launches, int max_stages) {
+  std::vector<Rec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    recs.swap(g_recs);
+  }
+  for (const Rec& r : recs) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess &&
+        hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_ms[r.stage] += t;
+      g_cnt[r.stage] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (int s = 0; s < kNumStages && s < max_stages; ++s) {
+    if (ms) ms[s] = g_ms[s];
+    if (launches) launches[s] = g_cnt[s];
+    g_ms[s] = 0;
+    g_cnt[s] = 0;
+  }
+  return kNumStages;
+}
+
+const char* fsparse_stage_name(int stage) {
+  return (stage >= 0 && stage < kNumStages) ? kStageNames[stage] : "";
+}
+
+fsparse_status fsparse_stream_copy(const void* src, void* dst, size_t bytes,
+                                   hipStream_t stream) {
+  if (!src || !dst || (bytes % 16) || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16))
+    return FSPARSE_E_ARG;
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return FSPARSE_OK;
+  hipError_t e = launch(kCopy, stream, [&] {
+    hipLaunchKernelGGL(fsp::k_copy16, dim3(grid_for(n16, 256, 16)), dim3(256), 0,
+                       stream, (const uint4*)src, (uint4*)dst, n16);
+  });
+  return e == hipSuccess ? FSPARSE_OK : FSPARSE_E_HIP;
+}
+
+}  // extern "C"

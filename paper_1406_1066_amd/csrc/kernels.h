@@ -1,0 +1,1024 @@
+// Device code of the gfx950 sparse-assembly pipeline.
+//
+// Fresh assembly of S = sparse(ii, jj, ss, m, n) (Section 2.1) runs as
+//   hist   column histogram of jj                (role of Part 1, Section 2.3.1,
+//                                                 but over columns)
+//   scan   single-pass decoupled look-back exclusive scan of the histogram
+//          -> triplet column pointers (collisions not yet removed, like the
+//          "pessimistic" row pointer of Part 1) and the chunk table
+//   bucket every triplet claims a slot in its column's bucket (device atomic
+//          on the column fill pointer) and stores (row, k, value) there
+//   chunk  one workgroup per window of the bucket array: in LDS it groups
+//          equal (column,row) pairs (hash), ranks the distinct rows of every
+//          column (rows increase within a column, as Part 3 guarantees),
+//          orders each pair's contributions by k and folds them from +0.0 in
+//          that order (the order of the serial post-processing); the chunk's
+//          output offset comes from a chained look-back over the chunks, in
+//          column order, which yields jcS (Part 4's running sum) as well.
+// The permutation of the contributions and the segment starts are kept for
+// pattern re-use; slot[k] is the paper's inverse rank irank (eqs. (2.2)-(2.3)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsp {
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagPrefix = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+
+// error bits in Ctrl::err
+constexpr uint32_t kErrCol = 1u;
+constexpr uint32_t kErrRow = 2u;
+constexpr uint32_t kErrCap = 4u;
+
+// Control block at the start of the workspace (zeroed before every call).
+struct Ctrl {
+  uint32_t err;
+  uint32_t tick_scan;
+  uint32_t tick_chunk;
+  uint32_t pad0;
+  int64_t nnz;
+  int64_t ltot;
+  int32_t rmin, rmax, cmin, cmax;  // dims pass
+  uint32_t pad1[20];
+};
+static_assert(sizeof(Ctrl) <= 256, "control block");
+
+// One triplet in its column bucket.  (row, k) then the value; 16 bytes for
+// fp64 (one dwordx4 access), 12 bytes for fp32.
+template <typename VT>
+struct Entry;
+template <>
+struct __attribute__((aligned(16))) Entry<double> {
+  uint32_t row, k;
+  double v;
+};
+template <>
+struct Entry<float> {
+  uint32_t row, k;
+  float v;
+};
+
+// Several matrices assembled by the same launches: matrix b owns triplets
+// [trip_off[b], trip_off[b+1]) and global columns [col_off[b], col_off[b+1]).
+struct BatchDesc {
+  const int64_t* trip_off;
+  const int64_t* col_off;
+  const int32_t* mdim;
+  const int32_t* ndim;
+  int32_t nb;
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t ld_acq(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_rel(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_sum(T x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x = x > y ? x : y;
+  }
+  return x;
+}
+
+// Exclusive block-wide sum of one value per thread.  All threads call it.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t* sWave,
+                                                   uint32_t& total) {
+  const int wid = threadIdx.x >> 6;
+  uint32_t x = wave_incl_sum(v);
+  if (lane_id() == 63) sWave[wid] = x;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    uint32_t t = sWave[w];
+    pre += (w < wid) ? t : 0u;
+    tot += t;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + x - v;
+}
+
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t* sWave) {
+  const int wid = threadIdx.x >> 6;
+  uint32_t x = wave_incl_max(v);
+  if (lane_id() == 63) sWave[wid] = x;
+  __syncthreads();
+  uint32_t pre = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    uint32_t t = sWave[w];
+    if (w < wid) pre = pre > t ? pre : t;
+  }
+  // exclusive max within the wave: value of the previous lane
+  uint32_t prev = __shfl_up(x, 1, 64);
+  if (lane_id() == 0) prev = 0;
+  __syncthreads();
+  return pre > prev ? pre : prev;
+}
+
+// In-place exclusive prefix sum of arr[0..S) in LDS; returns the total.
+// Each thread scans a contiguous run of the array.  All threads call it.
+template <int NT>
+__device__ uint32_t lds_excl_scan(uint32_t* arr, int S, uint32_t* sWave) {
+  const int ipt = (S + NT - 1) / NT;
+  const int lo = min(S, (int)threadIdx.x * ipt);
+  const int hi = min(S, lo + ipt);
+  uint32_t acc = 0;
+  for (int i = lo; i < hi; ++i) acc += arr[i];
+  uint32_t total;
+  uint32_t run = block_excl_sum<NT>(acc, sWave, total);
+  for (int i = lo; i < hi; ++i) {
+    uint32_t x = arr[i];
+    arr[i] = run;
+    run += x;
+  }
+  __syncthreads();
+  return total;
+}
+
+// In-place inclusive running maximum of arr[0..S) in LDS.
+template <int NT>
+__device__ void lds_incl_max(uint32_t* arr, int S, uint32_t* sWave) {
+  const int ipt = (S + NT - 1) / NT;
+  const int lo = min(S, (int)threadIdx.x * ipt);
+  const int hi = min(S, lo + ipt);
+  uint32_t acc = 0;
+  for (int i = lo; i < hi; ++i) acc = acc > arr[i] ? acc : arr[i];
+  uint32_t run = block_excl_max<NT>(acc, sWave);
+  for (int i = lo; i < hi; ++i) {
+    uint32_t x = arr[i];
+    run = run > x ? run : x;
+    arr[i] = run;
+  }
+  __syncthreads();
+}
+
+// Chained look-back over tiles in ticket order (Merrill & Garland's single
+// pass scan with decoupled look-back).  Called by the 64 lanes of one wave;
+// returns the exclusive prefix of tile q and publishes its inclusive prefix.
+__device__ int64_t lookback(uint64_t* status, int q, uint64_t agg) {
+  const int lane = lane_id();
+  if (q == 0) {
+    if (lane == 0) st_rel(&status[0], kFlagPrefix | agg);
+    return 0;
+  }
+  if (lane == 0) st_rel(&status[q], kFlagAgg | agg);
+  int64_t excl = 0;
+  int pred = q - 1;
+  for (;;) {
+    const int idx = pred - lane;
+    const uint64_t s = (idx >= 0) ? ld_acq(&status[idx]) : kFlagPrefix;
+    const uint32_t flag = (uint32_t)(s >> 62);
+    const uint64_t inval = __ballot(flag == 0);
+    const uint64_t pref = __ballot(flag == 2);
+    const int pl = pref ? (__ffsll((unsigned long long)pref) - 1) : 64;
+    const uint64_t need = (pl >= 63) ? ~0ull : ((2ull << pl) - 1ull);
+    if (inval & need) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    uint64_t v = (lane <= pl) ? (s & kValMask) : 0ull;
+    v = wave_incl_sum(v);
+    excl += (int64_t)__shfl(v, 63, 64);
+    if (pl < 64) break;
+    pred -= 64;
+  }
+  if (lane == 0) st_rel(&status[q], kFlagPrefix | (uint64_t)(excl + (int64_t)agg));
+  return excl;
+}
+
+__device__ __forceinline__ int find_mat(const int64_t* off, int nb, int64_t e) {
+  int lo = 0, hi = nb;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// zero fill, typed fill, copy
+// ---------------------------------------------------------------------------
+__global__ void k_zero(uint32_t* __restrict__ p, int64_t nwords) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < nwords; i += stride) p[i] = 0u;
+}
+
+__global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                         int64_t n16) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// dims: largest / smallest index (the pre-processing pass, Section 2.2)
+// ---------------------------------------------------------------------------
+template <bool BATCHED>
+__global__ void k_dims(const int32_t* __restrict__ ii,
+                       const int32_t* __restrict__ jj, int64_t L,
+                       BatchDesc bd, Ctrl* ctrl, int32_t* __restrict__ bmax) {
+  int32_t rmax = 0, cmax = 0, rmin = INT32_MAX, cmin = INT32_MAX;
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; e < L; e += stride) {
+    const int32_t r = ii[e], c = jj[e];
+    rmin = min(rmin, r);
+    cmin = min(cmin, c);
+    if (BATCHED) {
+      const int b = find_mat(bd.trip_off, bd.nb, e);
+      atomicMax(&bmax[2 * b], r);
+      atomicMax(&bmax[2 * b + 1], c);
+    } else {
+      rmax = max(rmax, r);
+      cmax = max(cmax, c);
+    }
+  }
+  // wave reductions then one atomic per wave
+  for (int d = 32; d > 0; d >>= 1) {
+    rmax = max(rmax, __shfl_xor(rmax, d, 64));
+    cmax = max(cmax, __shfl_xor(cmax, d, 64));
+    rmin = min(rmin, __shfl_xor(rmin, d, 64));
+    cmin = min(cmin, __shfl_xor(cmin, d, 64));
+  }
+  if (lane_id() == 0) {
+    atomicMax(&ctrl->rmax, rmax);
+    atomicMax(&ctrl->cmax, cmax);
+    atomicMin(&ctrl->rmin, rmin);
+    atomicMin(&ctrl->cmin, cmin);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// hist: triplets per column; out-of-range columns are flagged and skipped
+// ---------------------------------------------------------------------------
+template <bool BATCHED>
+__global__ void k_hist(const int32_t* __restrict__ jj, int64_t L, int32_t n,
+                       BatchDesc bd, int32_t* __restrict__ cnt, Ctrl* ctrl,
+                       int items) {
+  const int64_t tile = (int64_t)blockDim.x * items;
+  const int64_t t0 = (int64_t)blockIdx.x * tile;
+  __shared__ int sB;
+  int b = 0;
+  if (BATCHED) {
+    if (threadIdx.x == 0) sB = find_mat(bd.trip_off, bd.nb, min(t0, L - 1));
+    __syncthreads();
+    b = sB;
+  }
+  bool bad = false;
+  for (int j = 0; j < items; ++j) {
+    const int64_t e = t0 + (int64_t)j * blockDim.x + threadIdx.x;
+    if (e >= L) break;
+    const int32_t c = jj[e] - 1;
+    if (BATCHED) {
+      while (bd.trip_off[b + 1] <= e) ++b;
+      if ((uint32_t)c >= (uint32_t)bd.ndim[b]) { bad = true; continue; }
+      atomicAdd(&cnt[bd.col_off[b] + c], 1);
+    } else {
+      if ((uint32_t)c >= (uint32_t)n) { bad = true; continue; }
+      atomicAdd(&cnt[c], 1);
+    }
+  }
+  if (bad) atomicOr(&ctrl->err, kErrCol);
+}
+
+// ---------------------------------------------------------------------------
+// scan: colptr = exclusive prefix of cnt[0..N] (cnt[N] = 0), fill = colptr,
+// chunk_col[q] = first column whose colptr is >= q*T (q = 0..Q)
+// ---------------------------------------------------------------------------
+template <int NT, int IPT>
+__global__ void __launch_bounds__(NT)
+k_scan(const int32_t* __restrict__ cnt, int32_t N, int32_t* __restrict__ colptr,
+       int32_t* __restrict__ fill, int32_t* __restrict__ chunk_col, int32_t T,
+       int32_t Q, uint64_t* status, Ctrl* ctrl) {
+  __shared__ uint32_t sWave[NT / 64];
+  __shared__ int sTile;
+  __shared__ int64_t sBase;
+  if (threadIdx.x == 0) sTile = (int)atomicAdd(&ctrl->tick_scan, 1u);
+  __syncthreads();
+  const int tile = sTile;
+  const int N1 = N + 1;
+  const int64_t i0 = (int64_t)tile * NT * IPT + (int64_t)threadIdx.x * IPT;
+  int32_t v[IPT];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const int64_t i = i0 + j;
+    v[j] = (i < N) ? cnt[i] : 0;
+    sum += (uint32_t)v[j];
+  }
+  uint32_t total;
+  const uint32_t pre = block_excl_sum<NT>(sum, sWave, total);
+  if (threadIdx.x < 64) {
+    int64_t ex = lookback(status, tile, total);
+    if (threadIdx.x == 0) sBase = ex;
+  }
+  __syncthreads();
+  int64_t run = sBase + pre;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const int64_t i = i0 + j;
+    if (i < N1) {
+      colptr[i] = (int32_t)run;
+      if (i < N) {
+        fill[i] = (int32_t)run;
+        // windows q with q*T in (colptr[i], colptr[i+1]] start at column i+1
+        const int64_t nx = run + v[j];
+        for (int64_t q = run / T + 1; q <= nx / T; ++q) chunk_col[q] = (int32_t)(i + 1);
+      } else {
+        // i == N: total number of bucketed triplets; later windows are empty
+        ctrl->ltot = run;
+        for (int64_t q = run / T + 1; q <= Q; ++q) chunk_col[q] = N + 1;
+      }
+      if (i == 0) chunk_col[0] = 0;
+    }
+    run += v[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// bucket: scatter (row, k, value) into the column buckets
+// ---------------------------------------------------------------------------
+template <typename VT>
+__device__ __forceinline__ void store_entry(Entry<VT>* p, uint32_t row,
+                                            uint32_t k, VT v);
+template <>
+__device__ __forceinline__ void store_entry<double>(Entry<double>* p,
+                                                    uint32_t row, uint32_t k,
+                                                    double v) {
+  uint4 x;
+  x.x = row;
+  x.y = k;
+  const uint64_t b = __double_as_longlong(v);
+  x.z = (uint32_t)b;
+  x.w = (uint32_t)(b >> 32);
+  *reinterpret_cast<uint4*>(p) = x;
+}
+template <>
+__device__ __forceinline__ void store_entry<float>(Entry<float>* p, uint32_t row,
+                                                   uint32_t k, float v) {
+  p->row = row;
+  p->k = k;
+  p->v = v;
+}
+
+template <typename VT>
+__device__ __forceinline__ Entry<VT> load_entry(const Entry<VT>* p);
+template <>
+__device__ __forceinline__ Entry<double> load_entry<double>(const Entry<double>* p) {
+  const uint4 x = *reinterpret_cast<const uint4*>(p);
+  Entry<double> e;
+  e.row = x.x;
+  e.k = x.y;
+  e.v = __longlong_as_double(((int64_t)x.w << 32) | (int64_t)x.z);
+  return e;
+}
+template <>
+__device__ __forceinline__ Entry<float> load_entry<float>(const Entry<float>* p) {
+  return *p;
+}
+
+template <typename VT, bool BATCHED>
+__global__ void k_bucket(const int32_t* __restrict__ ii,
+                         const int32_t* __restrict__ jj,
+                         const VT* __restrict__ ss, int64_t L, int32_t m,
+                         int32_t n, BatchDesc bd, int32_t* __restrict__ fill,
+                         Entry<VT>* __restrict__ bucket, Ctrl* ctrl, int items) {
+  const int64_t tile = (int64_t)blockDim.x * items;
+  const int64_t t0 = (int64_t)blockIdx.x * tile;
+  __shared__ int sB;
+  int b = 0;
+  if (BATCHED) {
+    if (threadIdx.x == 0) sB = find_mat(bd.trip_off, bd.nb, min(t0, L - 1));
+    __syncthreads();
+    b = sB;
+  }
+  bool badr = false;
+  for (int j = 0; j < items; ++j) {
+    const int64_t e = t0 + (int64_t)j * blockDim.x + threadIdx.x;
+    if (e >= L) break;
+    const int32_t c = jj[e] - 1;
+    const int32_t r = ii[e] - 1;
+    int64_t g;
+    int32_t mb;
+    if (BATCHED) {
+      while (bd.trip_off[b + 1] <= e) ++b;
+      if ((uint32_t)c >= (uint32_t)bd.ndim[b]) continue;  // flagged by hist
+      g = bd.col_off[b] + c;
+      mb = bd.mdim[b];
+    } else {
+      if ((uint32_t)c >= (uint32_t)n) continue;
+      g = c;
+      mb = m;
+    }
+    badr |= (uint32_t)r >= (uint32_t)mb;
+    const int32_t p = atomicAdd(&fill[g], 1);
+    store_entry<VT>(&bucket[p], (uint32_t)r, (uint32_t)e, ss[e]);
+  }
+  if (badr) atomicOr(&ctrl->err, kErrRow);
+}
+
+// ---------------------------------------------------------------------------
+// chunk: sort/group/fold one window of the bucket array in LDS
+// ---------------------------------------------------------------------------
+template <typename VT>
+struct ChunkArgs {
+  const int32_t* colptr;     // [N+1] triplet column pointers
+  const int32_t* chunk_col;  // [Q+1]
+  Entry<VT>* bucket;         // [Ltot] (overwritten only on the long path)
+  Entry<VT>* tmp;            // [Ltot] scratch of the long path
+  int32_t N;                 // columns (all matrices)
+  int32_t T;                 // window length (triplets)
+  int32_t cap;               // LDS capacity in use (power of two <= CAP)
+  int32_t Q;                 // number of windows
+  uint64_t* status;          // [Q] look-back words
+  Ctrl* ctrl;
+  int32_t* jcS;              // [N+1] column pointers, global numbering
+  int32_t* irS;              // [out_cap]
+  VT* prS;                   // [out_cap]
+  int64_t out_cap;
+  int32_t* slot;             // [Ltot] or null
+  int32_t* perm;             // [Ltot] or null: k of the p-th sorted triplet
+  int32_t* seg;              // [nnz+1] or null: first sorted position of slot
+};
+
+__device__ __forceinline__ uint32_t pair_hash(uint32_t cs, uint32_t row) {
+  uint32_t h = cs * 0x9E3779B1u ^ (row + 0x7F4A7C15u) * 0x85EBCA77u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  return h;
+}
+
+// LDS carve-up for capacity CAP (bytes):
+//   [0, 8CAP)          hash table u32[2CAP] | dlist u32[CAP] + gout u32[CAP]
+//                      | placed values VT[CAP] | long path keys u64[CAP]
+//   [8CAP, 12CAP)      rows u32[CAP]  | placed k u32[CAP]
+//   [12CAP, 16CAP)     column start (+1) per entry | group of placed entry
+//                      ([8CAP,16CAP) = long path values VT[CAP])
+//   [16CAP, 20CAP)     column end by column start
+//   [20CAP, 24CAP)     group counts by representative | sorted index
+//   [24CAP, 28CAP)     group row by output index
+//   [28CAP, 32CAP+4)   distinct per column start -> exclusive scan
+//   [32CAP+4, 36CAP+8) group sizes by output index -> exclusive scan
+//   tail               wave totals, misc
+template <int CAP>
+struct Lds {
+  static constexpr int kBytes = 36 * CAP + 8 + 64 * 4 + 8 * 8 + 16;
+};
+
+template <typename VT, int CAP, int NT>
+struct ChunkCtx {
+  unsigned char* smem;
+  __device__ uint32_t* ht() const { return reinterpret_cast<uint32_t*>(smem); }
+  __device__ uint32_t* dlist() const { return ht(); }
+  __device__ uint32_t* gout() const { return ht() + CAP; }
+  __device__ VT* mval() const { return reinterpret_cast<VT*>(smem); }
+  __device__ uint64_t* lkey() const { return reinterpret_cast<uint64_t*>(smem); }
+  __device__ VT* lval() const { return reinterpret_cast<VT*>(smem + 8 * CAP); }
+  __device__ uint32_t* row() const { return reinterpret_cast<uint32_t*>(smem + 8 * CAP); }
+  __device__ uint32_t* cs() const { return reinterpret_cast<uint32_t*>(smem + 12 * CAP); }
+  __device__ uint32_t* cend() const { return reinterpret_cast<uint32_t*>(smem + 16 * CAP); }
+  __device__ uint32_t* cnt() const { return reinterpret_cast<uint32_t*>(smem + 20 * CAP); }
+  __device__ uint32_t* grow() const { return reinterpret_cast<uint32_t*>(smem + 24 * CAP); }
+  __device__ uint32_t* cd() const { return reinterpret_cast<uint32_t*>(smem + 28 * CAP); }
+  __device__ uint32_t* gs() const { return reinterpret_cast<uint32_t*>(smem + 32 * CAP + 4); }
+  __device__ uint32_t* wave() const { return reinterpret_cast<uint32_t*>(smem + 36 * CAP + 8); }
+  __device__ int64_t* misc() const {
+    return reinterpret_cast<int64_t*>(smem + 36 * CAP + 8 + 64 * 4 + 8);
+  }
+};
+
+// Columns [cb, ce) whose triplets are bucket[e0, e1), e1 - e0 <= cap.
+// Groups, ranks and folds them.  The output offset of the batch is obtained
+// by `base_of(D)` (look-back, or a given offset) once the distinct count D is
+// known; with EMIT false only D is computed.  Returns D.
+template <typename VT, int CAP, int NT, bool EMIT, typename BaseFn>
+__device__ uint32_t batch(const ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x,
+                          int cb, int ce, int e0, int e1, BaseFn base_of) {
+  constexpr int EPT = CAP / NT;
+  constexpr int H = 2 * CAP;
+  const int tid = threadIdx.x;
+  const int span = e1 - e0;
+  uint32_t* ht = x.ht();
+  uint32_t* row = x.row();
+  uint32_t* cs = x.cs();
+  uint32_t* cend = x.cend();
+  uint32_t* cnt = x.cnt();
+  uint32_t* cd = x.cd();
+
+  // P1: clear, load, mark column starts
+  for (int i = tid; i < H; i += NT) ht[i] = kEmpty;
+  for (int i = tid; i < span; i += NT) {
+    cs[i] = 0;
+    cnt[i] = 0;
+    cd[i] = 0;
+  }
+  if (tid == 0) cd[span] = 0;
+  uint32_t kr[EPT];
+  VT vr[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = tid + j * NT;
+    if (i < span) {
+      const Entry<VT> en = load_entry<VT>(&a.bucket[e0 + i]);
+      row[i] = en.row;
+      kr[j] = en.k;
+      vr[j] = en.v;
+    }
+  }
+  __syncthreads();
+  for (int c = cb + tid; c < ce; c += NT) {
+    const int s = a.colptr[c] - e0, t = a.colptr[c + 1] - e0;
+    if (t > s) {
+      cs[s] = (uint32_t)s + 1u;
+      cend[s] = (uint32_t)t;
+    }
+  }
+  __syncthreads();
+  lds_incl_max<NT>(cs, span, x.wave());
+
+  // P2: group equal (column, row) pairs with a hash table of entry indices
+  uint32_t repa[EPT], dpos[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = tid + j * NT;
+    if (i < span) {
+      const uint32_t c0 = cs[i], r0 = row[i];
+      uint32_t h = pair_hash(c0, r0) & (H - 1);
+      uint32_t rep;
+      for (;;) {
+        const uint32_t old = atomicCAS(&ht[h], kEmpty, (uint32_t)i);
+        if (old == kEmpty) { rep = (uint32_t)i; break; }
+        if (cs[old] == c0 && row[old] == r0) { rep = old; break; }
+        h = (h + 1) & (H - 1);
+      }
+      const uint32_t arr = atomicAdd(&cnt[rep], 1u);
+      repa[j] = rep | (arr << 16);
+      dpos[j] = (rep == (uint32_t)i) ? atomicAdd(&cd[c0 - 1], 1u) : kEmpty;
+    }
+  }
+  __syncthreads();
+
+  // P3: distinct pairs before each position; the batch's output offset
+  const uint32_t D = lds_excl_scan<NT>(cd, span + 1, x.wave());
+  if (EMIT) {
+    if (tid < 64) {
+      const int64_t b = base_of(D);
+      if (tid == 0) x.misc()[1] = b;
+    }
+  } else {
+    return D;
+  }
+  uint32_t* dlist = x.dlist();
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = tid + j * NT;
+    if (i < span && dpos[j] != kEmpty) dlist[cd[cs[i] - 1] + dpos[j]] = (uint32_t)i;
+  }
+  __syncthreads();
+
+  // P4: rank the distinct rows of every column
+  uint32_t* gout = x.gout();
+  uint32_t* gs = x.gs();
+  uint32_t* grow = x.grow();
+  for (int d = tid; d < (int)D; d += NT) {
+    const uint32_t i = dlist[d];
+    const uint32_t c0 = cs[i] - 1;
+    const uint32_t r0 = row[i];
+    const uint32_t lo = cd[c0], hi = cd[cend[c0]];
+    uint32_t rk = 0;
+    for (uint32_t t = lo; t < hi; ++t) rk += row[dlist[t]] < r0 ? 1u : 0u;
+    const uint32_t o = lo + rk;
+    gout[i] = o;
+    gs[o] = cnt[i];
+    grow[o] = r0;
+  }
+  if (tid == 0) gs[D] = 0;
+  __syncthreads();
+
+  // P5: start of every group in the sorted order
+  lds_excl_scan<NT>(gs, (int)D + 1, x.wave());
+
+  // P6: place every triplet into its group (arrival order for now)
+  uint32_t posr[EPT], orr[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = tid + j * NT;
+    if (i < span) {
+      const uint32_t o = gout[repa[j] & 0xFFFFu];
+      orr[j] = o;
+      posr[j] = gs[o] + (repa[j] >> 16);
+    }
+  }
+  __syncthreads();
+  VT* mval = x.mval();
+  uint32_t* mk = row;   // k of placed triplets
+  uint32_t* mgrp = cs;  // group of placed triplets
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = tid + j * NT;
+    if (i < span) {
+      mk[posr[j]] = kr[j];
+      mval[posr[j]] = vr[j];
+      mgrp[posr[j]] = orr[j];
+    }
+  }
+  __syncthreads();
+
+  // P7: order each group's triplets by k (rank by counting)
+  uint32_t* sidx = cnt;
+  for (int p = tid; p < span; p += NT) {
+    const uint32_t o = mgrp[p];
+    const uint32_t g0 = gs[o], g1 = gs[o + 1];
+    const uint32_t kk = mk[p];
+    uint32_t rk = 0;
+    for (uint32_t t = g0; t < g1; ++t) rk += mk[t] < kk ? 1u : 0u;
+    sidx[g0 + rk] = (uint32_t)p;
+  }
+  __syncthreads();
+
+  // P8: emit
+  const int64_t base = x.misc()[1];
+  if (a.perm)
+    for (int p = tid; p < span; p += NT) a.perm[e0 + p] = (int32_t)mk[sidx[p]];
+  if (a.slot)
+    for (int p = tid; p < span; p += NT) {
+      const uint32_t q = sidx[p];
+      a.slot[mk[q]] = (int32_t)(base + mgrp[q]);
+    }
+  bool over = false;
+  for (int o = tid; o < (int)D; o += NT) {
+    const uint32_t g0 = gs[o], g1 = gs[o + 1];
+    VT acc = (VT)0;
+    for (uint32_t t = g0; t < g1; ++t) acc = acc + mval[sidx[t]];
+    const int64_t out = base + o;
+    if (out < a.out_cap) {
+      a.irS[out] = (int32_t)grow[o];
+      a.prS[out] = acc;
+    } else {
+      over = true;
+    }
+    if (a.seg) a.seg[out] = e0 + (int32_t)g0;
+  }
+  if (over) atomicOr(&a.ctrl->err, kErrCap);
+  for (int c = cb + tid; c < ce; c += NT)
+    a.jcS[c] = (int32_t)(base + cd[a.colptr[c] - e0]);
+  __syncthreads();
+  return D;
+}
+
+// ---- long path: one column with more triplets than the LDS holds --------
+__device__ __forceinline__ uint64_t ekey(uint32_t row, uint32_t k) {
+  return ((uint64_t)row << 32) | (uint64_t)k;
+}
+
+// Sorts bucket[a0, a0+len) by (row, k) with a bitonic sort of LDS tiles
+// followed by merge passes between `bucket` and `tmp`; returns which array
+// holds the result (0 = bucket, 1 = tmp).
+template <typename VT, int CAP, int NT>
+__device__ int long_sort(const ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x,
+                         int a0, int len) {
+  const int tid = threadIdx.x;
+  const int TS = a.cap;
+  uint64_t* key = x.lkey();
+  VT* val = x.lval();
+  for (int t0 = 0; t0 < len; t0 += TS) {
+    const int tl = min(TS, len - t0);
+    int P = 1;
+    while (P < tl) P <<= 1;
+    for (int i = tid; i < P; i += NT) {
+      if (i < tl) {
+        const Entry<VT> en = load_entry<VT>(&a.bucket[a0 + t0 + i]);
+        key[i] = ekey(en.row, en.k);
+        val[i] = en.v;
+      } else {
+        key[i] = ~0ull;
+        val[i] = (VT)0;
+      }
+    }
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = tid; i < P / 2; i += NT) {
+          const int lo = 2 * i - (i & (j - 1));
+          const int hi = lo + j;
+          const bool up = (lo & k) == 0;
+          const uint64_t kl = key[lo], kh = key[hi];
+          if ((kl > kh) == up) {
+            key[lo] = kh;
+            key[hi] = kl;
+            const VT t = val[lo];
+            val[lo] = val[hi];
+            val[hi] = t;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = tid; i < tl; i += NT)
+      store_entry<VT>(&a.tmp[a0 + t0 + i], (uint32_t)(key[i] >> 32),
+                      (uint32_t)key[i], val[i]);
+    __syncthreads();
+  }
+  __threadfence();
+  __syncthreads();
+  Entry<VT>* src = a.tmp;
+  Entry<VT>* dst = a.bucket;
+  int where = 1;
+  for (int w = TS; w < len; w <<= 1) {
+    for (int idx = tid; idx < len; idx += NT) {
+      const int r = idx / w;
+      const int ps = (r & ~1) * w;  // start of the pair of runs
+      const int i = idx - r * w;
+      const Entry<VT> en = load_entry<VT>(&src[a0 + idx]);
+      const uint64_t kk = ekey(en.row, en.k);
+      int os, ol;  // other run
+      if ((r & 1) == 0) {
+        os = (r + 1) * w;
+        ol = max(0, min(w, len - os));
+      } else {
+        os = (r - 1) * w;
+        ol = w;
+      }
+      int lo = 0, hi = ol;  // count of other-run keys below kk
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const Entry<VT> om = load_entry<VT>(&src[a0 + os + mid]);
+        if (ekey(om.row, om.k) < kk) lo = mid + 1; else hi = mid;
+      }
+      store_entry<VT>(&dst[a0 + ps + i + lo], en.row, en.k, en.v);
+    }
+    __threadfence();
+    __syncthreads();
+    Entry<VT>* t = src;
+    src = dst;
+    dst = t;
+    where ^= 1;
+  }
+  return where;
+}
+
+// Distinct rows of a sorted long column.
+template <typename VT, int NT>
+__device__ uint32_t long_count(const Entry<VT>* s, int a0, int len,
+                               uint32_t* sWave) {
+  uint32_t c = 0;
+  for (int p = threadIdx.x; p < len; p += NT) {
+    const uint32_t r = s[a0 + p].row;
+    c += (p == 0 || s[a0 + p - 1].row != r) ? 1u : 0u;
+  }
+  uint32_t total;
+  block_excl_sum<NT>(c, sWave, total);
+  return total;
+}
+
+// Emits a sorted long column whose first output slot is `base`.
+template <typename VT, int CAP, int NT>
+__device__ void long_emit(const ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x,
+                          const Entry<VT>* s, int a0, int len, int64_t base) {
+  const int tid = threadIdx.x;
+  bool over = false;
+  int64_t run = 0;  // heads before the current tile
+  for (int t0 = 0; t0 < len; t0 += NT) {
+    const int p = t0 + tid;
+    uint32_t head = 0;
+    uint32_t r = 0;
+    if (p < len) {
+      r = s[a0 + p].row;
+      head = (p == 0 || s[a0 + p - 1].row != r) ? 1u : 0u;
+    }
+    uint32_t total;
+    const uint32_t pre = block_excl_sum<NT>(head, x.wave(), total);
+    if (p < len) {
+      const int64_t g = run + pre + head - 1;  // group of position p
+      const int64_t out = base + g;
+      const Entry<VT> en = s[a0 + p];
+      if (a.perm) a.perm[a0 + p] = (int32_t)en.k;
+      if (a.slot) a.slot[en.k] = (int32_t)out;
+      if (head) {
+        VT acc = (VT)0;
+        int t = p;
+        do {
+          acc = acc + s[a0 + t].v;
+          ++t;
+        } while (t < len && s[a0 + t].row == r);
+        if (out < a.out_cap) {
+          a.irS[out] = (int32_t)r;
+          a.prS[out] = acc;
+        } else {
+          over = true;
+        }
+        if (a.seg) a.seg[out] = a0 + p;
+      }
+    }
+    run += total;
+  }
+  if (over) atomicOr(&a.ctrl->err, kErrCap);
+  __syncthreads();
+}
+
+// Columns [cb, cl) whose triplets do not fit the LDS at once: they are taken
+// in batches of consecutive columns that fit, and columns longer than the
+// capacity take the long path.  Two sweeps: count, look-back, emit.
+template <typename VT, int CAP, int NT>
+__device__ int64_t chunk_slow(const ChunkArgs<VT>& a,
+                              const ChunkCtx<VT, CAP, NT>& x, int q, int cb,
+                              int cl) {
+  int64_t* misc = x.misc();
+  int64_t base = 0;
+  for (int sweep = 0; sweep < 2; ++sweep) {
+    int64_t off = base;
+    int c = cb;
+    while (c < cl) {
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        // largest ce in (c, cl] with colptr[ce] - colptr[c] <= cap
+        const int64_t lim = (int64_t)a.colptr[c] + a.cap;
+        int lo = c, hi = cl;  // colptr[lo] - colptr[c] <= cap
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (a.colptr[mid] <= lim) lo = mid; else hi = mid - 1;
+        }
+        misc[2] = (lo == c) ? c + 1 : lo;
+        misc[3] = (lo == c) ? 1 : 0;
+      }
+      __syncthreads();
+      const int ce = (int)misc[2];
+      const bool is_long = misc[3] != 0;
+      const int e0 = a.colptr[c], e1 = a.colptr[ce];
+      uint32_t D;
+      if (is_long) {
+        int where;
+        if (sweep == 0) {
+          where = long_sort<VT, CAP, NT>(a, x, e0, e1 - e0);
+        } else {
+          // same pass count as in the first sweep
+          where = 1;
+          for (int w = a.cap; w < e1 - e0; w <<= 1) where ^= 1;
+        }
+        const Entry<VT>* s = where ? a.tmp : a.bucket;
+        D = long_count<VT, NT>(s, e0, e1 - e0, x.wave());
+        if (sweep == 1) {
+          if (threadIdx.x == 0) a.jcS[c] = (int32_t)off;
+          long_emit<VT, CAP, NT>(a, x, s, e0, e1 - e0, off);
+        }
+      } else if (sweep == 0) {
+        D = batch<VT, CAP, NT, false>(a, x, c, ce, e0, e1,
+                                      [](uint32_t) -> int64_t { return 0; });
+        __syncthreads();
+      } else {
+        const int64_t o = off;
+        D = batch<VT, CAP, NT, true>(a, x, c, ce, e0, e1,
+                                     [o](uint32_t) -> int64_t { return o; });
+      }
+      off += D;
+      c = ce;
+    }
+    __syncthreads();
+    if (sweep == 0) {
+      if (threadIdx.x < 64) {
+        const int64_t b = lookback(a.status, q, (uint64_t)(off - base));
+        if (threadIdx.x == 0) misc[4] = b;
+      }
+      __syncthreads();
+      base = misc[4];
+    } else {
+      return off;  // base + distinct count of the chunk
+    }
+  }
+  return base;
+}
+
+template <typename VT, int CAP, int NT>
+__global__ void __launch_bounds__(NT) k_chunk(ChunkArgs<VT> a) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<CAP>::kBytes];
+  ChunkCtx<VT, CAP, NT> x{smem};
+  int64_t* misc = x.misc();
+  if (threadIdx.x == 0) misc[0] = (int64_t)atomicAdd(&a.ctrl->tick_chunk, 1u);
+  __syncthreads();
+  const int q = (int)misc[0];
+  const int N = a.N;
+  const int cbeg = a.chunk_col[q];
+  const int cend = a.chunk_col[q + 1];
+  const int cl = min(cend, N);
+  const bool owns_term = (cbeg <= N) && (N < cend);
+  int e0, e1;
+  if (cbeg >= N) {
+    e0 = e1 = a.colptr[N];
+  } else {
+    e0 = a.colptr[cbeg];
+    e1 = a.colptr[cl];
+  }
+  int64_t end;
+  if (e1 - e0 <= a.cap) {
+    uint64_t* status = a.status;
+    const uint32_t D = batch<VT, CAP, NT, true>(
+        a, x, cbeg < cl ? cbeg : cl, cl, e0, e1,
+        [status, q](uint32_t d) -> int64_t { return lookback(status, q, d); });
+    end = misc[1] + D;
+  } else {
+    end = chunk_slow<VT, CAP, NT>(a, x, q, cbeg, cl);
+  }
+  if (owns_term && threadIdx.x == 0) {
+    a.jcS[N] = (int32_t)end;
+    a.ctrl->nnz = end;
+    if (a.seg) a.seg[end] = e1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batched: per-matrix column pointers from the global ones
+// ---------------------------------------------------------------------------
+__global__ void k_batched_jcs(const int32_t* __restrict__ jcg,
+                              const int64_t* __restrict__ col_off, int32_t nb,
+                              int64_t total, int32_t* __restrict__ jcS,
+                              int64_t* __restrict__ nnz_off) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (idx <= nb) nnz_off[idx] = jcg[col_off[idx]];
+  for (; idx < total; idx += stride) {
+    // matrix b owns positions [col_off[b] + b, col_off[b+1] + b + 1)
+    int lo = 0, hi = nb;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (col_off[mid] + mid <= idx) lo = mid; else hi = mid;
+    }
+    const int64_t c = idx - (col_off[lo] + lo);
+    jcS[idx] = jcg[col_off[lo] + c] - jcg[col_off[lo]];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// re-assembly, atomic accumulation, backward
+// ---------------------------------------------------------------------------
+template <typename VT>
+__global__ void k_reuse(const int32_t* __restrict__ perm,
+                        const int32_t* __restrict__ seg,
+                        const VT* __restrict__ ss, int64_t nnz,
+                        VT* __restrict__ prS) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; j < nnz; j += stride) {
+    const int32_t b = seg[j], e = seg[j + 1];
+    VT acc = (VT)0;
+    for (int32_t p = b; p < e; ++p) acc = acc + ss[perm[p]];
+    prS[j] = acc;
+  }
+}
+
+template <typename VT>
+__global__ void k_fill(VT* __restrict__ p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = (VT)0;
+}
+
+template <typename VT>
+__global__ void k_atomic(const int32_t* __restrict__ slot,
+                         const VT* __restrict__ ss, int64_t L,
+                         VT* __restrict__ prS) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; k < L; k += stride) unsafeAtomicAdd(&prS[slot[k]], ss[k]);
+}
+
+template <typename VT>
+__global__ void k_backward(const int32_t* __restrict__ slot,
+                           const VT* __restrict__ g, int64_t L,
+                           VT* __restrict__ gs) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; k < L; k += stride) gs[k] = g[slot[k]];
+}
+
+}  // namespace fsp

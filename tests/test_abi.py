@@ -1,0 +1,80 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+and its host-only entry points (no GPU needed) behave as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fsparse.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fsparse_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1406_1066_amd import _lib
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(_lib.lib, name), name
+    assert set(_lib.EXPORTS) == set(names)
+
+
+def test_version_and_status_strings():
+    from paper_1406_1066_amd import _lib as L
+    assert b"gfx950" in L.fsparse_version()
+    assert L.fsparse_status_string(L.OK) == b"ok"
+    assert L.fsparse_status_string(L.E_INDEX) == b"index out of range"
+    assert L.fsparse_status_string(99) == b"unknown status"
+
+
+def test_workspace_bytes_host_only():
+    from paper_1406_1066_amd import _lib as L
+    a = L.fsparse_workspace_bytes(1000, 100, 1, L.F64)
+    b = L.fsparse_workspace_bytes(2000, 100, 1, L.F64)
+    c = L.fsparse_workspace_bytes(1000, 100, 1, L.F32)
+    assert 0 < a < b and c < a
+    assert L.fsparse_workspace_bytes(-1, 10, 1, L.F64) == 0
+    assert L.fsparse_workspace_bytes(10, 10, 0, L.F64) == 0
+    assert L.fsparse_workspace_bytes(10, 10, 1, 7) == 0
+    # bucket (16 B/triplet fp64) + long-path scratch + perm/seg/slot
+    assert a >= 1000 * (16 + 16 + 4 + 4 + 4)
+
+
+def test_tuning_validation():
+    from paper_1406_1066_amd import _lib as L
+    import paper_1406_1066_amd as fs
+    fs.set_tuning(reset=True)
+    d = fs.get_tuning()
+    assert d == {"chunk_cap": 2048, "stream_block": 256, "stream_items": 8,
+                 "reuse_block": 256}
+    fs.set_tuning(chunk_cap=64)
+    assert fs.get_tuning()["chunk_cap"] == 64
+    with pytest.raises(fs.FsparseError):
+        fs.set_tuning(chunk_cap=3000)
+    with pytest.raises(fs.FsparseError):
+        fs.set_tuning(stream_block=100)
+    fs.set_tuning(reset=True)
+    assert fs.get_tuning() == d
+
+
+def test_argument_errors_without_gpu():
+    from paper_1406_1066_amd import _lib as L
+    info = L.FsparseInfo()
+    # NULL jcS / workspace are rejected before any device work
+    st = L.fsparse_assemble(None, None, None, L.F64, 0, 3, 3, 0, 0, None, 4,
+                            None, None, 0, None, None, 0, None,
+                            ctypes.byref(info), None)
+    assert st == L.E_ARG
+    st = L.fsparse_assemble(None, None, None, 9, 0, 3, 3, 0, 0, None, 4,
+                            None, None, 0, None, None, 0, None, None, None)
+    assert st == L.E_ARG
+    assert L.fsparse_assemble_reuse(None, None, None, 0, None) == L.E_PLAN
+    assert L.fsparse_backward(None, -1, None, 0, L.F64, None, None) == L.E_ARG
+    assert L.fsparse_plan_query(None, None, None, None) == L.E_PLAN
+    L.fsparse_plan_destroy(None)

@@ -1,0 +1,179 @@
+"""HIP path against the CPU oracle, element by element (bit-exact).
+
+Sizes span many LDS chunks and ragged tails; the chunk capacity is lowered
+in some cases so that the multi-batch and long-column paths run on inputs
+the oracle handles in seconds.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from golden.load import load
+from gpu_util import assert_same, check, run, to_dev
+
+pytestmark = pytest.mark.gpu
+
+EX = load("worked_example.txt")
+
+
+@pytest.fixture(scope="module")
+def fs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1406_1066_amd as fs
+    fs.set_tuning(reset=True)
+    yield fs
+    fs.set_tuning(reset=True)
+
+
+@pytest.fixture
+def cap(fs):
+    def set_cap(c):
+        fs.set_tuning(chunk_cap=c)
+    yield set_cap
+    fs.set_tuning(reset=True)
+
+
+def i32(a):
+    return np.asarray(a, dtype=np.int32)
+
+
+def test_worked_example(fs):
+    res, ref = check(fs, i32(EX["example_i"]), i32(EX["example_j"]),
+                     EX["example_s"])
+    np.testing.assert_array_equal(res.prS.cpu().numpy(), EX["prS"])
+    np.testing.assert_array_equal(res.slot.cpu().numpy(), EX["example_irank"])
+
+
+def test_worked_example_sorted(fs):
+    check(fs, i32(EX["sorted_i"]), i32(EX["sorted_j"]), EX["sorted_s"])
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_tiny_random(fs, dtype):
+    rng = np.random.default_rng(77)
+    for case in range(60):
+        m = int(rng.integers(1, 13))
+        n = int(rng.integers(1, 13))
+        L = int(rng.integers(1, 80))
+        ii = rng.integers(1, m + 1, size=L).astype(np.int32)
+        jj = rng.integers(1, n + 1, size=L).astype(np.int32)
+        ss = (rng.standard_normal(L) * 10.0 ** rng.integers(-6, 7, size=L)
+              ).astype(dtype)
+        check(fs, ii, jj, ss, m, n)
+
+
+def test_fold_order_and_signed_zero(fs):
+    check(fs, i32([2, 2, 2, 1, 1]), i32([1, 1, 1, 2, 2]),
+          np.array([1.0, 1e16, -1e16, -0.0, -0.0]), 2, 2)
+
+
+@pytest.mark.parametrize("c", [1024, 2048, 4096])
+def test_fem2d_100_all_caps(fs, cap, c):
+    cap(c)
+    t = W.config("fem2d_100")
+    check(fs, t.ii, t.jj, t.ss, t.m, t.n)
+
+
+def test_fem3d_small(fs):
+    t = W.fem3d(14, 0.15, seed=3)
+    check(fs, t.ii, t.jj, t.ss, t.m, t.n)
+
+
+def test_fem3d_fp32(fs):
+    t = W.fem3d(11, 0.15, seed=4, dtype=np.float32)
+    check(fs, t.ii, t.jj, t.ss, t.m, t.n)
+
+
+def test_uniform_medium(fs):
+    t = W.uniform(300_000, 20_000, 7_000, seed=5)
+    check(fs, t.ii, t.jj, t.ss, t.m, t.n)
+
+
+def test_ransparse_counts(fs):
+    t = W.ransparse(3000, 30, 20, seed=8)
+    res, ref = check(fs, t.ii, t.jj, t.ss, t.m, t.n)
+    assert float(res.prS.sum().item()) == t.L
+
+
+@pytest.mark.parametrize("c", [8, 16, 64, 256])
+def test_small_capacity_forces_slow_paths(fs, cap, c):
+    cap(c)
+    rng = np.random.default_rng(c)
+    # mixed column lengths: many short, some far longer than the capacity
+    t = W.uniform(6000, 40, 30, seed=c)
+    check(fs, t.ii, t.jj, t.ss, t.m, t.n)
+    t = W.fem2d(9, 0.2, seed=c)
+    check(fs, t.ii, t.jj, t.ss, t.m, t.n)
+    ii = rng.integers(1, 500, size=3000).astype(np.int32)
+    jj = np.full(3000, 3, dtype=np.int32)
+    check(fs, ii, jj, rng.standard_normal(3000), 600, 5)
+
+
+def test_single_column_and_single_pair(fs, cap):
+    rng = np.random.default_rng(2)
+    for c in (2048, 64):
+        cap(c)
+        L = 20000
+        ii = rng.integers(1, 3000, size=L).astype(np.int32)
+        check(fs, ii, np.ones(L, dtype=np.int32), rng.standard_normal(L))
+        check(fs, np.full(L, 7, dtype=np.int32), np.full(L, 2, dtype=np.int32),
+              rng.standard_normal(L), 9, 4)
+
+
+def test_empty_columns_and_given_dims(fs):
+    check(fs, i32([1, 3]), i32([2, 9]), np.array([1.0, 2.0]), 5, 200000)
+    check(fs, i32([4]), i32([1]), np.array([1.5]), 10, 1)
+
+
+def test_len_zero(fs):
+    res = run(fs, i32([]), i32([]), np.array([]), 3, 4)
+    assert res.nnz == 0 and res.jcS.cpu().tolist() == [0] * 5
+    res = run(fs, i32([]), i32([]), np.array([]))
+    assert (res.m, res.n, res.nnz) == (0, 0, 0)
+
+
+def test_default_dims(fs):
+    t = W.uniform(5000, 300, 200, seed=1)
+    ref = oracle.assemble(t.ii, t.jj, t.ss)
+    res = run(fs, t.ii, t.jj, t.ss, keep_slot=True)
+    assert (res.m, res.n) == (ref.m, ref.n)
+    assert_same(res, ref)
+
+
+@pytest.mark.parametrize("ii,jj,m,n", [
+    ([0, 1], [1, 1], None, None), ([1, 1], [1, -2], None, None),
+    ([3, 1], [1, 1], 2, 2), ([1, 1], [1, 3], 2, 2)])
+def test_bad_index(fs, ii, jj, m, n):
+    with pytest.raises(fs.FsparseIndexError):
+        run(fs, i32(ii), i32(jj), np.ones(2), m, n)
+
+
+def test_capacity_retry(fs):
+    t = W.fem2d(30, 0.2, seed=2)
+    ref = oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
+    res = run(fs, t.ii, t.jj, t.ss, t.m, t.n, cap=10, keep_slot=True)
+    assert_same(res, ref)
+
+
+def test_deterministic_bytes(fs, cap):
+    t = W.fem3d(12, 0.15, seed=9)
+    outs = []
+    for c in (1024, 2048, 4096, 1024):
+        cap(c)
+        r = run(fs, t.ii, t.jj, t.ss, t.m, t.n, keep_slot=True)
+        outs.append((r.jcS.cpu().numpy().tobytes(),
+                     r.irS.cpu().numpy().tobytes(),
+                     r.prS.cpu().numpy().tobytes(),
+                     r.slot.cpu().numpy().tobytes()))
+    assert all(o == outs[0] for o in outs)
+
+
+def test_stream_copy(fs):
+    a = torch.arange(1 << 20, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    fs.stream_copy(a, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
