@@ -185,6 +185,18 @@ fsparse_status fsparse_assemble_batched(
     int64_t cap, int64_t *nnz_off, int32_t *slot, void *ws, size_t ws_bytes,
     fsparse_plan **plan, fsparse_info *info, hipStream_t stream);
 
+/*
+ * Per-matrix default dimensions of a batch (largest row / column index of
+ * each matrix, 0 for a matrix without triplets), so that the caller can
+ * size jcS and ws before fsparse_assemble_batched.  trip_off is host [nb+1];
+ * m, n are host [nb] outputs.  ws needs fsparse_workspace_bytes(0, 0, nb, dt)
+ * bytes.  Any index below 1 gives FSPARSE_E_INDEX.  Waits for the stream.
+ */
+fsparse_status fsparse_dims_batched(int32_t nb, const int64_t *trip_off,
+                                    const int32_t *ii, const int32_t *jj,
+                                    int64_t *m, int64_t *n, void *ws,
+                                    size_t ws_bytes, hipStream_t stream);
+
 /* Release a plan (host memory and its graph only; device buffers are the
  * caller's).  NULL is ignored. */
 void fsparse_plan_destroy(fsparse_plan *plan);

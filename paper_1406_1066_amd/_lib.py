@@ -70,6 +70,10 @@ fsparse_assemble_batched = _sig(
      ctypes.POINTER(_i64), _u, _vp, _i64, _vp, _vp, _i64,
      ctypes.POINTER(_i64), _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp),
      ctypes.POINTER(FsparseInfo), _vp])
+fsparse_dims_batched = _sig("fsparse_dims_batched", _st,
+                            [_i32, ctypes.POINTER(_i64), _vp, _vp,
+                             ctypes.POINTER(_i64), ctypes.POINTER(_i64), _vp,
+                             ctypes.c_size_t, _vp])
 fsparse_plan_destroy = _sig("fsparse_plan_destroy", None, [_vp])
 fsparse_plan_query = _sig("fsparse_plan_query", _st,
                           [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
@@ -89,7 +93,8 @@ fsparse_stream_copy = _sig("fsparse_stream_copy", _st,
 EXPORTS = [
     "fsparse_version", "fsparse_status_string", "fsparse_workspace_bytes",
     "fsparse_dims", "fsparse_assemble", "fsparse_assemble_reuse",
-    "fsparse_backward", "fsparse_assemble_batched", "fsparse_plan_destroy",
+    "fsparse_backward", "fsparse_assemble_batched", "fsparse_dims_batched",
+    "fsparse_plan_destroy",
     "fsparse_plan_query", "fsparse_set_tuning", "fsparse_get_tuning",
     "fsparse_timing_enable", "fsparse_timing_read", "fsparse_stage_name",
     "fsparse_stream_copy",

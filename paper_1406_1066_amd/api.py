@@ -145,7 +145,8 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
            n: Optional[int] = None, nzmax: Optional[int] = None, *,
            atomic: bool = False, keep_slot: bool = False, plan: bool = False,
            cap: Optional[int] = None,
-           ws: Optional[torch.Tensor] = None) -> Assembled:
+           ws: Optional[torch.Tensor] = None,
+           out: Optional[tuple] = None) -> Assembled:
     """S = sparse(ii, jj, ss, m, n, nzmax) on the GPU.
 
     ``ii``/``jj`` unit-offset indices (any integer tensor, converted to
@@ -153,7 +154,8 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
     ``m``/``n`` default to the largest index.  ``cap`` is the capacity of
     irS/prS (default len, always enough).  With ``plan=True`` the result
     carries a re-use plan (see ``reassemble``); ``keep_slot`` returns the
-    inverse rank slot[k].
+    inverse rank slot[k].  ``out = (jcS, irS, prS[, slot])`` supplies
+    preallocated output buffers (irS/prS capacity = their length).
     """
     dev = _device(ss, ii, jj)
     ss = ss.contiguous()
@@ -168,18 +170,28 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
         m = dm if m is None else m
         n = dn if n is None else n
     m, n = int(m), int(n)
-    if cap is None:
-        cap = max(Ln, 1)
     need = workspace_bytes(Ln, n, 1, ss.dtype)
     if ws is None or ws.numel() < need:
         ws = _workspace(need, dev)
-    jcS = torch.empty(n + 1, dtype=torch.int32, device=dev)
     slot = None
-    if keep_slot or plan or atomic:
+    if out is not None:
+        jcS, irS0, prS0 = out[0], out[1], out[2]
+        if len(out) > 3:
+            slot = out[3]
+        cap = min(irS0.numel(), prS0.numel())
+    else:
+        jcS = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        irS0 = prS0 = None
+        if cap is None:
+            cap = max(Ln, 1)
+    if slot is None and (keep_slot or plan or atomic):
         slot = torch.empty(max(Ln, 1), dtype=torch.int32, device=dev)
     while True:
-        irS = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-        prS = torch.empty(max(cap, 1), dtype=ss.dtype, device=dev)
+        if irS0 is not None:
+            irS, prS = irS0, prS0
+        else:
+            irS = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            prS = torch.empty(max(cap, 1), dtype=ss.dtype, device=dev)
         info = L.FsparseInfo()
         ph = ctypes.c_void_p()
         st = L.fsparse_assemble(
@@ -188,7 +200,7 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
             L.ATOMIC if atomic else L.ORDERED, _ptr(jcS), jcS.numel(),
             _ptr(irS), _ptr(prS), cap, _ptr(slot), _ptr(ws), ws.numel(),
             ctypes.byref(ph) if plan else None, ctypes.byref(info), _stream())
-        if st == L.E_CAPACITY and info.nnz > cap:
+        if st == L.E_CAPACITY and info.nnz > cap and irS0 is None:
             cap = int(info.nnz)       # retry with the reported size
             continue
         _check(st, "fsparse_assemble")
@@ -327,6 +339,20 @@ def assemble_batched(ii, jj, ss: torch.Tensor, trip_off: Sequence[int],
     to = (ctypes.c_int64 * (nb + 1))(*[int(x) for x in trip_off])
     mm = (ctypes.c_int64 * nb)(*[int(x) for x in m])
     nn = (ctypes.c_int64 * nb)(*[int(x) for x in n])
+    if any(int(x) < 0 for x in m) or any(int(x) < 0 for x in n):
+        dm = (ctypes.c_int64 * nb)()
+        dn = (ctypes.c_int64 * nb)()
+        w0 = _workspace(workspace_bytes(0, 0, nb, ss.dtype), dev)
+        _check(L.fsparse_dims_batched(nb, to, _ptr(ii), _ptr(jj), dm, dn,
+                                      _ptr(w0), w0.numel(), _stream()),
+               "fsparse_dims_batched")
+        for b in range(nb):
+            if mm[b] < 0:
+                mm[b] = dm[b]
+            if nn[b] < 0:
+                nn[b] = dn[b]
+        m = [mm[b] for b in range(nb)]
+        n = [nn[b] for b in range(nb)]
     Ln = int(trip_off[-1])
     N = sum(int(x) for x in n)
     if cap is None:

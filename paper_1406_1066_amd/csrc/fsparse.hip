@@ -56,6 +56,7 @@ struct Rec {
 };
 bool g_timing = false;
 std::vector<Rec> g_recs;
+std::vector<hipEvent_t> g_pool;  // recycled timing events
 double g_ms[kNumStages];
 int64_t g_cnt[kNumStages];
 
@@ -71,7 +72,16 @@ hipError_t launch(int stage, hipStream_t s, F&& f) {
     return hipGetLastError();
   }
   Rec r{stage, nullptr, nullptr};
-  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess)
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_pool.size() >= 2) {
+      r.a = g_pool.back();
+      g_pool.pop_back();
+      r.b = g_pool.back();
+      g_pool.pop_back();
+    }
+  }
+  if (!r.a && (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess))
     return hipErrorOutOfMemory;
   hipEventRecord(r.a, s);
   f();
@@ -381,6 +391,46 @@ fsparse_status check_dt(fsparse_dtype dt) {
 
 constexpr int64_t kMaxI32 = 0x7FFFFFFE;
 
+// Per-matrix largest row / column index of a batch (defaults of the batched
+// call).  ws needs the small-table layout of make_layout(0, 0, nb, ...).
+fsparse_status batched_dims(int32_t nb, const int64_t* trip_off,
+                            const int32_t* ii, const int32_t* jj, int64_t L,
+                            fsparse_dtype dt, int cap, void* ws,
+                            size_t ws_bytes, int64_t* mm, int64_t* nn,
+                            hipStream_t stream) {
+  Layout pre = make_layout(0, 0, nb, esize_of(dt), cap);
+  if (ws_bytes < pre.total) return FSPARSE_E_CAPACITY;
+  Ctrl* hi = static_cast<Ctrl*>(pinned());
+  if (!hi || sizeof(Ctrl) + 8 * (size_t)nb > kPinnedBytes) return FSPARSE_E_ARG;
+  std::memset(hi, 0, sizeof(Ctrl));
+  hi->rmin = INT32_MAX;
+  hi->cmin = INT32_MAX;
+  HIPCHK(hipMemcpyAsync(ws, hi, sizeof(Ctrl), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemsetAsync(at<char>(ws, pre.bmax), 0, 8 * (size_t)nb, stream));
+  HIPCHK(hipMemcpyAsync(at<int64_t>(ws, pre.b_trip), trip_off,
+                        8 * (size_t)(nb + 1), hipMemcpyHostToDevice, stream));
+  BatchDesc bd{at<int64_t>(ws, pre.b_trip), nullptr, nullptr, nullptr, nb};
+  hipError_t e = launch(kDims, stream, [&] {
+    hipLaunchKernelGGL(fsp::k_dims<true>, dim3(grid_for(L, 256, 8)), dim3(256),
+                       0, stream, ii, jj, L, bd, (Ctrl*)ws,
+                       at<int32_t>(ws, pre.bmax));
+  });
+  if (e != hipSuccess) return FSPARSE_E_HIP;
+  char* h = reinterpret_cast<char*>(hi);
+  HIPCHK(hipMemcpyAsync(h + sizeof(Ctrl), at<char>(ws, pre.bmax), 8 * (size_t)nb,
+                        hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(h, ws, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  const Ctrl* hc = reinterpret_cast<const Ctrl*>(h);
+  if (hc->rmin < 1 || hc->cmin < 1) return FSPARSE_E_INDEX;
+  const int32_t* bm = reinterpret_cast<const int32_t*>(h + sizeof(Ctrl));
+  for (int b = 0; b < nb; ++b) {
+    if (mm[b] < 0) mm[b] = bm[2 * b];
+    if (nn[b] < 0) nn[b] = bm[2 * b + 1];
+  }
+  return FSPARSE_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -607,37 +657,9 @@ fsparse_status fsparse_assemble_batched(
   // worst-case layout for the dims pass: tables must fit before N is known
   if (ws_bytes < 4096) return FSPARSE_E_CAPACITY;
   if (need_dims && L > 0) {
-    Layout pre = make_layout(0, 0, nb, esize_of(dt), tu.cap);
-    if (ws_bytes < pre.total) return FSPARSE_E_CAPACITY;
-    Ctrl* hi = static_cast<Ctrl*>(pinned());
-    if (!hi) return FSPARSE_E_HIP;
-    std::memset(hi, 0, sizeof(Ctrl));
-    hi->rmin = INT32_MAX;
-    hi->cmin = INT32_MAX;
-    HIPCHK(hipMemcpyAsync(ws, hi, sizeof(Ctrl), hipMemcpyHostToDevice, stream));
-    HIPCHK(hipMemsetAsync(at<char>(ws, pre.bmax), 0, 8 * (size_t)nb, stream));
-    HIPCHK(hipMemcpyAsync(at<int64_t>(ws, pre.b_trip), trip_off,
-                          8 * (size_t)(nb + 1), hipMemcpyHostToDevice, stream));
-    BatchDesc bd{at<int64_t>(ws, pre.b_trip), nullptr, nullptr, nullptr, nb};
-    hipError_t e = launch(kDims, stream, [&] {
-      hipLaunchKernelGGL(fsp::k_dims<true>, dim3(grid_for(L, 256, 8)), dim3(256),
-                         0, stream, ii, jj, L, bd, (Ctrl*)ws,
-                         at<int32_t>(ws, pre.bmax));
-    });
-    if (e != hipSuccess) return FSPARSE_E_HIP;
-    char* h = static_cast<char*>(pinned());
-    if (!h || sizeof(Ctrl) + 8 * (size_t)nb > kPinnedBytes) return FSPARSE_E_ARG;
-    HIPCHK(hipMemcpyAsync(h, ws, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipMemcpyAsync(h + sizeof(Ctrl), at<char>(ws, pre.bmax), 8 * (size_t)nb,
-                          hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    const Ctrl* hc = reinterpret_cast<const Ctrl*>(h);
-    if (hc->rmin < 1 || hc->cmin < 1) return FSPARSE_E_INDEX;
-    const int32_t* bm = reinterpret_cast<const int32_t*>(h + sizeof(Ctrl));
-    for (int b = 0; b < nb; ++b) {
-      if (mm[b] < 0) mm[b] = bm[2 * b];
-      if (nn[b] < 0) nn[b] = bm[2 * b + 1];
-    }
+    fsparse_status st = batched_dims(nb, trip_off, ii, jj, L, dt, tu.cap, ws,
+                                     ws_bytes, mm.data(), nn.data(), stream);
+    if (st != FSPARSE_OK) return st;
   }
   for (int b = 0; b < nb; ++b) {
     if (mm[b] < 0) mm[b] = 0;
@@ -756,6 +778,32 @@ fsparse_status fsparse_assemble_batched(
   return FSPARSE_OK;
 }
 
+fsparse_status fsparse_dims_batched(int32_t nb, const int64_t* trip_off,
+                                    const int32_t* ii, const int32_t* jj,
+                                    int64_t* m, int64_t* n, void* ws,
+                                    size_t ws_bytes, hipStream_t stream) {
+  if (nb < 1 || !trip_off || !m || !n || !ws || trip_off[0] != 0)
+    return FSPARSE_E_ARG;
+  for (int b = 0; b < nb; ++b)
+    if (trip_off[b + 1] < trip_off[b]) return FSPARSE_E_ARG;
+  const int64_t L = trip_off[nb];
+  if (L > kMaxI32 || (L > 0 && (!ii || !jj))) return FSPARSE_E_ARG;
+  for (int b = 0; b < nb; ++b) {
+    m[b] = -1;
+    n[b] = -1;
+  }
+  if (L > 0) {
+    fsparse_status st = batched_dims(nb, trip_off, ii, jj, L, FSPARSE_F64,
+                                     tuning().cap, ws, ws_bytes, m, n, stream);
+    if (st != FSPARSE_OK) return st;
+  }
+  for (int b = 0; b < nb; ++b) {
+    if (m[b] < 0) m[b] = 0;
+    if (n[b] < 0) n[b] = 0;
+  }
+  return FSPARSE_OK;
+}
+
 void fsparse_plan_destroy(fsparse_plan* plan) {
   if (!plan) return;
   if (plan->x_ord) (void)hipGraphExecDestroy(plan->x_ord);
@@ -834,8 +882,9 @@ int fsparse_timing_read(double* ms, int64_t* launches, int max_stages) {
       g_ms[r.stage] += t;
       g_cnt[r.stage] += 1;
     }
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
   }
   std::lock_guard<std::mutex> lk(g_mu);
   for (int s = 0; s < kNumStages && s < max_stages; ++s) {

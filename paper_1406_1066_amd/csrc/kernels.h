@@ -965,7 +965,7 @@ __global__ void k_batched_jcs(const int32_t* __restrict__ jcg,
                               int64_t* __restrict__ nnz_off) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  if (idx <= nb) nnz_off[idx] = jcg[col_off[idx]];
+  for (int64_t b = idx; b <= nb; b += stride) nnz_off[b] = jcg[col_off[b]];
   for (; idx < total; idx += stride) {
     // matrix b owns positions [col_off[b] + b, col_off[b+1] + b + 1)
     int lo = 0, hi = nb;
