@@ -42,15 +42,14 @@ def kernel_hash() -> str:
 
 def stage_bytes(stage, L, nnz, n, vb, eb, plan=False, slot=False):
     """Algorithmic bytes of one launch of a stage: every array the stage
-    must read or write, touched once."""
-    if stage == "hist":
-        return 4 * L + 4 * n
-    if stage == "scan":
-        return 4 * n + 8 * (n + 1)
-    if stage == "bucket":
-        return (8 + vb) * L + eb * L
-    if stage == "chunk":
-        b = eb * L + 4 * (n + 1) + (4 + vb) * nnz + 4 * (n + 1)
+    must read or write, touched once.  eb = bytes of one binned triplet
+    (row, k, value), vb = bytes of one value."""
+    if stage == "count":
+        return 4 * L
+    if stage == "scatter":
+        return (8 + vb) * L + (eb + 4) * L
+    if stage == "bin":
+        b = (eb + 4) * L + (4 + vb) * nnz + 4 * (n + 1)
         if slot:
             b += 4 * L
         if plan:

@@ -9,7 +9,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfsparse.so")
+# FSPARSE_LIBRARY may point at another build of the same ABI
+LIB_PATH = os.environ.get("FSPARSE_LIBRARY") or os.path.join(HERE, "libfsparse.so")
 
 F64, F32 = 0, 1
 ORDERED, ATOMIC = 0, 1

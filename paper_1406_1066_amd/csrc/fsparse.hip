@@ -44,11 +44,11 @@ int kernel_cap(int cap) { return cap <= 1024 ? 1024 : (cap <= 2048 ? 2048 : 4096
 // ---------------------------------------------------------------------------
 enum Stage {
   kDims, kInit, kHist, kScan, kBucket, kChunk, kBatchedJcs, kAtomic,
-  kReuse, kBackward, kCopy, kFill, kNumStages
+  kReuse, kBackward, kCopy, kFill, kColScan, kNumStages
 };
 const char* kStageNames[kNumStages] = {
-    "dims", "init", "hist", "scan", "bucket", "chunk", "batched_jcs",
-    "atomic", "reuse", "backward", "copy", "fill"};
+    "dims", "init", "count", "binscan", "scatter", "bin", "batched_jcs",
+    "atomic", "reuse", "backward", "copy", "fill", "colscan"};
 
 struct Rec {
   int stage;
@@ -135,32 +135,70 @@ void* pinned() {
 constexpr int kScanNT = 256;
 constexpr int kScanIPT = 16;
 constexpr int64_t kScanTile = (int64_t)kScanNT * kScanIPT;
+constexpr int64_t kDenseBins = 16384;       // LDS counters of the dense mode
+constexpr int64_t kDenseMatrix = 8 << 20;   // tiles x bins counters
+constexpr int kClaimNT = 256;
+constexpr int kClaimIPT = 16;
+constexpr int kClaimWindow = 16384;         // LDS bins of one claim tile
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Column bins: w = 2^s columns per bin, sized so that an average bin holds
+// about half the sort stage's LDS capacity.
+struct Geom {
+  int s;
+  int64_t w, B, TS, T;
+  bool dense;
+};
+
+Geom make_geom(int64_t L, int64_t N, int cap) {
+  Geom g{};
+  int64_t w = 1;
+  if (L > 0) {
+    const double target = (double)std::max(1, cap / 2) * (double)N / (double)L;
+    while (w * 2 <= target && w * 2 <= cap) w *= 2;
+  }
+  g.w = w;
+  g.s = 0;
+  while ((int64_t(1) << g.s) < w) ++g.s;
+  g.B = std::max<int64_t>(1, (N + w - 1) / w);
+  g.dense = g.B <= kDenseBins;
+  if (g.dense) {
+    g.TS = 4096;
+    while (((L + g.TS - 1) / g.TS) * g.B > kDenseMatrix && g.TS < (1 << 22)) g.TS *= 2;
+  } else {
+    g.TS = (int64_t)kClaimNT * kClaimIPT;
+  }
+  g.T = std::max<int64_t>(1, (L + g.TS - 1) / g.TS);
+  return g;
+}
+
 struct Layout {
-  size_t ctrl, scan_st, chunk_st, colcnt, zero_end;
-  size_t colptr, fill, chunk_col, bucket, tmp, perm, seg, islot;
-  size_t b_trip, b_col, b_m, b_n, jcg, nnzoff, bmax;
+  Geom g;
+  size_t ctrl, scan_st, bin_st, bincnt, binfill, bmax, zero_end;
+  size_t binstart, cntmat, bcol, colptr, bucket, tmp, perm, seg, islot;
+  size_t b_trip, b_col, b_m, b_n, jcg, nnzoff;
   size_t total;
-  int64_t nscan, Q, T;
+  int64_t nscan;
 };
 
 Layout make_layout(int64_t L, int64_t N, int nb, int esize, int cap) {
   Layout o{};
-  o.T = std::max(1, cap / 2);
-  o.nscan = (N + 1 + kScanTile - 1) / kScanTile;
-  o.Q = L / o.T + 1;
+  o.g = make_geom(L, N, cap);
+  const int64_t B = o.g.B;
+  o.nscan = (B + 1 + kScanTile - 1) / kScanTile;
   size_t p = 0;
   o.ctrl = p;        p = al(p + sizeof(Ctrl));
   o.scan_st = p;     p = al(p + 8 * (size_t)o.nscan);
-  o.chunk_st = p;    p = al(p + 8 * (size_t)o.Q);
-  o.colcnt = p;      p = al(p + 4 * (size_t)(N + 1));
+  o.bin_st = p;      p = al(p + 8 * (size_t)B);
+  o.bincnt = p;      p = al(p + 4 * (size_t)B);
+  o.binfill = p;     p = al(p + 4 * (size_t)B);
   o.bmax = p;        p = al(p + 8 * (size_t)nb);
   o.zero_end = p;
+  o.binstart = p;    p = al(p + 4 * (size_t)(B + 1));
+  o.cntmat = p;      p = al(p + (o.g.dense ? 4 * (size_t)o.g.T * B : 0));
+  o.bcol = p;        p = al(p + 4 * (size_t)L);
   o.colptr = p;      p = al(p + 4 * (size_t)(N + 1));
-  o.fill = p;        p = al(p + 4 * (size_t)(N + 1));
-  o.chunk_col = p;   p = al(p + 4 * (size_t)(o.Q + 1));
   o.bucket = p;      p = al(p + (size_t)esize * L);
   o.tmp = p;         p = al(p + (size_t)esize * L);
   o.perm = p;        p = al(p + 4 * (size_t)L);
@@ -318,50 +356,74 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
                         void* ws, int32_t* jcS_target, int32_t* irS, VT* prS,
                         int64_t cap, int32_t* slot, bool keep_plan,
                         hipStream_t stream) {
+  const Geom& g = lo.g;
   Ctrl* ctrl = at<Ctrl>(ws, lo.ctrl);
   hipError_t e;
-  // init: zero control block, look-back words, column counts
   const int64_t zwords = (int64_t)(lo.zero_end / 4);
   e = launch(kInit, stream, [&] {
     hipLaunchKernelGGL(fsp::k_zero, dim3(grid_for(zwords, 256, 4)), dim3(256), 0,
                        stream, at<uint32_t>(ws, 0), zwords);
   });
   if (e != hipSuccess) return e;
-  const int blk = tu.sblock, items = tu.sitems;
-  const int64_t tiles = (L + (int64_t)blk * items - 1) / ((int64_t)blk * items);
-  int32_t* colcnt = at<int32_t>(ws, lo.colcnt);
-  e = launch(kHist, stream, [&] {
-    hipLaunchKernelGGL(fsp::k_hist<BATCHED>, dim3((unsigned)tiles), dim3(blk), 0,
-                       stream, jj, L, n, bd, colcnt, ctrl, items);
-  });
-  if (e != hipSuccess) return e;
-  int32_t* colptr = at<int32_t>(ws, lo.colptr);
-  int32_t* fill = at<int32_t>(ws, lo.fill);
-  int32_t* chunk_col = at<int32_t>(ws, lo.chunk_col);
-  e = launch(kScan, stream, [&] {
-    hipLaunchKernelGGL((fsp::k_scan<kScanNT, kScanIPT>), dim3((unsigned)lo.nscan),
-                       dim3(kScanNT), 0, stream, colcnt, (int32_t)N, colptr, fill,
-                       chunk_col, (int32_t)lo.T, (int32_t)lo.Q,
-                       at<uint64_t>(ws, lo.scan_st), ctrl);
-  });
-  if (e != hipSuccess) return e;
+  uint32_t* bincnt = at<uint32_t>(ws, lo.bincnt);
+  uint32_t* binfill = at<uint32_t>(ws, lo.binfill);
+  int32_t* binstart = at<int32_t>(ws, lo.binstart);
+  uint32_t* cntmat = at<uint32_t>(ws, lo.cntmat);
+  uint32_t* bcol = at<uint32_t>(ws, lo.bcol);
   Entry<VT>* bucket = at<Entry<VT>>(ws, lo.bucket);
-  e = launch(kBucket, stream, [&] {
-    hipLaunchKernelGGL((fsp::k_bucket<VT, BATCHED>), dim3((unsigned)tiles),
-                       dim3(blk), 0, stream, ii, jj, ss, L, m, n, bd, fill,
-                       bucket, ctrl, items);
+  const int s = g.s, B = (int)g.B;
+  const int blk = tu.sblock;
+  // 1. bin counts
+  e = launch(kHist, stream, [&] {
+    if (g.dense)
+      hipLaunchKernelGGL(fsp::k_count_dense<BATCHED>, dim3((unsigned)g.T), dim3(blk),
+                         (size_t)B * 4, stream, jj, L, n, bd, s, B, (int32_t)g.TS,
+                         cntmat, ctrl);
+    else
+      hipLaunchKernelGGL((fsp::k_count_claim<BATCHED, kClaimNT, kClaimIPT>),
+                         dim3((unsigned)g.T), dim3(kClaimNT),
+                         (size_t)kClaimWindow * 4, stream, jj, L, n, bd, s,
+                         kClaimWindow, bincnt, ctrl);
   });
   if (e != hipSuccess) return e;
+  if (g.dense) {
+    e = launch(kColScan, stream, [&] {
+      hipLaunchKernelGGL(fsp::k_colscan, dim3((unsigned)((B + 255) / 256)), dim3(256),
+                         0, stream, cntmat, (int32_t)g.T, B, bincnt);
+    });
+    if (e != hipSuccess) return e;
+  }
+  // 2. bin pointers
+  e = launch(kScan, stream, [&] {
+    hipLaunchKernelGGL((fsp::k_scan_excl<kScanNT, kScanIPT>), dim3((unsigned)lo.nscan),
+                       dim3(kScanNT), 0, stream, bincnt, B, binstart,
+                       at<uint64_t>(ws, lo.scan_st), &ctrl->tick_scan);
+  });
+  if (e != hipSuccess) return e;
+  // 3. scatter into the bins
+  e = launch(kBucket, stream, [&] {
+    if (g.dense)
+      hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED>), dim3((unsigned)g.T),
+                         dim3(blk), (size_t)B * 4, stream, ii, jj, ss, L, m, n, bd,
+                         s, B, (int32_t)g.TS, cntmat, binstart, bucket, bcol, ctrl);
+    else
+      hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, kClaimNT, kClaimIPT>),
+                         dim3((unsigned)g.T), dim3(kClaimNT),
+                         (size_t)kClaimWindow * 4, stream, ii, jj, ss, L, m, n, bd,
+                         s, kClaimWindow, binstart, binfill, bucket, bcol, ctrl);
+  });
+  if (e != hipSuccess) return e;
+  // 4. one workgroup per bin: group, rank, order, fold, emit
   ChunkArgs<VT> a{};
-  a.colptr = colptr;
-  a.chunk_col = chunk_col;
+  a.colptr = nullptr;
+  a.chunk_col = nullptr;
   a.bucket = bucket;
   a.tmp = at<Entry<VT>>(ws, lo.tmp);
   a.N = (int32_t)N;
-  a.T = (int32_t)lo.T;
+  a.T = 0;
   a.cap = tu.cap;
-  a.Q = (int32_t)lo.Q;
-  a.status = at<uint64_t>(ws, lo.chunk_st);
+  a.Q = B;
+  a.status = at<uint64_t>(ws, lo.bin_st);
   a.ctrl = ctrl;
   a.jcS = jcS_target;
   a.irS = irS;
@@ -370,17 +432,18 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   a.slot = slot;
   a.perm = keep_plan ? at<int32_t>(ws, lo.perm) : nullptr;
   a.seg = keep_plan ? at<int32_t>(ws, lo.seg) : nullptr;
+  int32_t* colptr_g = at<int32_t>(ws, lo.colptr);
   const int kc = kernel_cap(tu.cap);
   e = launch(kChunk, stream, [&] {
     if (kc == 1024)
-      hipLaunchKernelGGL((fsp::k_chunk<VT, 1024, 256>), dim3((unsigned)lo.Q),
-                         dim3(256), 0, stream, a);
+      hipLaunchKernelGGL((fsp::k_bin<VT, 1024, 256>), dim3((unsigned)B), dim3(256), 0,
+                         stream, a, binstart, bcol, colptr_g, s, B);
     else if (kc == 2048)
-      hipLaunchKernelGGL((fsp::k_chunk<VT, 2048, 256>), dim3((unsigned)lo.Q),
-                         dim3(256), 0, stream, a);
+      hipLaunchKernelGGL((fsp::k_bin<VT, 2048, 256>), dim3((unsigned)B), dim3(256), 0,
+                         stream, a, binstart, bcol, colptr_g, s, B);
     else
-      hipLaunchKernelGGL((fsp::k_chunk<VT, 4096, 512>), dim3((unsigned)lo.Q),
-                         dim3(512), 0, stream, a);
+      hipLaunchKernelGGL((fsp::k_bin<VT, 4096, 512>), dim3((unsigned)B), dim3(512), 0,
+                         stream, a, binstart, bcol, colptr_g, s, B);
   });
   return e;
 }

@@ -75,11 +75,15 @@ struct BatchDesc {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t ld_acq(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Look-back status words carry their flag and value in one 64-bit word and
+// no other data is published through them, so relaxed device-scope atomics
+// are enough (acquire/release would add cache invalidation and write-back
+// around every access).
+__device__ __forceinline__ uint64_t ld_status(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_rel(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void st_status(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
@@ -187,15 +191,15 @@ __device__ void lds_incl_max(uint32_t* arr, int S, uint32_t* sWave) {
 __device__ int64_t lookback(uint64_t* status, int q, uint64_t agg) {
   const int lane = lane_id();
   if (q == 0) {
-    if (lane == 0) st_rel(&status[0], kFlagPrefix | agg);
+    if (lane == 0) st_status(&status[0], kFlagPrefix | agg);
     return 0;
   }
-  if (lane == 0) st_rel(&status[q], kFlagAgg | agg);
+  if (lane == 0) st_status(&status[q], kFlagAgg | agg);
   int64_t excl = 0;
   int pred = q - 1;
   for (;;) {
     const int idx = pred - lane;
-    const uint64_t s = (idx >= 0) ? ld_acq(&status[idx]) : kFlagPrefix;
+    const uint64_t s = (idx >= 0) ? ld_status(&status[idx]) : kFlagPrefix;
     const uint32_t flag = (uint32_t)(s >> 62);
     const uint64_t inval = __ballot(flag == 0);
     const uint64_t pref = __ballot(flag == 2);
@@ -211,7 +215,7 @@ __device__ int64_t lookback(uint64_t* status, int q, uint64_t agg) {
     if (pl < 64) break;
     pred -= 64;
   }
-  if (lane == 0) st_rel(&status[q], kFlagPrefix | (uint64_t)(excl + (int64_t)agg));
+  if (lane == 0) st_status(&status[q], kFlagPrefix | (uint64_t)(excl + (int64_t)agg));
   return excl;
 }
 
@@ -279,93 +283,6 @@ __global__ void k_dims(const int32_t* __restrict__ ii,
 }
 
 // ---------------------------------------------------------------------------
-// hist: triplets per column; out-of-range columns are flagged and skipped
-// ---------------------------------------------------------------------------
-template <bool BATCHED>
-__global__ void k_hist(const int32_t* __restrict__ jj, int64_t L, int32_t n,
-                       BatchDesc bd, int32_t* __restrict__ cnt, Ctrl* ctrl,
-                       int items) {
-  const int64_t tile = (int64_t)blockDim.x * items;
-  const int64_t t0 = (int64_t)blockIdx.x * tile;
-  __shared__ int sB;
-  int b = 0;
-  if (BATCHED) {
-    if (threadIdx.x == 0) sB = find_mat(bd.trip_off, bd.nb, min(t0, L - 1));
-    __syncthreads();
-    b = sB;
-  }
-  bool bad = false;
-  for (int j = 0; j < items; ++j) {
-    const int64_t e = t0 + (int64_t)j * blockDim.x + threadIdx.x;
-    if (e >= L) break;
-    const int32_t c = jj[e] - 1;
-    if (BATCHED) {
-      while (bd.trip_off[b + 1] <= e) ++b;
-      if ((uint32_t)c >= (uint32_t)bd.ndim[b]) { bad = true; continue; }
-      atomicAdd(&cnt[bd.col_off[b] + c], 1);
-    } else {
-      if ((uint32_t)c >= (uint32_t)n) { bad = true; continue; }
-      atomicAdd(&cnt[c], 1);
-    }
-  }
-  if (bad) atomicOr(&ctrl->err, kErrCol);
-}
-
-// ---------------------------------------------------------------------------
-// scan: colptr = exclusive prefix of cnt[0..N] (cnt[N] = 0), fill = colptr,
-// chunk_col[q] = first column whose colptr is >= q*T (q = 0..Q)
-// ---------------------------------------------------------------------------
-template <int NT, int IPT>
-__global__ void __launch_bounds__(NT)
-k_scan(const int32_t* __restrict__ cnt, int32_t N, int32_t* __restrict__ colptr,
-       int32_t* __restrict__ fill, int32_t* __restrict__ chunk_col, int32_t T,
-       int32_t Q, uint64_t* status, Ctrl* ctrl) {
-  __shared__ uint32_t sWave[NT / 64];
-  __shared__ int sTile;
-  __shared__ int64_t sBase;
-  if (threadIdx.x == 0) sTile = (int)atomicAdd(&ctrl->tick_scan, 1u);
-  __syncthreads();
-  const int tile = sTile;
-  const int N1 = N + 1;
-  const int64_t i0 = (int64_t)tile * NT * IPT + (int64_t)threadIdx.x * IPT;
-  int32_t v[IPT];
-  uint32_t sum = 0;
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    const int64_t i = i0 + j;
-    v[j] = (i < N) ? cnt[i] : 0;
-    sum += (uint32_t)v[j];
-  }
-  uint32_t total;
-  const uint32_t pre = block_excl_sum<NT>(sum, sWave, total);
-  if (threadIdx.x < 64) {
-    int64_t ex = lookback(status, tile, total);
-    if (threadIdx.x == 0) sBase = ex;
-  }
-  __syncthreads();
-  int64_t run = sBase + pre;
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    const int64_t i = i0 + j;
-    if (i < N1) {
-      colptr[i] = (int32_t)run;
-      if (i < N) {
-        fill[i] = (int32_t)run;
-        // windows q with q*T in (colptr[i], colptr[i+1]] start at column i+1
-        const int64_t nx = run + v[j];
-        for (int64_t q = run / T + 1; q <= nx / T; ++q) chunk_col[q] = (int32_t)(i + 1);
-      } else {
-        // i == N: total number of bucketed triplets; later windows are empty
-        ctrl->ltot = run;
-        for (int64_t q = run / T + 1; q <= Q; ++q) chunk_col[q] = N + 1;
-      }
-      if (i == 0) chunk_col[0] = 0;
-    }
-    run += v[j];
-  }
-}
-
-// ---------------------------------------------------------------------------
 // bucket: scatter (row, k, value) into the column buckets
 // ---------------------------------------------------------------------------
 template <typename VT>
@@ -407,42 +324,296 @@ __device__ __forceinline__ Entry<float> load_entry<float>(const Entry<float>* p)
   return *p;
 }
 
-template <typename VT, bool BATCHED>
-__global__ void k_bucket(const int32_t* __restrict__ ii,
-                         const int32_t* __restrict__ jj,
-                         const VT* __restrict__ ss, int64_t L, int32_t m,
-                         int32_t n, BatchDesc bd, int32_t* __restrict__ fill,
-                         Entry<VT>* __restrict__ bucket, Ctrl* ctrl, int items) {
-  const int64_t tile = (int64_t)blockDim.x * items;
-  const int64_t t0 = (int64_t)blockIdx.x * tile;
-  __shared__ int sB;
-  int b = 0;
+// ---------------------------------------------------------------------------
+// Column bins.  Global column g (matrix b's column c is col_off[b] + c) lies
+// in bin g >> s; a bin is w = 2^s consecutive columns, and the bin kernel
+// handles one bin per workgroup.  Bin pointers come from per-tile LDS
+// histograms: either a dense tiles x bins count matrix whose column prefix
+// sums give every tile its exclusive offset in every bin (no device-wide
+// atomics at all), or, with too many bins for that, one global claim per
+// (tile, bin) that the tile touches.
+// ---------------------------------------------------------------------------
+
+// Global column of triplet e; `b` walks forward over the matrices.
+template <bool BATCHED>
+__device__ __forceinline__ int64_t global_col(const BatchDesc& bd, int& b,
+                                              int64_t e, int32_t c, int32_t n,
+                                              int32_t m, int32_t& mb, bool& ok) {
   if (BATCHED) {
-    if (threadIdx.x == 0) sB = find_mat(bd.trip_off, bd.nb, min(t0, L - 1));
-    __syncthreads();
-    b = sB;
+    while (bd.trip_off[b + 1] <= e) ++b;
+    ok = (uint32_t)c < (uint32_t)bd.ndim[b];
+    mb = bd.mdim[b];
+    return bd.col_off[b] + c;
   }
-  bool badr = false;
-  for (int j = 0; j < items; ++j) {
-    const int64_t e = t0 + (int64_t)j * blockDim.x + threadIdx.x;
-    if (e >= L) break;
-    const int32_t c = jj[e] - 1;
-    const int32_t r = ii[e] - 1;
-    int64_t g;
-    int32_t mb;
-    if (BATCHED) {
-      while (bd.trip_off[b + 1] <= e) ++b;
-      if ((uint32_t)c >= (uint32_t)bd.ndim[b]) continue;  // flagged by hist
-      g = bd.col_off[b] + c;
-      mb = bd.mdim[b];
-    } else {
-      if ((uint32_t)c >= (uint32_t)n) continue;
-      g = c;
-      mb = m;
+  ok = (uint32_t)c < (uint32_t)n;
+  mb = m;
+  return c;
+}
+
+template <bool BATCHED>
+__device__ __forceinline__ int tile_first_mat(const BatchDesc& bd, int64_t t0,
+                                              int64_t L, int* sB) {
+  if (!BATCHED) return 0;
+  if (threadIdx.x == 0) *sB = find_mat(bd.trip_off, bd.nb, min(t0, L - 1));
+  __syncthreads();
+  return *sB;
+}
+
+// Exclusive scan of in[0..n) (decoupled look-back) into out[0..n]; out[n]
+// is the total.
+template <int NT, int IPT>
+__global__ void __launch_bounds__(NT)
+k_scan_excl(const uint32_t* __restrict__ in, int32_t n, int32_t* __restrict__ out,
+            uint64_t* status, uint32_t* ticket) {
+  __shared__ uint32_t sWave[NT / 64];
+  __shared__ int sTile;
+  __shared__ int64_t sBase;
+  if (threadIdx.x == 0) sTile = (int)atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int tile = sTile;
+  const int64_t i0 = (int64_t)tile * NT * IPT + (int64_t)threadIdx.x * IPT;
+  uint32_t v[IPT];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    v[j] = (i0 + j < n) ? in[i0 + j] : 0u;
+    sum += v[j];
+  }
+  uint32_t total;
+  const uint32_t pre = block_excl_sum<NT>(sum, sWave, total);
+  if (threadIdx.x < 64) {
+    const int64_t ex = lookback(status, tile, total);
+    if (threadIdx.x == 0) sBase = ex;
+  }
+  __syncthreads();
+  int64_t run = sBase + pre;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    if (i0 + j <= n) out[i0 + j] = (int32_t)run;
+    run += v[j];
+  }
+}
+
+// dense mode, pass 1: per-tile bin histogram -> row `tile` of cnt[T][B]
+template <bool BATCHED>
+__global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
+                              int32_t n, BatchDesc bd, int32_t s, int32_t B,
+                              int32_t TS, uint32_t* __restrict__ cnt,
+                              Ctrl* ctrl) {
+  extern __shared__ uint32_t hist[];
+  __shared__ int sB;
+  const int64_t t0 = (int64_t)blockIdx.x * TS;
+  const int64_t t1 = min(L, t0 + TS);
+  for (int i = threadIdx.x; i < B; i += blockDim.x) hist[i] = 0u;
+  int b = tile_first_mat<BATCHED>(bd, t0, L, &sB);
+  __syncthreads();
+  bool bad = false;
+  int32_t mb;
+  for (int64_t e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
+    bool ok;
+    const int64_t g = global_col<BATCHED>(bd, b, e, jj[e] - 1, n, 0, mb, ok);
+    if (!ok) { bad = true; continue; }
+    atomicAdd(&hist[g >> s], 1u);
+  }
+  __syncthreads();
+  uint32_t* row = cnt + (int64_t)blockIdx.x * B;
+  for (int i = threadIdx.x; i < B; i += blockDim.x) row[i] = hist[i];
+  if (bad) atomicOr(&ctrl->err, kErrCol);
+}
+
+// dense mode, pass 2: for every bin, exclusive prefix over the tiles (in
+// place) and the bin total
+__global__ void k_colscan(uint32_t* __restrict__ cnt, int32_t T, int32_t B,
+                          uint32_t* __restrict__ tot) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  uint32_t run = 0;
+  int t = 0;
+  for (; t + 8 <= T; t += 8) {
+    uint32_t c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = cnt[(int64_t)(t + u) * B + b];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      cnt[(int64_t)(t + u) * B + b] = run;
+      run += c[u];
     }
+  }
+  for (; t < T; ++t) {
+    const uint32_t c = cnt[(int64_t)t * B + b];
+    cnt[(int64_t)t * B + b] = run;
+    run += c;
+  }
+  tot[b] = run;
+}
+
+// dense mode, pass 3: scatter (row, k, value) and the in-bin column into
+// the bins; the position inside the bin is an LDS atomic rank
+template <typename VT, bool BATCHED>
+__global__ void k_scatter_dense(const int32_t* __restrict__ ii,
+                                const int32_t* __restrict__ jj,
+                                const VT* __restrict__ ss, int64_t L, int32_t m,
+                                int32_t n, BatchDesc bd, int32_t s, int32_t B,
+                                int32_t TS, const uint32_t* __restrict__ offs,
+                                const int32_t* __restrict__ binstart,
+                                Entry<VT>* __restrict__ bucket,
+                                uint32_t* __restrict__ bcol, Ctrl* ctrl) {
+  extern __shared__ uint32_t ctr[];
+  __shared__ int sB;
+  const int64_t t0 = (int64_t)blockIdx.x * TS;
+  const int64_t t1 = min(L, t0 + TS);
+  const uint32_t* orow = offs + (int64_t)blockIdx.x * B;
+  for (int i = threadIdx.x; i < B; i += blockDim.x)
+    ctr[i] = (uint32_t)binstart[i] + orow[i];
+  int b = tile_first_mat<BATCHED>(bd, t0, L, &sB);
+  __syncthreads();
+  const uint32_t wmask = (1u << s) - 1u;
+  bool badr = false;
+  for (int64_t e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
+    bool ok;
+    int32_t mb;
+    const int64_t g = global_col<BATCHED>(bd, b, e, jj[e] - 1, n, m, mb, ok);
+    if (!ok) continue;  // flagged by the count pass
+    const int32_t r = ii[e] - 1;
     badr |= (uint32_t)r >= (uint32_t)mb;
-    const int32_t p = atomicAdd(&fill[g], 1);
+    const uint32_t p = atomicAdd(&ctr[g >> s], 1u);
     store_entry<VT>(&bucket[p], (uint32_t)r, (uint32_t)e, ss[e]);
+    bcol[p] = (uint32_t)g & wmask;
+  }
+  if (badr) atomicOr(&ctrl->err, kErrRow);
+}
+
+// claim mode: tiles of NT*IPT triplets; bins of the tile live in registers
+template <bool BATCHED, int NT, int IPT>
+__device__ __forceinline__ void tile_bins(const int32_t* __restrict__ jj,
+                                          int64_t L, int32_t n, const BatchDesc& bd,
+                                          int32_t s, int64_t t0, int* sB,
+                                          int32_t (&bn)[IPT], int32_t& lo,
+                                          int32_t& hi, bool& bad) {
+  int b = tile_first_mat<BATCHED>(bd, t0, L, sB);
+  lo = INT32_MAX;
+  hi = -1;
+  int32_t mb;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const int64_t e = t0 + (int64_t)j * NT + threadIdx.x;
+    bn[j] = -1;
+    if (e < L) {
+      bool ok;
+      const int64_t g = global_col<BATCHED>(bd, b, e, jj[e] - 1, n, 0, mb, ok);
+      if (ok) {
+        bn[j] = (int32_t)(g >> s);
+        lo = min(lo, bn[j]);
+        hi = max(hi, bn[j]);
+      } else {
+        bad = true;
+      }
+    }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void block_minmax(int32_t& lo, int32_t& hi,
+                                             int32_t* sLo, int32_t* sHi) {
+  for (int d = 32; d > 0; d >>= 1) {
+    lo = min(lo, __shfl_xor(lo, d, 64));
+    hi = max(hi, __shfl_xor(hi, d, 64));
+  }
+  if (threadIdx.x == 0) {
+    *sLo = INT32_MAX;
+    *sHi = -1;
+  }
+  __syncthreads();
+  if (lane_id() == 0) {
+    atomicMin(sLo, lo);
+    atomicMax(sHi, hi);
+  }
+  __syncthreads();
+  lo = *sLo;
+  hi = *sHi;
+}
+
+template <bool BATCHED, int NT, int IPT>
+__global__ void __launch_bounds__(NT)
+k_count_claim(const int32_t* __restrict__ jj, int64_t L, int32_t n,
+              BatchDesc bd, int32_t s, int32_t WMAX,
+              uint32_t* __restrict__ bincnt, Ctrl* ctrl) {
+  extern __shared__ uint32_t hist[];
+  __shared__ int sB;
+  __shared__ int32_t sLo, sHi;
+  const int64_t t0 = (int64_t)blockIdx.x * NT * IPT;
+  int32_t bn[IPT], lo, hi;
+  bool bad = false;
+  tile_bins<BATCHED, NT, IPT>(jj, L, n, bd, s, t0, &sB, bn, lo, hi, bad);
+  block_minmax<NT>(lo, hi, &sLo, &sHi);
+  if (bad) atomicOr(&ctrl->err, kErrCol);
+  if (hi < lo) return;
+  const int width = hi - lo + 1;
+  if (width <= WMAX) {
+    for (int i = threadIdx.x; i < width; i += NT) hist[i] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+      if (bn[j] >= 0) atomicAdd(&hist[bn[j] - lo], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < width; i += NT)
+      if (hist[i]) atomicAdd(&bincnt[lo + i], hist[i]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+      if (bn[j] >= 0) atomicAdd(&bincnt[bn[j]], 1u);
+  }
+}
+
+template <typename VT, bool BATCHED, int NT, int IPT>
+__global__ void __launch_bounds__(NT)
+k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
+                const VT* __restrict__ ss, int64_t L, int32_t m, int32_t n,
+                BatchDesc bd, int32_t s, int32_t WMAX,
+                const int32_t* __restrict__ binstart,
+                uint32_t* __restrict__ binfill, Entry<VT>* __restrict__ bucket,
+                uint32_t* __restrict__ bcol, Ctrl* ctrl) {
+  extern __shared__ uint32_t hist[];
+  __shared__ int sB;
+  __shared__ int32_t sLo, sHi;
+  const int64_t t0 = (int64_t)blockIdx.x * NT * IPT;
+  int32_t bn[IPT], lo, hi;
+  bool bad = false;
+  tile_bins<BATCHED, NT, IPT>(jj, L, n, bd, s, t0, &sB, bn, lo, hi, bad);
+  block_minmax<NT>(lo, hi, &sLo, &sHi);
+  if (hi < lo) return;
+  const int width = hi - lo + 1;
+  const bool narrow = width <= WMAX;
+  uint32_t rk[IPT];
+  if (narrow) {
+    for (int i = threadIdx.x; i < width; i += NT) hist[i] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+      rk[j] = bn[j] >= 0 ? atomicAdd(&hist[bn[j] - lo], 1u) : 0u;
+    __syncthreads();
+    for (int i = threadIdx.x; i < width; i += NT) {
+      const uint32_t h = hist[i];
+      if (h) hist[i] = (uint32_t)binstart[lo + i] + atomicAdd(&binfill[lo + i], h);
+    }
+    __syncthreads();
+  }
+  const uint32_t wmask = (1u << s) - 1u;
+  int b = BATCHED ? sB : 0;
+  bool badr = false;
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    if (bn[j] < 0) continue;
+    const int64_t e = t0 + (int64_t)j * NT + threadIdx.x;
+    bool ok;
+    int32_t mb;
+    const int64_t g = global_col<BATCHED>(bd, b, e, jj[e] - 1, n, m, mb, ok);
+    const int32_t r = ii[e] - 1;
+    badr |= (uint32_t)r >= (uint32_t)mb;
+    const uint32_t p = narrow ? hist[bn[j] - lo] + rk[j]
+                              : (uint32_t)binstart[bn[j]] + atomicAdd(&binfill[bn[j]], 1u);
+    store_entry<VT>(&bucket[p], (uint32_t)r, (uint32_t)e, ss[e]);
+    bcol[p] = (uint32_t)g & wmask;
   }
   if (badr) atomicOr(&ctrl->err, kErrRow);
 }
@@ -919,8 +1090,214 @@ __device__ int64_t chunk_slow(const ChunkArgs<VT>& a,
   return base;
 }
 
+// ---------------------------------------------------------------------------
+// bin kernel: one workgroup per bin of w consecutive columns
+// ---------------------------------------------------------------------------
+// Fast path: the bin's triplets fit the LDS.  Columns are known per triplet
+// (bcol), so equal (column,row) pairs are grouped by hashing straight away;
+// the distinct rows of each column are ranked, contributions of a pair are
+// put in increasing k and folded from +0.0.  Returns base + distinct count.
 template <typename VT, int CAP, int NT>
-__global__ void __launch_bounds__(NT) k_chunk(ChunkArgs<VT> a) {
+__device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__ bcol,
+                            const ChunkCtx<VT, CAP, NT>& x, int q, int c0, int c1,
+                            int e0, int e1) {
+  constexpr int EPT = CAP / NT;
+  constexpr int H = 2 * CAP;
+  const int tid = threadIdx.x;
+  const int span = e1 - e0;
+  const int wc = c1 - c0;
+  uint32_t* ht = x.ht();
+  uint32_t* row = x.row();
+  uint32_t* col = x.cs();
+  uint32_t* drow = x.cend();
+  uint32_t* cnt = x.cnt();
+  uint32_t* cd = x.cd();
+
+  for (int i = tid; i < H; i += NT) ht[i] = kEmpty;
+  for (int i = tid; i < span; i += NT) cnt[i] = 0u;
+  for (int i = tid; i <= wc; i += NT) cd[i] = 0u;
+  uint32_t kr[EPT];
+  VT vr[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = tid + j * NT;
+    if (i < span) {
+      const Entry<VT> en = load_entry<VT>(&a.bucket[e0 + i]);
+      row[i] = en.row;
+      col[i] = bcol[e0 + i];
+      kr[j] = en.k;
+      vr[j] = en.v;
+    }
+  }
+  __syncthreads();
+
+  // group equal (column,row) pairs
+  uint32_t repa[EPT], dpos[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = tid + j * NT;
+    if (i < span) {
+      const uint32_t c = col[i], r = row[i];
+      uint32_t h = pair_hash(c, r) & (H - 1);
+      uint32_t rep;
+      for (;;) {
+        const uint32_t old = atomicCAS(&ht[h], kEmpty, (uint32_t)i);
+        if (old == kEmpty) { rep = (uint32_t)i; break; }
+        if (col[old] == c && row[old] == r) { rep = old; break; }
+        h = (h + 1) & (H - 1);
+      }
+      const uint32_t arr = atomicAdd(&cnt[rep], 1u);
+      repa[j] = rep | (arr << 16);
+      dpos[j] = (rep == (uint32_t)i) ? atomicAdd(&cd[c], 1u) : kEmpty;
+    }
+  }
+  __syncthreads();
+
+  // distinct pairs per column -> offsets; the bin's output offset
+  const uint32_t D = lds_excl_scan<NT>(cd, wc + 1, x.wave());
+  if (tid < 64) {
+    const int64_t b = lookback(a.status, q, D);
+    if (tid == 0) x.misc()[1] = b;
+  }
+  uint32_t* dlist = x.dlist();
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = tid + j * NT;
+    if (i < span && dpos[j] != kEmpty) {
+      const uint32_t d = cd[col[i]] + dpos[j];
+      dlist[d] = (uint32_t)i;
+      drow[d] = row[i];
+    }
+  }
+  __syncthreads();
+
+  // rank the distinct rows of every column
+  uint32_t* gout = x.gout();
+  uint32_t* gs = x.gs();
+  uint32_t* grow = x.grow();
+  for (int d = tid; d < (int)D; d += NT) {
+    const uint32_t i = dlist[d];
+    const uint32_t c = col[i];
+    const uint32_t r0 = drow[d];
+    const uint32_t lo = cd[c], hi = cd[c + 1];
+    // count smaller rows; eight independent reads in flight per step
+    uint32_t r8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t t = lo;
+    for (; t + 8 <= hi; t += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) r8[u] += drow[t + u] < r0 ? 1u : 0u;
+    }
+    uint32_t rk = ((r8[0] + r8[1]) + (r8[2] + r8[3])) + ((r8[4] + r8[5]) + (r8[6] + r8[7]));
+    for (; t < hi; ++t) rk += drow[t] < r0 ? 1u : 0u;
+    const uint32_t o = lo + rk;
+    gout[i] = o;
+    gs[o] = cnt[i];
+    grow[o] = r0;
+  }
+  if (tid == 0) gs[D] = 0;
+  __syncthreads();
+  lds_excl_scan<NT>(gs, (int)D + 1, x.wave());
+
+  // place triplets into their groups, then order each group by k
+  uint32_t posr[EPT], orr[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = tid + j * NT;
+    if (i < span) {
+      const uint32_t o = gout[repa[j] & 0xFFFFu];
+      orr[j] = o;
+      posr[j] = gs[o] + (repa[j] >> 16);
+    }
+  }
+  __syncthreads();
+  VT* mval = x.mval();
+  uint32_t* mk = row;
+  uint32_t* mgrp = col;
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = tid + j * NT;
+    if (i < span) {
+      mk[posr[j]] = kr[j];
+      mval[posr[j]] = vr[j];
+      mgrp[posr[j]] = orr[j];
+    }
+  }
+  __syncthreads();
+  uint32_t* sidx = cnt;
+  for (int p = tid; p < span; p += NT) {
+    const uint32_t o = mgrp[p];
+    const uint32_t g0 = gs[o], g1 = gs[o + 1];
+    const uint32_t kk = mk[p];
+    uint32_t rk = 0;
+    for (uint32_t t = g0; t < g1; ++t) rk += mk[t] < kk ? 1u : 0u;
+    sidx[g0 + rk] = (uint32_t)p;
+  }
+  __syncthreads();
+
+  // emit
+  const int64_t base = x.misc()[1];
+  if (a.perm)
+    for (int p = tid; p < span; p += NT) a.perm[e0 + p] = (int32_t)mk[sidx[p]];
+  if (a.slot)
+    for (int p = tid; p < span; p += NT) a.slot[mk[p]] = (int32_t)(base + mgrp[p]);
+  bool over = false;
+  for (int o = tid; o < (int)D; o += NT) {
+    const uint32_t g0 = gs[o], g1 = gs[o + 1];
+    VT acc = (VT)0;
+    for (uint32_t t = g0; t < g1; ++t) acc = acc + mval[sidx[t]];
+    const int64_t out = base + o;
+    if (out < a.out_cap) {
+      a.irS[out] = (int32_t)grow[o];
+      a.prS[out] = acc;
+    } else {
+      over = true;
+    }
+    if (a.seg) a.seg[out] = e0 + (int32_t)g0;
+  }
+  if (over) atomicOr(&a.ctrl->err, kErrCap);
+  for (int c = tid; c < wc; c += NT) a.jcS[c0 + c] = (int32_t)(base + cd[c]);
+  return base + D;
+}
+
+// Slow path: the bin holds more triplets than the LDS.  Sort it by column
+// into the scratch array (counting sort in LDS over the bin's columns), write
+// the bin's column pointers, and hand over to the batched / long-column
+// processing, which reads the column-sorted copy.
+template <typename VT, int CAP, int NT>
+__device__ int64_t bin_slow(ChunkArgs<VT> a, const uint32_t* __restrict__ bcol,
+                            int32_t* __restrict__ colptr_g,
+                            const ChunkCtx<VT, CAP, NT>& x, int q, int c0, int c1,
+                            int e0, int e1) {
+  const int tid = threadIdx.x;
+  const int span = e1 - e0;
+  const int wc = c1 - c0;
+  uint32_t* hist = x.cd();  // CAP+1 entries, wc <= CAP
+  for (int i = tid; i <= wc; i += NT) hist[i] = 0u;
+  __syncthreads();
+  for (int i = tid; i < span; i += NT) atomicAdd(&hist[bcol[e0 + i]], 1u);
+  __syncthreads();
+  lds_excl_scan<NT>(hist, wc + 1, x.wave());
+  for (int c = tid; c <= wc; c += NT) colptr_g[c0 + c] = e0 + (int32_t)hist[c];
+  __syncthreads();
+  for (int i = tid; i < span; i += NT) {
+    const uint32_t p = atomicAdd(&hist[bcol[e0 + i]], 1u);
+    const Entry<VT> en = load_entry<VT>(&a.bucket[e0 + i]);
+    store_entry<VT>(&a.tmp[e0 + p], en.row, en.k, en.v);
+  }
+  __threadfence();
+  __syncthreads();
+  a.colptr = colptr_g;
+  Entry<VT>* t = a.bucket;
+  a.bucket = a.tmp;
+  a.tmp = t;
+  return chunk_slow<VT, CAP, NT>(a, x, q, c0, c1);
+}
+
+template <typename VT, int CAP, int NT>
+__global__ void __launch_bounds__(NT)
+k_bin(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
+      const uint32_t* __restrict__ bcol, int32_t* __restrict__ colptr_g,
+      int32_t s, int32_t B) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<CAP>::kBytes];
   ChunkCtx<VT, CAP, NT> x{smem};
   int64_t* misc = x.misc();
@@ -928,28 +1305,15 @@ __global__ void __launch_bounds__(NT) k_chunk(ChunkArgs<VT> a) {
   __syncthreads();
   const int q = (int)misc[0];
   const int N = a.N;
-  const int cbeg = a.chunk_col[q];
-  const int cend = a.chunk_col[q + 1];
-  const int cl = min(cend, N);
-  const bool owns_term = (cbeg <= N) && (N < cend);
-  int e0, e1;
-  if (cbeg >= N) {
-    e0 = e1 = a.colptr[N];
-  } else {
-    e0 = a.colptr[cbeg];
-    e1 = a.colptr[cl];
-  }
+  const int c0 = (int)min((int64_t)N, (int64_t)q << s);
+  const int c1 = (int)min((int64_t)N, ((int64_t)q + 1) << s);
+  const int e0 = binstart[q], e1 = binstart[q + 1];
   int64_t end;
-  if (e1 - e0 <= a.cap) {
-    uint64_t* status = a.status;
-    const uint32_t D = batch<VT, CAP, NT, true>(
-        a, x, cbeg < cl ? cbeg : cl, cl, e0, e1,
-        [status, q](uint32_t d) -> int64_t { return lookback(status, q, d); });
-    end = misc[1] + D;
-  } else {
-    end = chunk_slow<VT, CAP, NT>(a, x, q, cbeg, cl);
-  }
-  if (owns_term && threadIdx.x == 0) {
+  if (e1 - e0 <= a.cap)
+    end = bin_fast<VT, CAP, NT>(a, bcol, x, q, c0, c1, e0, e1);
+  else
+    end = bin_slow<VT, CAP, NT>(a, bcol, colptr_g, x, q, c0, c1, e0, e1);
+  if (q == B - 1 && threadIdx.x == 0) {
     a.jcS[N] = (int32_t)end;
     a.ctrl->nnz = end;
     if (a.seg) a.seg[end] = e1;
