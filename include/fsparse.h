@@ -212,13 +212,16 @@ fsparse_status fsparse_plan_query(const fsparse_plan *plan, int64_t *len,
  * path on small inputs).  stream_block: threads per block of the streaming
  * stages (64..1024, multiple of 64).  stream_items: elements per thread per
  * tile (1..32).  reuse_block: threads per block of the re-assembly kernel.
- * Zero fields keep the current value.  NULL restores the defaults.
+ * chunk_block: threads of one sort/fold workgroup (256, 512 or 1024; at
+ * least chunk_cap/16 are used).  Zero fields keep the current value.  NULL
+ * restores the defaults.
  */
 typedef struct {
   int32_t chunk_cap;
   int32_t stream_block;
   int32_t stream_items;
   int32_t reuse_block;
+  int32_t chunk_block;
 } fsparse_tuning;
 
 fsparse_status fsparse_set_tuning(const fsparse_tuning *t);

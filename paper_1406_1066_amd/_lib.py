@@ -25,7 +25,8 @@ class FsparseInfo(ctypes.Structure):
 class FsparseTuning(ctypes.Structure):
     _fields_ = [("chunk_cap", ctypes.c_int32), ("stream_block", ctypes.c_int32),
                 ("stream_items", ctypes.c_int32),
-                ("reuse_block", ctypes.c_int32)]
+                ("reuse_block", ctypes.c_int32),
+                ("chunk_block", ctypes.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):

@@ -393,11 +393,12 @@ def to_torch_csc(res: Assembled) -> torch.Tensor:
 
 def set_tuning(chunk_cap: int = 0, stream_block: int = 0,
                stream_items: int = 0, reuse_block: int = 0,
-               reset: bool = False):
+               chunk_block: int = 0, reset: bool = False):
     if reset:
         _check(L.fsparse_set_tuning(None), "fsparse_set_tuning")
         return
-    t = L.FsparseTuning(chunk_cap, stream_block, stream_items, reuse_block)
+    t = L.FsparseTuning(chunk_cap, stream_block, stream_items, reuse_block,
+                        chunk_block)
     _check(L.fsparse_set_tuning(ctypes.byref(t)), "fsparse_set_tuning")
 
 
@@ -405,7 +406,8 @@ def get_tuning() -> dict:
     t = L.FsparseTuning()
     _check(L.fsparse_get_tuning(ctypes.byref(t)), "fsparse_get_tuning")
     return {"chunk_cap": t.chunk_cap, "stream_block": t.stream_block,
-            "stream_items": t.stream_items, "reuse_block": t.reuse_block}
+            "stream_items": t.stream_items, "reuse_block": t.reuse_block,
+            "chunk_block": t.chunk_block}
 
 
 class timing:

@@ -18,6 +18,12 @@ using fsp::ChunkArgs;
 using fsp::Ctrl;
 using fsp::Entry;
 
+#ifdef FSP_PHASE_TIMING
+// profiling builds only: device buffer for per-bin phase timestamps
+static uint64_t* g_phase = nullptr;
+extern "C" void fsparse_phase_buffer(void* p) { g_phase = (uint64_t*)p; }
+#endif
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -28,6 +34,7 @@ struct Tuning {
   int sblock = 256;
   int sitems = 8;
   int rblock = 256;
+  int cblock = 256;  // threads of one bin workgroup
 };
 std::mutex g_mu;
 Tuning g_tune;
@@ -432,18 +439,24 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   a.slot = slot;
   a.perm = keep_plan ? at<int32_t>(ws, lo.perm) : nullptr;
   a.seg = keep_plan ? at<int32_t>(ws, lo.seg) : nullptr;
+#ifdef FSP_PHASE_TIMING
+  a.phase = g_phase;
+#endif
   int32_t* colptr_g = at<int32_t>(ws, lo.colptr);
   const int kc = kernel_cap(tu.cap);
+  const int nt = std::max(kc / 16, std::min(tu.cblock, kc));  // <= 16 triplets per thread
   e = launch(kChunk, stream, [&] {
-    if (kc == 1024)
-      hipLaunchKernelGGL((fsp::k_bin<VT, 1024, 256>), dim3((unsigned)B), dim3(256), 0,
-                         stream, a, binstart, bcol, colptr_g, s, B);
-    else if (kc == 2048)
-      hipLaunchKernelGGL((fsp::k_bin<VT, 2048, 256>), dim3((unsigned)B), dim3(256), 0,
-                         stream, a, binstart, bcol, colptr_g, s, B);
-    else
-      hipLaunchKernelGGL((fsp::k_bin<VT, 4096, 512>), dim3((unsigned)B), dim3(512), 0,
-                         stream, a, binstart, bcol, colptr_g, s, B);
+#define FSP_BIN(C, T)                                                          \
+  hipLaunchKernelGGL((fsp::k_bin<VT, C, T>), dim3((unsigned)B), dim3(T), 0,    \
+                     stream, a, binstart, bcol, colptr_g, s, B)
+    if (kc == 1024) {
+      if (nt <= 256) FSP_BIN(1024, 256); else if (nt <= 512) FSP_BIN(1024, 512); else FSP_BIN(1024, 1024);
+    } else if (kc == 2048) {
+      if (nt <= 256) FSP_BIN(2048, 256); else if (nt <= 512) FSP_BIN(2048, 512); else FSP_BIN(2048, 1024);
+    } else {
+      if (nt <= 256) FSP_BIN(4096, 256); else if (nt <= 512) FSP_BIN(4096, 512); else FSP_BIN(4096, 1024);
+    }
+#undef FSP_BIN
   });
   return e;
 }
@@ -911,6 +924,11 @@ fsparse_status fsparse_set_tuning(const fsparse_tuning* t) {
     if (b < 64 || b > 1024 || (b % 64)) return FSPARSE_E_ARG;
     n.rblock = b;
   }
+  if (t->chunk_block) {
+    const int b = t->chunk_block;
+    if (b != 256 && b != 512 && b != 1024) return FSPARSE_E_ARG;
+    n.cblock = b;
+  }
   g_tune = n;
   return FSPARSE_OK;
 }
@@ -922,6 +940,7 @@ fsparse_status fsparse_get_tuning(fsparse_tuning* t) {
   t->stream_block = g_tune.sblock;
   t->stream_items = g_tune.sitems;
   t->reuse_block = g_tune.rblock;
+  t->chunk_block = g_tune.cblock;
   return FSPARSE_OK;
 }
 

@@ -219,6 +219,41 @@ __device__ int64_t lookback(uint64_t* status, int q, uint64_t agg) {
   return excl;
 }
 
+// The two halves of `lookback` for callers that have work to do between
+// publishing their aggregate and needing their prefix.
+__device__ __forceinline__ void lookback_publish(uint64_t* status, int q,
+                                                 uint64_t agg) {
+  if (lane_id() == 0)
+    st_status(&status[q], (q == 0 ? kFlagPrefix : kFlagAgg) | agg);
+}
+
+__device__ int64_t lookback_wait(uint64_t* status, int q, uint64_t agg) {
+  const int lane = lane_id();
+  if (q == 0) return 0;
+  int64_t excl = 0;
+  int pred = q - 1;
+  for (;;) {
+    const int idx = pred - lane;
+    const uint64_t s = (idx >= 0) ? ld_status(&status[idx]) : kFlagPrefix;
+    const uint32_t flag = (uint32_t)(s >> 62);
+    const uint64_t inval = __ballot(flag == 0);
+    const uint64_t pref = __ballot(flag == 2);
+    const int pl = pref ? (__ffsll((unsigned long long)pref) - 1) : 64;
+    const uint64_t need = (pl >= 63) ? ~0ull : ((2ull << pl) - 1ull);
+    if (inval & need) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    uint64_t v = (lane <= pl) ? (s & kValMask) : 0ull;
+    v = wave_incl_sum(v);
+    excl += (int64_t)__shfl(v, 63, 64);
+    if (pl < 64) break;
+    pred -= 64;
+  }
+  if (lane == 0) st_status(&status[q], kFlagPrefix | (uint64_t)(excl + (int64_t)agg));
+  return excl;
+}
+
 __device__ __forceinline__ int find_mat(const int64_t* off, int nb, int64_t e) {
   int lo = 0, hi = nb;
   while (hi - lo > 1) {
@@ -640,7 +675,18 @@ struct ChunkArgs {
   int32_t* slot;             // [Ltot] or null
   int32_t* perm;             // [Ltot] or null: k of the p-th sorted triplet
   int32_t* seg;              // [nnz+1] or null: first sorted position of slot
+  uint64_t* phase;           // per-bin phase timestamps (profiling builds only)
 };
+
+// Phase timestamps of the bin kernel, compiled in only with
+// -DFSP_PHASE_TIMING (16 slots per bin, 100 MHz wall clock).
+#ifdef FSP_PHASE_TIMING
+#define FSP_PHASE(a, q, i)                                          \
+  if ((a).phase && threadIdx.x == 0)                               \
+    (a).phase[(int64_t)(q) * 16 + (i)] = wall_clock64();
+#else
+#define FSP_PHASE(a, q, i)
+#endif
 
 __device__ __forceinline__ uint32_t pair_hash(uint32_t cs, uint32_t row) {
   uint32_t h = cs * 0x9E3779B1u ^ (row + 0x7F4A7C15u) * 0x85EBCA77u;
@@ -827,31 +873,44 @@ __device__ uint32_t batch(const ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x
   __syncthreads();
 
   // P7: order each group's triplets by k (rank by counting)
-  uint32_t* sidx = cnt;
+  // order each group by k: values go straight to their sorted place (the
+  // column-end / count arrays are free by now), so do the k of the plan
+  VT* sval = reinterpret_cast<VT*>(x.cend());
   for (int p = tid; p < span; p += NT) {
     const uint32_t o = mgrp[p];
     const uint32_t g0 = gs[o], g1 = gs[o + 1];
     const uint32_t kk = mk[p];
-    uint32_t rk = 0;
-    for (uint32_t t = g0; t < g1; ++t) rk += mk[t] < kk ? 1u : 0u;
-    sidx[g0 + rk] = (uint32_t)p;
+    uint32_t r4[4] = {0u, 0u, 0u, 0u};
+    uint32_t t = g0;
+    for (; t + 4 <= g1; t += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) r4[u] += mk[t + u] < kk ? 1u : 0u;
+    }
+    uint32_t rk = (r4[0] + r4[1]) + (r4[2] + r4[3]);
+    for (; t < g1; ++t) rk += mk[t] < kk ? 1u : 0u;
+    sval[g0 + rk] = mval[p];
+    if (a.perm) a.perm[e0 + g0 + rk] = (int32_t)kk;
   }
   __syncthreads();
 
   // P8: emit
   const int64_t base = x.misc()[1];
-  if (a.perm)
-    for (int p = tid; p < span; p += NT) a.perm[e0 + p] = (int32_t)mk[sidx[p]];
   if (a.slot)
-    for (int p = tid; p < span; p += NT) {
-      const uint32_t q = sidx[p];
-      a.slot[mk[q]] = (int32_t)(base + mgrp[q]);
-    }
+    for (int p = tid; p < span; p += NT) a.slot[mk[p]] = (int32_t)(base + mgrp[p]);
   bool over = false;
   for (int o = tid; o < (int)D; o += NT) {
     const uint32_t g0 = gs[o], g1 = gs[o + 1];
+    // left fold from +0.0 in increasing k; loads four ahead
     VT acc = (VT)0;
-    for (uint32_t t = g0; t < g1; ++t) acc = acc + mval[sidx[t]];
+    uint32_t t = g0;
+    for (; t + 4 <= g1; t += 4) {
+      const VT v0 = sval[t], v1 = sval[t + 1], v2 = sval[t + 2], v3 = sval[t + 3];
+      acc = acc + v0;
+      acc = acc + v1;
+      acc = acc + v2;
+      acc = acc + v3;
+    }
+    for (; t < g1; ++t) acc = acc + sval[t];
     const int64_t out = base + o;
     if (out < a.out_cap) {
       a.irS[out] = (int32_t)grow[o];
@@ -1106,6 +1165,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
   const int tid = threadIdx.x;
   const int span = e1 - e0;
   const int wc = c1 - c0;
+  FSP_PHASE(a, q, 1)
   uint32_t* ht = x.ht();
   uint32_t* row = x.row();
   uint32_t* col = x.cs();
@@ -1131,6 +1191,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
   }
   __syncthreads();
 
+  FSP_PHASE(a, q, 2)
   // group equal (column,row) pairs
   uint32_t repa[EPT], dpos[EPT];
 #pragma unroll
@@ -1153,12 +1214,11 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
   }
   __syncthreads();
 
-  // distinct pairs per column -> offsets; the bin's output offset
+  FSP_PHASE(a, q, 3)
+  // distinct pairs per column -> offsets; publish the bin's count now, read
+  // the prefix of the earlier bins only when emitting
   const uint32_t D = lds_excl_scan<NT>(cd, wc + 1, x.wave());
-  if (tid < 64) {
-    const int64_t b = lookback(a.status, q, D);
-    if (tid == 0) x.misc()[1] = b;
-  }
+  if (tid < 64) lookback_publish(a.status, q, D);
   uint32_t* dlist = x.dlist();
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
@@ -1171,6 +1231,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
   }
   __syncthreads();
 
+  FSP_PHASE(a, q, 4)
   // rank the distinct rows of every column
   uint32_t* gout = x.gout();
   uint32_t* gs = x.gs();
@@ -1196,7 +1257,9 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
   }
   if (tid == 0) gs[D] = 0;
   __syncthreads();
+  FSP_PHASE(a, q, 5)
   lds_excl_scan<NT>(gs, (int)D + 1, x.wave());
+  FSP_PHASE(a, q, 6)
 
   // place triplets into their groups, then order each group by k
   uint32_t posr[EPT], orr[EPT];
@@ -1223,28 +1286,50 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
     }
   }
   __syncthreads();
-  uint32_t* sidx = cnt;
+  // order each group by k: values go straight to their sorted place (the
+  // column-end / count arrays are free by now), so do the k of the plan
+  VT* sval = reinterpret_cast<VT*>(x.cend());
   for (int p = tid; p < span; p += NT) {
     const uint32_t o = mgrp[p];
     const uint32_t g0 = gs[o], g1 = gs[o + 1];
     const uint32_t kk = mk[p];
-    uint32_t rk = 0;
-    for (uint32_t t = g0; t < g1; ++t) rk += mk[t] < kk ? 1u : 0u;
-    sidx[g0 + rk] = (uint32_t)p;
+    uint32_t r4[4] = {0u, 0u, 0u, 0u};
+    uint32_t t = g0;
+    for (; t + 4 <= g1; t += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) r4[u] += mk[t + u] < kk ? 1u : 0u;
+    }
+    uint32_t rk = (r4[0] + r4[1]) + (r4[2] + r4[3]);
+    for (; t < g1; ++t) rk += mk[t] < kk ? 1u : 0u;
+    sval[g0 + rk] = mval[p];
+    if (a.perm) a.perm[e0 + g0 + rk] = (int32_t)kk;
+  }
+  FSP_PHASE(a, q, 7)
+  if (tid < 64) {
+    const int64_t b = lookback_wait(a.status, q, D);
+    if (tid == 0) x.misc()[1] = b;
   }
   __syncthreads();
+  FSP_PHASE(a, q, 9)
 
   // emit
   const int64_t base = x.misc()[1];
-  if (a.perm)
-    for (int p = tid; p < span; p += NT) a.perm[e0 + p] = (int32_t)mk[sidx[p]];
   if (a.slot)
     for (int p = tid; p < span; p += NT) a.slot[mk[p]] = (int32_t)(base + mgrp[p]);
   bool over = false;
   for (int o = tid; o < (int)D; o += NT) {
     const uint32_t g0 = gs[o], g1 = gs[o + 1];
+    // left fold from +0.0 in increasing k; loads four ahead
     VT acc = (VT)0;
-    for (uint32_t t = g0; t < g1; ++t) acc = acc + mval[sidx[t]];
+    uint32_t t = g0;
+    for (; t + 4 <= g1; t += 4) {
+      const VT v0 = sval[t], v1 = sval[t + 1], v2 = sval[t + 2], v3 = sval[t + 3];
+      acc = acc + v0;
+      acc = acc + v1;
+      acc = acc + v2;
+      acc = acc + v3;
+    }
+    for (; t < g1; ++t) acc = acc + sval[t];
     const int64_t out = base + o;
     if (out < a.out_cap) {
       a.irS[out] = (int32_t)grow[o];
@@ -1256,6 +1341,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
   }
   if (over) atomicOr(&a.ctrl->err, kErrCap);
   for (int c = tid; c < wc; c += NT) a.jcS[c0 + c] = (int32_t)(base + cd[c]);
+  FSP_PHASE(a, q, 8)
   return base + D;
 }
 
@@ -1301,9 +1387,15 @@ k_bin(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
   __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<CAP>::kBytes];
   ChunkCtx<VT, CAP, NT> x{smem};
   int64_t* misc = x.misc();
+#ifdef FSP_PHASE_TIMING
+  const uint64_t tstart = wall_clock64();
+#endif
   if (threadIdx.x == 0) misc[0] = (int64_t)atomicAdd(&a.ctrl->tick_chunk, 1u);
   __syncthreads();
   const int q = (int)misc[0];
+#ifdef FSP_PHASE_TIMING
+  if (a.phase && threadIdx.x == 0) a.phase[(int64_t)q * 16] = tstart;
+#endif
   const int N = a.N;
   const int c0 = (int)min((int64_t)N, (int64_t)q << s);
   const int c1 = (int)min((int64_t)N, ((int64_t)q + 1) << s);
