@@ -213,8 +213,12 @@ fsparse_status fsparse_plan_query(const fsparse_plan *plan, int64_t *len,
  * stages (64..1024, multiple of 64).  stream_items: elements per thread per
  * tile (1..32).  reuse_block: threads per block of the re-assembly kernel.
  * chunk_block: threads of one sort/fold workgroup (256, 512 or 1024; at
- * least chunk_cap/16 are used).  Zero fields keep the current value.  NULL
- * restores the defaults.
+ * least chunk_cap/16 are used).  Zero fields keep the current value.
+ * bin_mode chooses how triplets are placed into column bins: 0 automatic,
+ * 1 per-tile count matrix (only while the bins fit the LDS counters),
+ * 2 fixed-capacity bins filled in one pass, 3 count then place; it is
+ * always applied (0 restores the automatic choice).  NULL restores all
+ * defaults.
  */
 typedef struct {
   int32_t chunk_cap;
@@ -222,6 +226,7 @@ typedef struct {
   int32_t stream_items;
   int32_t reuse_block;
   int32_t chunk_block;
+  int32_t bin_mode;
 } fsparse_tuning;
 
 fsparse_status fsparse_set_tuning(const fsparse_tuning *t);

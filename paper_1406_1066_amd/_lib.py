@@ -26,7 +26,8 @@ class FsparseTuning(ctypes.Structure):
     _fields_ = [("chunk_cap", ctypes.c_int32), ("stream_block", ctypes.c_int32),
                 ("stream_items", ctypes.c_int32),
                 ("reuse_block", ctypes.c_int32),
-                ("chunk_block", ctypes.c_int32)]
+                ("chunk_block", ctypes.c_int32),
+                ("bin_mode", ctypes.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):

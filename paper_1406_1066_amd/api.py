@@ -391,14 +391,24 @@ def to_torch_csc(res: Assembled) -> torch.Tensor:
                                    size=(res.m, res.n))
 
 
+BIN_MODES = {"auto": 0, "dense": 1, "slot": 2, "claim": 3}
+
+
 def set_tuning(chunk_cap: int = 0, stream_block: int = 0,
                stream_items: int = 0, reuse_block: int = 0,
-               chunk_block: int = 0, reset: bool = False):
+               chunk_block: int = 0, bin_mode=None, reset: bool = False):
+    """Launch-shape tuning (process-wide); zero / None keeps a field.
+
+    ``bin_mode``: "auto", "dense", "slot" or "claim" (see fsparse.h)."""
     if reset:
         _check(L.fsparse_set_tuning(None), "fsparse_set_tuning")
         return
+    if bin_mode is None:
+        bm = get_tuning()["bin_mode"]
+    else:
+        bm = BIN_MODES[bin_mode] if isinstance(bin_mode, str) else int(bin_mode)
     t = L.FsparseTuning(chunk_cap, stream_block, stream_items, reuse_block,
-                        chunk_block)
+                        chunk_block, bm)
     _check(L.fsparse_set_tuning(ctypes.byref(t)), "fsparse_set_tuning")
 
 
@@ -407,7 +417,7 @@ def get_tuning() -> dict:
     _check(L.fsparse_get_tuning(ctypes.byref(t)), "fsparse_get_tuning")
     return {"chunk_cap": t.chunk_cap, "stream_block": t.stream_block,
             "stream_items": t.stream_items, "reuse_block": t.reuse_block,
-            "chunk_block": t.chunk_block}
+            "chunk_block": t.chunk_block, "bin_mode": t.bin_mode}
 
 
 class timing:

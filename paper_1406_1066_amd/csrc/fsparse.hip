@@ -35,6 +35,7 @@ struct Tuning {
   int sitems = 8;
   int rblock = 256;
   int cblock = 256;  // threads of one bin workgroup
+  int bmode = 0;     // 0 automatic, else 1 + BinMode to force one
 };
 std::mutex g_mu;
 Tuning g_tune;
@@ -152,13 +153,18 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Column bins: w = 2^s columns per bin, sized so that an average bin holds
 // about half the sort stage's LDS capacity.
+enum BinMode { kDense = 0, kSlot = 1, kClaim = 2 };
+
 struct Geom {
   int s;
   int64_t w, B, TS, T;
   bool dense;
+  int mode;         // BinMode
+  int64_t slotcap;  // fixed bin capacity of the slot mode
+  int64_t nslot;    // bucket places of the slot mode
 };
 
-Geom make_geom(int64_t L, int64_t N, int cap) {
+Geom make_geom(int64_t L, int64_t N, int cap, int force_mode) {
   Geom g{};
   int64_t w = 1;
   if (L > 0) {
@@ -177,11 +183,22 @@ Geom make_geom(int64_t L, int64_t N, int cap) {
     g.TS = (int64_t)kClaimNT * kClaimIPT;
   }
   g.T = std::max<int64_t>(1, (L + g.TS - 1) / g.TS);
+  // many bins: give every bin a fixed place of `cap` triplets so one pass
+  // (claims per tile and bin) places the triplets; an overflowing bin makes
+  // the call fall back to counting first (kClaim)
+  g.slotcap = cap;
+  g.mode = g.dense ? kDense
+                   : (g.B * (int64_t)cap < (int64_t(1) << 31) ? kSlot : kClaim);
+  if (force_mode == 1 + kDense && g.dense) g.mode = kDense;
+  if (force_mode == 1 + kSlot && g.B * (int64_t)cap < (int64_t(1) << 31)) g.mode = kSlot;
+  if (force_mode == 1 + kClaim) g.mode = kClaim;
+  g.nslot = g.mode == kSlot ? g.B * (int64_t)cap : 0;
   return g;
 }
 
 struct Layout {
   Geom g;
+  int64_t mmax;  // largest m over the matrices (batched)
   size_t ctrl, scan_st, bin_st, bincnt, binfill, bmax, zero_end;
   size_t binstart, cntmat, bcol, colptr, bucket, tmp, perm, seg, islot;
   size_t b_trip, b_col, b_m, b_n, jcg, nnzoff;
@@ -189,9 +206,9 @@ struct Layout {
   int64_t nscan;
 };
 
-Layout make_layout(int64_t L, int64_t N, int nb, int esize, int cap) {
+Layout make_layout(int64_t L, int64_t N, int nb, int esize, const Tuning& tu) {
   Layout o{};
-  o.g = make_geom(L, N, cap);
+  o.g = make_geom(L, N, tu.cap, tu.bmode);
   const int64_t B = o.g.B;
   o.nscan = (B + 1 + kScanTile - 1) / kScanTile;
   size_t p = 0;
@@ -204,9 +221,10 @@ Layout make_layout(int64_t L, int64_t N, int nb, int esize, int cap) {
   o.zero_end = p;
   o.binstart = p;    p = al(p + 4 * (size_t)(B + 1));
   o.cntmat = p;      p = al(p + (o.g.dense ? 4 * (size_t)o.g.T * B : 0));
-  o.bcol = p;        p = al(p + 4 * (size_t)L);
+  const int64_t nb_places = std::max(L, o.g.nslot);
+  o.bcol = p;        p = al(p + 4 * (size_t)nb_places);
   o.colptr = p;      p = al(p + 4 * (size_t)(N + 1));
-  o.bucket = p;      p = al(p + (size_t)esize * L);
+  o.bucket = p;      p = al(p + (size_t)esize * nb_places);
   o.tmp = p;         p = al(p + (size_t)esize * L);
   o.perm = p;        p = al(p + 4 * (size_t)L);
   o.seg = p;         p = al(p + 4 * (size_t)(L + 1));
@@ -362,7 +380,7 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
                         int64_t N, const Layout& lo, const Tuning& tu,
                         void* ws, int32_t* jcS_target, int32_t* irS, VT* prS,
                         int64_t cap, int32_t* slot, bool keep_plan,
-                        hipStream_t stream) {
+                        int mode, hipStream_t stream) {
   const Geom& g = lo.g;
   Ctrl* ctrl = at<Ctrl>(ws, lo.ctrl);
   hipError_t e;
@@ -380,9 +398,14 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   Entry<VT>* bucket = at<Entry<VT>>(ws, lo.bucket);
   const int s = g.s, B = (int)g.B;
   const int blk = tu.sblock;
-  // 1. bin counts
-  e = launch(kHist, stream, [&] {
-    if (g.dense)
+  // rows and in-bin columns share one word when (m << s) fits 32 bits
+  int64_t mmax = m;
+  if (BATCHED) mmax = lo.mmax;
+  const int packed = (mmax <= (int64_t(1) << (32 - s))) ? 1 : 0;
+  const int32_t slotcap = mode == kSlot ? (int32_t)g.slotcap : 0;
+  // 1. bin counts (the slot mode has none)
+  if (mode != kSlot) e = launch(kHist, stream, [&] {
+    if (mode == kDense)
       hipLaunchKernelGGL(fsp::k_count_dense<BATCHED>, dim3((unsigned)g.T), dim3(blk),
                          (size_t)B * 4, stream, jj, L, n, bd, s, B, (int32_t)g.TS,
                          cntmat, ctrl);
@@ -393,7 +416,7 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
                          kClaimWindow, bincnt, ctrl);
   });
   if (e != hipSuccess) return e;
-  if (g.dense) {
+  if (mode == kDense) {
     e = launch(kColScan, stream, [&] {
       hipLaunchKernelGGL(fsp::k_colscan, dim3((unsigned)((B + 255) / 256)), dim3(256),
                          0, stream, cntmat, (int32_t)g.T, B, bincnt);
@@ -401,7 +424,7 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
     if (e != hipSuccess) return e;
   }
   // 2. bin pointers
-  e = launch(kScan, stream, [&] {
+  if (mode != kSlot) e = launch(kScan, stream, [&] {
     hipLaunchKernelGGL((fsp::k_scan_excl<kScanNT, kScanIPT>), dim3((unsigned)lo.nscan),
                        dim3(kScanNT), 0, stream, bincnt, B, binstart,
                        at<uint64_t>(ws, lo.scan_st), &ctrl->tick_scan);
@@ -409,15 +432,17 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   if (e != hipSuccess) return e;
   // 3. scatter into the bins
   e = launch(kBucket, stream, [&] {
-    if (g.dense)
+    if (mode == kDense)
       hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED>), dim3((unsigned)g.T),
                          dim3(blk), (size_t)B * 4, stream, ii, jj, ss, L, m, n, bd,
-                         s, B, (int32_t)g.TS, cntmat, binstart, bucket, bcol, ctrl);
+                         s, B, (int32_t)g.TS, cntmat, binstart, bucket, bcol, packed,
+                         ctrl);
     else
       hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, kClaimNT, kClaimIPT>),
                          dim3((unsigned)g.T), dim3(kClaimNT),
                          (size_t)kClaimWindow * 4, stream, ii, jj, ss, L, m, n, bd,
-                         s, kClaimWindow, binstart, binfill, bucket, bcol, ctrl);
+                         s, kClaimWindow, binstart, slotcap, binfill, bucket, bcol,
+                         packed, ctrl);
   });
   if (e != hipSuccess) return e;
   // 4. one workgroup per bin: group, rank, order, fold, emit
@@ -442,13 +467,15 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
 #ifdef FSP_PHASE_TIMING
   a.phase = g_phase;
 #endif
+  a.rshift = packed ? s : 0;
+  const uint32_t* bcol_in = packed ? nullptr : bcol;
   int32_t* colptr_g = at<int32_t>(ws, lo.colptr);
   const int kc = kernel_cap(tu.cap);
   const int nt = std::max(kc / 16, std::min(tu.cblock, kc));  // <= 16 triplets per thread
   e = launch(kChunk, stream, [&] {
 #define FSP_BIN(C, T)                                                          \
   hipLaunchKernelGGL((fsp::k_bin<VT, C, T>), dim3((unsigned)B), dim3(T), 0,    \
-                     stream, a, binstart, bcol, colptr_g, s, B)
+                     stream, a, binstart, binfill, slotcap, bcol_in, colptr_g, s, B)
     if (kc == 1024) {
       if (nt <= 256) FSP_BIN(1024, 256); else if (nt <= 512) FSP_BIN(1024, 512); else FSP_BIN(1024, 1024);
     } else if (kc == 2048) {
@@ -471,10 +498,10 @@ constexpr int64_t kMaxI32 = 0x7FFFFFFE;
 // call).  ws needs the small-table layout of make_layout(0, 0, nb, ...).
 fsparse_status batched_dims(int32_t nb, const int64_t* trip_off,
                             const int32_t* ii, const int32_t* jj, int64_t L,
-                            fsparse_dtype dt, int cap, void* ws,
+                            fsparse_dtype dt, const Tuning& tu, void* ws,
                             size_t ws_bytes, int64_t* mm, int64_t* nn,
                             hipStream_t stream) {
-  Layout pre = make_layout(0, 0, nb, esize_of(dt), cap);
+  Layout pre = make_layout(0, 0, nb, esize_of(dt), tu);
   if (ws_bytes < pre.total) return FSPARSE_E_CAPACITY;
   Ctrl* hi = static_cast<Ctrl*>(pinned());
   if (!hi || sizeof(Ctrl) + 8 * (size_t)nb > kPinnedBytes) return FSPARSE_E_ARG;
@@ -531,7 +558,7 @@ const char* fsparse_status_string(int s) {
 size_t fsparse_workspace_bytes(int64_t len, int64_t ncols, int32_t nb,
                                fsparse_dtype dt) {
   if (len < 0 || ncols < 0 || nb < 1 || check_dt(dt) != FSPARSE_OK) return 0;
-  return make_layout(len, ncols, nb, esize_of(dt), tuning().cap).total;
+  return make_layout(len, ncols, nb, esize_of(dt), tuning()).total;
 }
 
 fsparse_status fsparse_dims(const int32_t* ii, const int32_t* jj, int64_t len,
@@ -594,7 +621,7 @@ fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
   }
   if (jcS_cap < n + 1) return FSPARSE_E_CAPACITY;
   const Tuning tu = tuning();
-  const Layout lo = make_layout(len, n, 1, esize_of(dt), tu.cap);
+  const Layout lo = make_layout(len, n, 1, esize_of(dt), tu);
   if (ws_bytes < lo.total) return FSPARSE_E_CAPACITY;
   Ctrl* ctrl = at<Ctrl>(ws, lo.ctrl);
   const bool keep = plan != nullptr;
@@ -608,20 +635,31 @@ fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
     HIPCHK(hipStreamSynchronize(stream));
   } else {
     BatchDesc bd{};
-    hipError_t e;
-    if (dt == FSPARSE_F64)
-      e = run_pipeline<double, false>(ii, jj, (const double*)ss, len, (int32_t)m,
-                                      (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
-                                      (double*)prS, cap, slot_used, keep, stream);
-    else
-      e = run_pipeline<float, false>(ii, jj, (const float*)ss, len, (int32_t)m,
-                                     (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
-                                     (float*)prS, cap, slot_used, keep, stream);
-    if (e != hipSuccess) return FSPARSE_E_HIP;
     Ctrl* h = static_cast<Ctrl*>(pinned());
     if (!h) return FSPARSE_E_HIP;
-    HIPCHK(hipMemcpyAsync(h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
+    int mode = lo.g.mode;
+    for (;;) {
+      hipError_t e;
+      if (dt == FSPARSE_F64)
+        e = run_pipeline<double, false>(ii, jj, (const double*)ss, len, (int32_t)m,
+                                        (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
+                                        (double*)prS, cap, slot_used, keep, mode,
+                                        stream);
+      else
+        e = run_pipeline<float, false>(ii, jj, (const float*)ss, len, (int32_t)m,
+                                       (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
+                                       (float*)prS, cap, slot_used, keep, mode,
+                                       stream);
+      if (e != hipSuccess) return FSPARSE_E_HIP;
+      HIPCHK(hipMemcpyAsync(h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      // a full fixed-capacity bin: count first and redo
+      if ((h->err & fsp::kErrSlot) && mode == kSlot) {
+        mode = kClaim;
+        continue;
+      }
+      break;
+    }
     const uint32_t err = h->err;
     const int64_t nnz = h->nnz;
     if (info) {
@@ -733,7 +771,7 @@ fsparse_status fsparse_assemble_batched(
   // worst-case layout for the dims pass: tables must fit before N is known
   if (ws_bytes < 4096) return FSPARSE_E_CAPACITY;
   if (need_dims && L > 0) {
-    fsparse_status st = batched_dims(nb, trip_off, ii, jj, L, dt, tu.cap, ws,
+    fsparse_status st = batched_dims(nb, trip_off, ii, jj, L, dt, tu, ws,
                                      ws_bytes, mm.data(), nn.data(), stream);
     if (st != FSPARSE_OK) return st;
   }
@@ -752,8 +790,10 @@ fsparse_status fsparse_assemble_batched(
       info[b].nzmax = 0;
     }
   if (jcS_cap < N + nb) return FSPARSE_E_CAPACITY;
-  const Layout lo = make_layout(L, N, nb, esize_of(dt), tu.cap);
+  Layout lo = make_layout(L, N, nb, esize_of(dt), tu);
   if (ws_bytes < lo.total) return FSPARSE_E_CAPACITY;
+  lo.mmax = 0;
+  for (int b = 0; b < nb; ++b) lo.mmax = std::max(lo.mmax, mm[b]);
   std::vector<int32_t> m32(nb), n32(nb);
   for (int b = 0; b < nb; ++b) {
     m32[b] = (int32_t)mm[b];
@@ -792,30 +832,38 @@ fsparse_status fsparse_assemble_batched(
     }
     return FSPARSE_OK;
   }
-  if (dt == FSPARSE_F64)
-    e = run_pipeline<double, true>(ii, jj, (const double*)ss, L, 0, 0, bd, N, lo, tu,
-                                   ws, jcg, irS, (double*)prS, cap, slot_used, keep,
-                                   stream);
-  else
-    e = run_pipeline<float, true>(ii, jj, (const float*)ss, L, 0, 0, bd, N, lo, tu,
-                                  ws, jcg, irS, (float*)prS, cap, slot_used, keep,
-                                  stream);
-  if (e != hipSuccess) return FSPARSE_E_HIP;
-  if (nb > 1) {
-    e = launch(kBatchedJcs, stream, [&] {
-      hipLaunchKernelGGL(fsp::k_batched_jcs, dim3(grid_for(N + nb, 256, 4)),
-                         dim3(256), 0, stream, jcg, at<int64_t>(ws, lo.b_col), nb,
-                         (int64_t)(N + nb), jcS, dnnz);
-    });
-    if (e != hipSuccess) return FSPARSE_E_HIP;
-  }
   char* h = static_cast<char*>(pinned());
   if (!h || sizeof(Ctrl) + 8 * (size_t)(nb + 1) > kPinnedBytes) return FSPARSE_E_ARG;
-  HIPCHK(hipMemcpyAsync(h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
-  if (nb > 1)
-    HIPCHK(hipMemcpyAsync(h + sizeof(Ctrl), dnnz, 8 * (size_t)(nb + 1),
-                          hipMemcpyDeviceToHost, stream));
-  HIPCHK(hipStreamSynchronize(stream));
+  int mode = lo.g.mode;
+  for (;;) {
+    if (dt == FSPARSE_F64)
+      e = run_pipeline<double, true>(ii, jj, (const double*)ss, L, 0, 0, bd, N, lo,
+                                     tu, ws, jcg, irS, (double*)prS, cap, slot_used,
+                                     keep, mode, stream);
+    else
+      e = run_pipeline<float, true>(ii, jj, (const float*)ss, L, 0, 0, bd, N, lo, tu,
+                                    ws, jcg, irS, (float*)prS, cap, slot_used, keep,
+                                    mode, stream);
+    if (e != hipSuccess) return FSPARSE_E_HIP;
+    if (nb > 1) {
+      e = launch(kBatchedJcs, stream, [&] {
+        hipLaunchKernelGGL(fsp::k_batched_jcs, dim3(grid_for(N + nb, 256, 4)),
+                           dim3(256), 0, stream, jcg, at<int64_t>(ws, lo.b_col), nb,
+                           (int64_t)(N + nb), jcS, dnnz);
+      });
+      if (e != hipSuccess) return FSPARSE_E_HIP;
+    }
+    HIPCHK(hipMemcpyAsync(h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+    if (nb > 1)
+      HIPCHK(hipMemcpyAsync(h + sizeof(Ctrl), dnnz, 8 * (size_t)(nb + 1),
+                            hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if ((reinterpret_cast<const Ctrl*>(h)->err & fsp::kErrSlot) && mode == kSlot) {
+      mode = kClaim;  // a full fixed-capacity bin: count first and redo
+      continue;
+    }
+    break;
+  }
   const Ctrl* hc = reinterpret_cast<const Ctrl*>(h);
   const int64_t nnz = hc->nnz;
   if (nb > 1) {
@@ -870,7 +918,7 @@ fsparse_status fsparse_dims_batched(int32_t nb, const int64_t* trip_off,
   }
   if (L > 0) {
     fsparse_status st = batched_dims(nb, trip_off, ii, jj, L, FSPARSE_F64,
-                                     tuning().cap, ws, ws_bytes, m, n, stream);
+                                     tuning(), ws, ws_bytes, m, n, stream);
     if (st != FSPARSE_OK) return st;
   }
   for (int b = 0; b < nb; ++b) {
@@ -929,6 +977,8 @@ fsparse_status fsparse_set_tuning(const fsparse_tuning* t) {
     if (b != 256 && b != 512 && b != 1024) return FSPARSE_E_ARG;
     n.cblock = b;
   }
+  if (t->bin_mode < 0 || t->bin_mode > 3) return FSPARSE_E_ARG;
+  n.bmode = t->bin_mode;
   g_tune = n;
   return FSPARSE_OK;
 }
@@ -941,6 +991,7 @@ fsparse_status fsparse_get_tuning(fsparse_tuning* t) {
   t->stream_items = g_tune.sitems;
   t->reuse_block = g_tune.rblock;
   t->chunk_block = g_tune.cblock;
+  t->bin_mode = g_tune.bmode;
   return FSPARSE_OK;
 }
 

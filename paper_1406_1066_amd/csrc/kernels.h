@@ -33,6 +33,7 @@ constexpr uint64_t kValMask = (1ull << 62) - 1;
 constexpr uint32_t kErrCol = 1u;
 constexpr uint32_t kErrRow = 2u;
 constexpr uint32_t kErrCap = 4u;
+constexpr uint32_t kErrSlot = 8u;  // a fixed-capacity bin overflowed: redo in two passes
 
 // Control block at the start of the workspace (zeroed before every call).
 struct Ctrl {
@@ -492,7 +493,8 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
                                 int32_t TS, const uint32_t* __restrict__ offs,
                                 const int32_t* __restrict__ binstart,
                                 Entry<VT>* __restrict__ bucket,
-                                uint32_t* __restrict__ bcol, Ctrl* ctrl) {
+                                uint32_t* __restrict__ bcol, int packed,
+                                Ctrl* ctrl) {
   extern __shared__ uint32_t ctr[];
   __shared__ int sB;
   const int64_t t0 = (int64_t)blockIdx.x * TS;
@@ -512,8 +514,13 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
     const int32_t r = ii[e] - 1;
     badr |= (uint32_t)r >= (uint32_t)mb;
     const uint32_t p = atomicAdd(&ctr[g >> s], 1u);
-    store_entry<VT>(&bucket[p], (uint32_t)r, (uint32_t)e, ss[e]);
-    bcol[p] = (uint32_t)g & wmask;
+    if (packed) {
+      store_entry<VT>(&bucket[p], ((uint32_t)r << s) | ((uint32_t)g & wmask),
+                      (uint32_t)e, ss[e]);
+    } else {
+      store_entry<VT>(&bucket[p], (uint32_t)r, (uint32_t)e, ss[e]);
+      bcol[p] = (uint32_t)g & wmask;
+    }
   }
   if (badr) atomicOr(&ctrl->err, kErrRow);
 }
@@ -605,9 +612,9 @@ __global__ void __launch_bounds__(NT)
 k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
                 const VT* __restrict__ ss, int64_t L, int32_t m, int32_t n,
                 BatchDesc bd, int32_t s, int32_t WMAX,
-                const int32_t* __restrict__ binstart,
+                const int32_t* __restrict__ binstart, int32_t slotcap,
                 uint32_t* __restrict__ binfill, Entry<VT>* __restrict__ bucket,
-                uint32_t* __restrict__ bcol, Ctrl* ctrl) {
+                uint32_t* __restrict__ bcol, int packed, Ctrl* ctrl) {
   extern __shared__ uint32_t hist[];
   __shared__ int sB;
   __shared__ int32_t sLo, sHi;
@@ -629,13 +636,17 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
     __syncthreads();
     for (int i = threadIdx.x; i < width; i += NT) {
       const uint32_t h = hist[i];
-      if (h) hist[i] = (uint32_t)binstart[lo + i] + atomicAdd(&binfill[lo + i], h);
+      if (h) {
+        const uint32_t c = atomicAdd(&binfill[lo + i], h);
+        hist[i] = (slotcap > 0 ? (uint32_t)(lo + i) * (uint32_t)slotcap
+                               : (uint32_t)binstart[lo + i]) + c;
+      }
     }
     __syncthreads();
   }
   const uint32_t wmask = (1u << s) - 1u;
   int b = BATCHED ? sB : 0;
-  bool badr = false;
+  bool badr = false, over = false;
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     if (bn[j] < 0) continue;
@@ -645,12 +656,27 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
     const int64_t g = global_col<BATCHED>(bd, b, e, jj[e] - 1, n, m, mb, ok);
     const int32_t r = ii[e] - 1;
     badr |= (uint32_t)r >= (uint32_t)mb;
-    const uint32_t p = narrow ? hist[bn[j] - lo] + rk[j]
-                              : (uint32_t)binstart[bn[j]] + atomicAdd(&binfill[bn[j]], 1u);
-    store_entry<VT>(&bucket[p], (uint32_t)r, (uint32_t)e, ss[e]);
-    bcol[p] = (uint32_t)g & wmask;
+    uint32_t p;
+    if (narrow) {
+      p = hist[bn[j] - lo] + rk[j];
+    } else {
+      const uint32_t c = atomicAdd(&binfill[bn[j]], 1u);
+      p = (slotcap > 0 ? (uint32_t)bn[j] * (uint32_t)slotcap : (uint32_t)binstart[bn[j]]) + c;
+    }
+    if (slotcap > 0 && p - (uint32_t)bn[j] * (uint32_t)slotcap >= (uint32_t)slotcap) {
+      over = true;  // this bin is full: the call is redone in two passes
+      continue;
+    }
+    if (packed) {
+      store_entry<VT>(&bucket[p], ((uint32_t)r << s) | ((uint32_t)g & wmask),
+                      (uint32_t)e, ss[e]);
+    } else {
+      store_entry<VT>(&bucket[p], (uint32_t)r, (uint32_t)e, ss[e]);
+      bcol[p] = (uint32_t)g & wmask;
+    }
   }
   if (badr) atomicOr(&ctrl->err, kErrRow);
+  if (over) atomicOr(&ctrl->err, kErrSlot);
 }
 
 // ---------------------------------------------------------------------------
@@ -676,7 +702,16 @@ struct ChunkArgs {
   int32_t* perm;             // [Ltot] or null: k of the p-th sorted triplet
   int32_t* seg;              // [nnz+1] or null: first sorted position of slot
   uint64_t* phase;           // per-bin phase timestamps (profiling builds only)
+  int32_t rshift;            // rows are stored as (row << rshift) | column
+  int64_t pshift;            // compact triplet position = bucket position + pshift
 };
+
+// Look-back words of the bin kernel carry two running sums at once: the
+// distinct pairs (low 31 bits) and the binned triplets (next 31 bits).
+constexpr uint64_t kLow31 = (1ull << 31) - 1;
+__device__ __forceinline__ uint64_t pack_agg(uint64_t triplets, uint64_t pairs) {
+  return (triplets << 31) | pairs;
+}
 
 // Phase timestamps of the bin kernel, compiled in only with
 // -DFSP_PHASE_TIMING (16 slots per bin, 100 MHz wall clock).
@@ -889,7 +924,7 @@ __device__ uint32_t batch(const ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x
     uint32_t rk = (r4[0] + r4[1]) + (r4[2] + r4[3]);
     for (; t < g1; ++t) rk += mk[t] < kk ? 1u : 0u;
     sval[g0 + rk] = mval[p];
-    if (a.perm) a.perm[e0 + g0 + rk] = (int32_t)kk;
+    if (a.perm) a.perm[e0 + g0 + rk + a.pshift] = (int32_t)kk;
   }
   __syncthreads();
 
@@ -913,12 +948,12 @@ __device__ uint32_t batch(const ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x
     for (; t < g1; ++t) acc = acc + sval[t];
     const int64_t out = base + o;
     if (out < a.out_cap) {
-      a.irS[out] = (int32_t)grow[o];
+      a.irS[out] = (int32_t)(grow[o] >> a.rshift);
       a.prS[out] = acc;
     } else {
       over = true;
     }
-    if (a.seg) a.seg[out] = e0 + (int32_t)g0;
+    if (a.seg) a.seg[out] = (int32_t)(e0 + g0 + a.pshift);
   }
   if (over) atomicOr(&a.ctrl->err, kErrCap);
   for (int c = cb + tid; c < ce; c += NT)
@@ -1053,7 +1088,7 @@ __device__ void long_emit(const ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x
       const int64_t g = run + pre + head - 1;  // group of position p
       const int64_t out = base + g;
       const Entry<VT> en = s[a0 + p];
-      if (a.perm) a.perm[a0 + p] = (int32_t)en.k;
+      if (a.perm) a.perm[a0 + p + a.pshift] = (int32_t)en.k;
       if (a.slot) a.slot[en.k] = (int32_t)out;
       if (head) {
         VT acc = (VT)0;
@@ -1063,12 +1098,12 @@ __device__ void long_emit(const ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x
           ++t;
         } while (t < len && s[a0 + t].row == r);
         if (out < a.out_cap) {
-          a.irS[out] = (int32_t)r;
+          a.irS[out] = (int32_t)(r >> a.rshift);
           a.prS[out] = acc;
         } else {
           over = true;
         }
-        if (a.seg) a.seg[out] = a0 + p;
+        if (a.seg) a.seg[out] = (int32_t)(a0 + p + a.pshift);
       }
     }
     run += total;
@@ -1081,9 +1116,8 @@ __device__ void long_emit(const ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x
 // in batches of consecutive columns that fit, and columns longer than the
 // capacity take the long path.  Two sweeps: count, look-back, emit.
 template <typename VT, int CAP, int NT>
-__device__ int64_t chunk_slow(const ChunkArgs<VT>& a,
-                              const ChunkCtx<VT, CAP, NT>& x, int q, int cb,
-                              int cl) {
+__device__ int64_t chunk_slow(ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x,
+                              int q, int cb, int cl) {
   int64_t* misc = x.misc();
   int64_t base = 0;
   for (int sweep = 0; sweep < 2; ++sweep) {
@@ -1136,12 +1170,17 @@ __device__ int64_t chunk_slow(const ChunkArgs<VT>& a,
     }
     __syncthreads();
     if (sweep == 0) {
+      const int64_t e0c = a.colptr[cb < cl ? cb : cl];
+      const int64_t e1c = a.colptr[cl];
       if (threadIdx.x < 64) {
-        const int64_t b = lookback(a.status, q, (uint64_t)(off - base));
+        const int64_t b = lookback(a.status, q,
+                                   pack_agg((uint64_t)(e1c - e0c), (uint64_t)(off - base)));
         if (threadIdx.x == 0) misc[4] = b;
       }
       __syncthreads();
-      base = misc[4];
+      base = misc[4] & kLow31;
+      a.pshift = (misc[4] >> 31) - e0c;
+      if (threadIdx.x == 0) misc[5] = (misc[4] >> 31) + (e1c - e0c);
     } else {
       return off;  // base + distinct count of the chunk
     }
@@ -1165,6 +1204,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
   const int tid = threadIdx.x;
   const int span = e1 - e0;
   const int wc = c1 - c0;
+  const uint32_t cmask = (1u << a.rshift) - 1u;  // packed keys only
   FSP_PHASE(a, q, 1)
   uint32_t* ht = x.ht();
   uint32_t* row = x.row();
@@ -1184,7 +1224,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
     if (i < span) {
       const Entry<VT> en = load_entry<VT>(&a.bucket[e0 + i]);
       row[i] = en.row;
-      col[i] = bcol[e0 + i];
+      col[i] = bcol ? bcol[e0 + i] : (en.row & cmask);
       kr[j] = en.k;
       vr[j] = en.v;
     }
@@ -1218,7 +1258,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
   // distinct pairs per column -> offsets; publish the bin's count now, read
   // the prefix of the earlier bins only when emitting
   const uint32_t D = lds_excl_scan<NT>(cd, wc + 1, x.wave());
-  if (tid < 64) lookback_publish(a.status, q, D);
+  if (tid < 64) lookback_publish(a.status, q, pack_agg((uint64_t)span, D));
   uint32_t* dlist = x.dlist();
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
@@ -1289,7 +1329,11 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
   // order each group by k: values go straight to their sorted place (the
   // column-end / count arrays are free by now), so do the k of the plan
   VT* sval = reinterpret_cast<VT*>(x.cend());
-  for (int p = tid; p < span; p += NT) {
+  uint32_t spos[EPT];  // sorted position of this thread's placed triplets
+#pragma unroll
+  for (int jj = 0; jj < EPT; ++jj) {
+    const int p = tid + jj * NT;
+    if (p >= span) break;
     const uint32_t o = mgrp[p];
     const uint32_t g0 = gs[o], g1 = gs[o + 1];
     const uint32_t kk = mk[p];
@@ -1302,18 +1346,30 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
     uint32_t rk = (r4[0] + r4[1]) + (r4[2] + r4[3]);
     for (; t < g1; ++t) rk += mk[t] < kk ? 1u : 0u;
     sval[g0 + rk] = mval[p];
-    if (a.perm) a.perm[e0 + g0 + rk] = (int32_t)kk;
+    spos[jj] = g0 + rk;
   }
   FSP_PHASE(a, q, 7)
   if (tid < 64) {
-    const int64_t b = lookback_wait(a.status, q, D);
-    if (tid == 0) x.misc()[1] = b;
+    const int64_t b = lookback_wait(a.status, q, pack_agg((uint64_t)span, D));
+    if (tid == 0) {
+      x.misc()[1] = b & kLow31;
+      x.misc()[5] = (b >> 31) + span;  // compact triplets up to this bin's end
+      x.misc()[6] = (b >> 31) - e0;
+    }
   }
   __syncthreads();
   FSP_PHASE(a, q, 9)
 
   // emit
   const int64_t base = x.misc()[1];
+  const int64_t pshift = x.misc()[6];
+  if (a.perm) {
+#pragma unroll
+    for (int jj = 0; jj < EPT; ++jj) {
+      const int p = tid + jj * NT;
+      if (p < span) a.perm[e0 + spos[jj] + pshift] = (int32_t)mk[p];
+    }
+  }
   if (a.slot)
     for (int p = tid; p < span; p += NT) a.slot[mk[p]] = (int32_t)(base + mgrp[p]);
   bool over = false;
@@ -1332,12 +1388,12 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
     for (; t < g1; ++t) acc = acc + sval[t];
     const int64_t out = base + o;
     if (out < a.out_cap) {
-      a.irS[out] = (int32_t)grow[o];
+      a.irS[out] = (int32_t)(grow[o] >> a.rshift);
       a.prS[out] = acc;
     } else {
       over = true;
     }
-    if (a.seg) a.seg[out] = e0 + (int32_t)g0;
+    if (a.seg) a.seg[out] = (int32_t)(e0 + g0 + pshift);
   }
   if (over) atomicOr(&a.ctrl->err, kErrCap);
   for (int c = tid; c < wc; c += NT) a.jcS[c0 + c] = (int32_t)(base + cd[c]);
@@ -1360,13 +1416,17 @@ __device__ int64_t bin_slow(ChunkArgs<VT> a, const uint32_t* __restrict__ bcol,
   uint32_t* hist = x.cd();  // CAP+1 entries, wc <= CAP
   for (int i = tid; i <= wc; i += NT) hist[i] = 0u;
   __syncthreads();
-  for (int i = tid; i < span; i += NT) atomicAdd(&hist[bcol[e0 + i]], 1u);
+  const uint32_t cmask = (1u << a.rshift) - 1u;
+  auto colof = [&](int i) -> uint32_t {
+    return bcol ? bcol[e0 + i] : (a.bucket[e0 + i].row & cmask);
+  };
+  for (int i = tid; i < span; i += NT) atomicAdd(&hist[colof(i)], 1u);
   __syncthreads();
   lds_excl_scan<NT>(hist, wc + 1, x.wave());
   for (int c = tid; c <= wc; c += NT) colptr_g[c0 + c] = e0 + (int32_t)hist[c];
   __syncthreads();
   for (int i = tid; i < span; i += NT) {
-    const uint32_t p = atomicAdd(&hist[bcol[e0 + i]], 1u);
+    const uint32_t p = atomicAdd(&hist[colof(i)], 1u);
     const Entry<VT> en = load_entry<VT>(&a.bucket[e0 + i]);
     store_entry<VT>(&a.tmp[e0 + p], en.row, en.k, en.v);
   }
@@ -1382,6 +1442,7 @@ __device__ int64_t bin_slow(ChunkArgs<VT> a, const uint32_t* __restrict__ bcol,
 template <typename VT, int CAP, int NT>
 __global__ void __launch_bounds__(NT)
 k_bin(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
+      const uint32_t* __restrict__ binfill, int32_t slotcap,
       const uint32_t* __restrict__ bcol, int32_t* __restrict__ colptr_g,
       int32_t s, int32_t B) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<CAP>::kBytes];
@@ -1399,7 +1460,16 @@ k_bin(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
   const int N = a.N;
   const int c0 = (int)min((int64_t)N, (int64_t)q << s);
   const int c1 = (int)min((int64_t)N, ((int64_t)q + 1) << s);
-  const int e0 = binstart[q], e1 = binstart[q + 1];
+  // bin q's triplets: [binstart[q], binstart[q+1]), or, with fixed-capacity
+  // bins, the first binfill[q] places of [q*slotcap, (q+1)*slotcap)
+  int e0, e1;
+  if (slotcap > 0) {
+    e0 = q * slotcap;
+    e1 = e0 + (int)min(binfill[q], (uint32_t)slotcap);
+  } else {
+    e0 = binstart[q];
+    e1 = binstart[q + 1];
+  }
   int64_t end;
   if (e1 - e0 <= a.cap)
     end = bin_fast<VT, CAP, NT>(a, bcol, x, q, c0, c1, e0, e1);
@@ -1408,7 +1478,7 @@ k_bin(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
   if (q == B - 1 && threadIdx.x == 0) {
     a.jcS[N] = (int32_t)end;
     a.ctrl->nnz = end;
-    if (a.seg) a.seg[end] = e1;
+    if (a.seg) a.seg[end] = (int32_t)misc[5];
   }
 }
 

@@ -52,7 +52,7 @@ def test_tuning_validation():
     fs.set_tuning(reset=True)
     d = fs.get_tuning()
     assert d == {"chunk_cap": 2048, "stream_block": 256, "stream_items": 8,
-                 "reuse_block": 256, "chunk_block": 256}
+                 "reuse_block": 256, "chunk_block": 256, "bin_mode": 0}
     fs.set_tuning(chunk_cap=64)
     assert fs.get_tuning()["chunk_cap"] == 64
     with pytest.raises(fs.FsparseError):

@@ -177,3 +177,39 @@ def test_stream_copy(fs):
     fs.stream_copy(a, b)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("mode", ["dense", "slot", "claim"])
+@pytest.mark.parametrize("c", [64, 2048])
+def test_bin_modes(fs, mode, c):
+    fs.set_tuning(chunk_cap=c, bin_mode=mode)
+    try:
+        t = W.uniform(400_000, 3000, 40_000, seed=12)
+        check(fs, t.ii, t.jj, t.ss, t.m, t.n)
+        t = W.fem3d(16, 0.15, seed=13)
+        check(fs, t.ii, t.jj, t.ss, t.m, t.n)
+        t = W.fem2d(120, 0.2, seed=14, dtype=np.float32)
+        check(fs, t.ii, t.jj, t.ss, t.m, t.n)
+    finally:
+        fs.set_tuning(reset=True)
+
+
+def test_slot_overflow_falls_back(fs):
+    # one column far heavier than a fixed-capacity bin: the one-pass
+    # placement overflows and the call redoes the placement in two passes
+    fs.set_tuning(chunk_cap=64, bin_mode="slot")
+    try:
+        t = W.uniform(400_000, 3000, 40_000, seed=15)
+        t.jj[:700] = 7
+        check(fs, t.ii, t.jj, t.ss, t.m, t.n)
+    finally:
+        fs.set_tuning(reset=True)
+
+
+def test_huge_row_indices(fs):
+    # rows near 2^31 do not fit a packed (row, column) word
+    rng = np.random.default_rng(16)
+    m = 2**31 - 2
+    ii = rng.integers(m - 50, m + 1, size=5000).astype(np.int32)
+    jj = rng.integers(1, 301, size=5000).astype(np.int32)
+    check(fs, ii, jj, rng.standard_normal(5000), m, 300)
