@@ -30,11 +30,11 @@ namespace {
 // tuning
 // ---------------------------------------------------------------------------
 struct Tuning {
-  int cap = 2048;
+  int cap = 4096;
   int sblock = 256;
   int sitems = 8;
   int rblock = 256;
-  int cblock = 256;  // threads of one bin workgroup
+  int cblock = 1024;  // threads of one bin workgroup
   int bmode = 0;     // 0 automatic, else 1 + BinMode to force one
 };
 std::mutex g_mu;
@@ -147,7 +147,7 @@ constexpr int64_t kDenseBins = 16384;       // LDS counters of the dense mode
 constexpr int64_t kDenseMatrix = 8 << 20;   // tiles x bins counters
 constexpr int kClaimNT = 256;
 constexpr int kClaimIPT = 16;
-constexpr int kClaimWindow = 16384;         // LDS bins of one claim tile
+constexpr int kClaimWindow = 4096;          // LDS bins of one claim tile
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -418,8 +418,8 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   if (e != hipSuccess) return e;
   if (mode == kDense) {
     e = launch(kColScan, stream, [&] {
-      hipLaunchKernelGGL(fsp::k_colscan, dim3((unsigned)((B + 255) / 256)), dim3(256),
-                         0, stream, cntmat, (int32_t)g.T, B, bincnt);
+      hipLaunchKernelGGL(fsp::k_colscan<1024>, dim3((unsigned)((B + 63) / 64)),
+                         dim3(1024), 0, stream, cntmat, (int32_t)g.T, B, bincnt);
     });
     if (e != hipSuccess) return e;
   }
@@ -471,7 +471,7 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   const uint32_t* bcol_in = packed ? nullptr : bcol;
   int32_t* colptr_g = at<int32_t>(ws, lo.colptr);
   const int kc = kernel_cap(tu.cap);
-  const int nt = std::max(kc / 16, std::min(tu.cblock, kc));  // <= 16 triplets per thread
+  const int nt = std::max(kc / 8, std::min(tu.cblock, kc));  // <= 8 triplets per thread
   e = launch(kChunk, stream, [&] {
 #define FSP_BIN(C, T)                                                          \
   hipLaunchKernelGGL((fsp::k_bin<VT, C, T>), dim3((unsigned)B), dim3(T), 0,    \
@@ -481,7 +481,7 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
     } else if (kc == 2048) {
       if (nt <= 256) FSP_BIN(2048, 256); else if (nt <= 512) FSP_BIN(2048, 512); else FSP_BIN(2048, 1024);
     } else {
-      if (nt <= 256) FSP_BIN(4096, 256); else if (nt <= 512) FSP_BIN(4096, 512); else FSP_BIN(4096, 1024);
+      if (nt <= 512) FSP_BIN(4096, 512); else FSP_BIN(4096, 1024);
     }
 #undef FSP_BIN
   });

@@ -458,14 +458,44 @@ __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
 }
 
 // dense mode, pass 2: for every bin, exclusive prefix over the tiles (in
-// place) and the bin total
-__global__ void k_colscan(uint32_t* __restrict__ cnt, int32_t T, int32_t B,
-                          uint32_t* __restrict__ tot) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+// place) and the bin total.  A block takes 64 bins (one per lane, so every
+// row access is coalesced) and splits the tiles into NT/64 segments that are
+// summed in parallel and then rewritten as running prefixes.
+template <int NT>
+__global__ void __launch_bounds__(NT)
+k_colscan(uint32_t* __restrict__ cnt, int32_t T, int32_t B,
+          uint32_t* __restrict__ tot) {
+  constexpr int NSEG = NT / 64;
+  __shared__ uint32_t part[NSEG][64];
+  const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
+  const int b = blockIdx.x * 64 + lane;
+  const int per = (T + NSEG - 1) / NSEG;
+  const int t0 = min(T, seg * per), t1 = min(T, t0 + per);
+  uint32_t sum = 0;
+  if (b < B) {
+    int t = t0;
+    for (; t + 8 <= t1; t += 8) {
+      uint32_t c[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) c[u] = cnt[(int64_t)(t + u) * B + b];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sum += c[u];
+    }
+    for (; t < t1; ++t) sum += cnt[(int64_t)t * B + b];
+  }
+  part[seg][lane] = sum;
+  __syncthreads();
+  uint32_t run = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < NSEG; ++k) {
+    const uint32_t v = part[k][lane];
+    run += k < seg ? v : 0u;
+    all += v;
+  }
   if (b >= B) return;
-  uint32_t run = 0;
-  int t = 0;
-  for (; t + 8 <= T; t += 8) {
+  if (seg == 0) tot[b] = all;
+  int t = t0;
+  for (; t + 8 <= t1; t += 8) {
     uint32_t c[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) c[u] = cnt[(int64_t)(t + u) * B + b];
@@ -475,12 +505,11 @@ __global__ void k_colscan(uint32_t* __restrict__ cnt, int32_t T, int32_t B,
       run += c[u];
     }
   }
-  for (; t < T; ++t) {
+  for (; t < t1; ++t) {
     const uint32_t c = cnt[(int64_t)t * B + b];
     cnt[(int64_t)t * B + b] = run;
     run += c;
   }
-  tot[b] = run;
 }
 
 // dense mode, pass 3: scatter (row, k, value) and the in-bin column into
@@ -1191,6 +1220,7 @@ __device__ int64_t chunk_slow(ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x,
 // ---------------------------------------------------------------------------
 // bin kernel: one workgroup per bin of w consecutive columns
 // ---------------------------------------------------------------------------
+
 // Fast path: the bin's triplets fit the LDS.  Columns are known per triplet
 // (bcol), so equal (column,row) pairs are grouped by hashing straight away;
 // the distinct rows of each column are ranked, contributions of a pair are
