@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only run the 1 GiB copy kernel (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -126,6 +128,12 @@ def main():
 
     import paper_1406_1066_amd as fs
     import workloads as W
+
+    if args.copy_only:
+        gbs = copy_bw(fs, torch)
+        print(json.dumps({"copy_bytes_per_launch": 2 * (1 << 30),
+                          "copy_gbps": gbs}), flush=True)
+        return
 
     vt = np.float64 if args.dtype == "f64" else np.float32
     vb = 8 if vt == np.float64 else 4
