@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 1 GiB copy kernel (counter calibration)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch shapes")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -147,6 +149,12 @@ def main():
     jj = torch.from_numpy(t.jj).to(dev)
     ss = torch.from_numpy(t.ss).to(dev)
     L, m, n = t.L, t.m, t.n
+    tuned = None
+    if not args.no_autotune:
+        from paper_1406_1066_amd import autotune
+        log("autotuning")
+        tuned = autotune.tune(ii, jj, ss, m, n)
+        log("tuning", tuned["best"], "cached" if tuned["cached"] else "")
     ws = torch.empty(fs.workspace_bytes(L, n, 1, ss.dtype), dtype=torch.uint8,
                      device=dev)
     jcS = torch.empty(n + 1, dtype=torch.int32, device=dev)
@@ -198,6 +206,7 @@ def main():
                      "algorithmic_bytes": ab,
                      "avg_launch_ms": stages[dom]},
         "stages_ms": stages,
+        "tuning": fs.get_tuning(),
         "path": {"bytes": path_bytes(L, nnz, n, vb),
                  "frac": path_bytes(L, nnz, n, vb) / (el / args.steps)
                  / 1e9 / HBM_PEAK_GBS},
@@ -288,6 +297,11 @@ def bench_batched(args, batch, fs, torch, np, vb, eb):
     iid = torch.from_numpy(ii).to(dev)
     jjd = torch.from_numpy(jj).to(dev)
     ssd = torch.from_numpy(ss).to(dev)
+    if not args.no_autotune:
+        from paper_1406_1066_amd import autotune
+        log("autotuning")
+        tuned = autotune.tune(iid, jjd, ssd, list(m), list(n), trip_off=off)
+        log("tuning", tuned["best"], "cached" if tuned["cached"] else "")
     ws = torch.empty(fs.workspace_bytes(L, int(n.sum()), batch.nb, ssd.dtype),
                      dtype=torch.uint8, device=dev)
 
@@ -336,6 +350,7 @@ def bench_batched(args, batch, fs, torch, np, vb, eb):
                      "traffic": read_traffic(args.config, dom),
                      "algorithmic_bytes": ab, "avg_launch_ms": stages[dom]},
         "stages_ms": stages,
+        "tuning": fs.get_tuning(),
         "modes": {"reuse": {"value": L / (rms * 1e-3) / 1e9, "ms": rms,
                             "unit": "Gtriplets/s",
                             "frac": stage_bytes("reuse", L, nnz, N, vb, eb)
