@@ -148,6 +148,7 @@ constexpr int64_t kDenseMatrix = 8 << 20;   // tiles x bins counters
 constexpr int kClaimNT = 256;
 constexpr int kClaimIPT = 16;
 constexpr int kClaimWindow = 4096;          // LDS bins of one claim tile
+constexpr int kReuseTP = 2048;              // sorted positions per re-use tile
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -200,7 +201,7 @@ struct Layout {
   Geom g;
   int64_t mmax;  // largest m over the matrices (batched)
   size_t ctrl, scan_st, bin_st, bincnt, binfill, bmax, zero_end;
-  size_t binstart, cntmat, bcol, colptr, bucket, tmp, perm, seg, islot;
+  size_t binstart, cntmat, bcol, colptr, bucket, tmp, perm, seg, islot, rtile;
   size_t b_trip, b_col, b_m, b_n, jcg, nnzoff;
   size_t total;
   int64_t nscan;
@@ -229,6 +230,7 @@ Layout make_layout(int64_t L, int64_t N, int nb, int esize, const Tuning& tu) {
   o.perm = p;        p = al(p + 4 * (size_t)L);
   o.seg = p;         p = al(p + 4 * (size_t)(L + 1));
   o.islot = p;       p = al(p + 4 * (size_t)L);
+  o.rtile = p;       p = al(p + 4 * (size_t)(L / kReuseTP + 3));
   o.b_trip = p;      p = al(p + 8 * (size_t)(nb + 1));
   o.b_col = p;       p = al(p + 8 * (size_t)(nb + 1));
   o.b_m = p;         p = al(p + 4 * (size_t)nb);
@@ -263,6 +265,8 @@ struct fsparse_plan {
   const int32_t* perm = nullptr;
   const int32_t* seg = nullptr;
   const int32_t* slot = nullptr;
+  const int32_t* rtile = nullptr;  // first output of every re-use tile
+  int64_t ntiles = 0;
   int rblock = 256;
   // ordered re-use graph: one kernel node
   hipGraph_t g_ord = nullptr;
@@ -281,8 +285,10 @@ struct fsparse_plan {
 namespace {
 
 template <typename VT>
-void* reuse_fn() {
-  return reinterpret_cast<void*>(&fsp::k_reuse<VT>);
+void* reuse_fn(int nt) {
+  if (nt <= 256) return reinterpret_cast<void*>(&fsp::k_reuse<VT, kReuseTP, 256>);
+  if (nt <= 512) return reinterpret_cast<void*>(&fsp::k_reuse<VT, kReuseTP, 512>);
+  return reinterpret_cast<void*>(&fsp::k_reuse<VT, kReuseTP, 1024>);
 }
 template <typename VT>
 void* fill_fn() {
@@ -295,15 +301,14 @@ void* atomic_fn() {
 
 fsparse_status plan_reuse_ordered(fsparse_plan* pl, const void* ss, void* prS,
                                   hipStream_t stream) {
-  const int blk = pl->rblock;
-  const int grid = grid_for(pl->nnz, blk, 16);
+  const int blk = pl->rblock <= 256 ? 256 : (pl->rblock <= 512 ? 512 : 1024);
   const int32_t* perm = pl->perm;
   const int32_t* seg = pl->seg;
-  int64_t nnz = pl->nnz;
-  void* args[] = {(void*)&perm, (void*)&seg, (void*)&ss, (void*)&nnz, (void*)&prS};
+  const int32_t* rtile = pl->rtile;
+  void* args[] = {(void*)&perm, (void*)&seg, (void*)&rtile, (void*)&ss, (void*)&prS};
   hipKernelNodeParams kp{};
-  kp.func = pl->dt == FSPARSE_F64 ? reuse_fn<double>() : reuse_fn<float>();
-  kp.gridDim = dim3(grid);
+  kp.func = pl->dt == FSPARSE_F64 ? reuse_fn<double>(blk) : reuse_fn<float>(blk);
+  kp.gridDim = dim3((unsigned)pl->ntiles);
   kp.blockDim = dim3(blk);
   kp.sharedMemBytes = 0;
   kp.kernelParams = args;
@@ -488,6 +493,19 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   return e;
 }
 
+// Tile table of the re-use kernel (first output of every tile); reads the
+// distinct count from the control block, so it can be queued before the
+// readback.
+hipError_t launch_reuse_tiles(void* ws, const Layout& lo, int64_t L,
+                              hipStream_t stream) {
+  const int64_t T = (L + kReuseTP - 1) / kReuseTP;
+  return launch(kReuse, stream, [&] {
+    hipLaunchKernelGGL(fsp::k_reuse_tiles, dim3(grid_for(L + 1, 256, 8)), dim3(256), 0,
+                       stream, at<int32_t>(ws, lo.seg), &at<Ctrl>(ws, lo.ctrl)->nnz,
+                       kReuseTP, T, at<int32_t>(ws, lo.rtile));
+  });
+}
+
 fsparse_status check_dt(fsparse_dtype dt) {
   return (dt == FSPARSE_F64 || dt == FSPARSE_F32) ? FSPARSE_OK : FSPARSE_E_ARG;
 }
@@ -651,6 +669,7 @@ fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
                                        (float*)prS, cap, slot_used, keep, mode,
                                        stream);
       if (e != hipSuccess) return FSPARSE_E_HIP;
+      if (keep && launch_reuse_tiles(ws, lo, len, stream) != hipSuccess) return FSPARSE_E_HIP;
       HIPCHK(hipMemcpyAsync(h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
       HIPCHK(hipStreamSynchronize(stream));
       // a full fixed-capacity bin: count first and redo
@@ -688,6 +707,8 @@ fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
       pl->perm = at<int32_t>(ws, lo.perm);
       pl->seg = at<int32_t>(ws, lo.seg);
       pl->slot = slot_used;
+      pl->rtile = at<int32_t>(ws, lo.rtile);
+      pl->ntiles = (len + kReuseTP - 1) / kReuseTP;
       pl->rblock = tu.rblock;
       *plan = pl;
     }
@@ -845,6 +866,7 @@ fsparse_status fsparse_assemble_batched(
                                     ws, jcg, irS, (float*)prS, cap, slot_used, keep,
                                     mode, stream);
     if (e != hipSuccess) return FSPARSE_E_HIP;
+    if (keep && launch_reuse_tiles(ws, lo, L, stream) != hipSuccess) return FSPARSE_E_HIP;
     if (nb > 1) {
       e = launch(kBatchedJcs, stream, [&] {
         hipLaunchKernelGGL(fsp::k_batched_jcs, dim3(grid_for(N + nb, 256, 4)),
@@ -896,6 +918,8 @@ fsparse_status fsparse_assemble_batched(
     pl->perm = at<int32_t>(ws, lo.perm);
     pl->seg = at<int32_t>(ws, lo.seg);
     pl->slot = slot_used;
+    pl->rtile = at<int32_t>(ws, lo.rtile);
+    pl->ntiles = (L + kReuseTP - 1) / kReuseTP;
     pl->rblock = tu.rblock;
     *plan = pl;
   }

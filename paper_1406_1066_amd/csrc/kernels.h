@@ -1537,18 +1537,64 @@ __global__ void k_batched_jcs(const int32_t* __restrict__ jcg,
 // ---------------------------------------------------------------------------
 // re-assembly, atomic accumulation, backward
 // ---------------------------------------------------------------------------
-template <typename VT>
-__global__ void k_reuse(const int32_t* __restrict__ perm,
-                        const int32_t* __restrict__ seg,
-                        const VT* __restrict__ ss, int64_t nnz,
-                        VT* __restrict__ prS) {
+// Re-use tiles: tile t owns the outputs j whose first sorted position
+// seg[j] lies in [t*TP, (t+1)*TP); rtile[t] is the first of them.  seg is
+// strictly increasing (every output has a contribution).
+__global__ void k_reuse_tiles(const int32_t* __restrict__ seg,
+                              const int64_t* __restrict__ nnz_dev, int32_t TP,
+                              int64_t T, int32_t* __restrict__ rtile) {
+  const int64_t nnz = *nnz_dev;
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; j < nnz; j += stride) {
-    const int32_t b = seg[j], e = seg[j + 1];
-    VT acc = (VT)0;
-    for (int32_t p = b; p < e; ++p) acc = acc + ss[perm[p]];
-    prS[j] = acc;
+  for (; j <= nnz; j += stride) {
+    const int64_t lo = j == 0 ? 0 : (int64_t)seg[j - 1] / TP + 1;
+    const int64_t hi = min((int64_t)seg[j] / TP, T);
+    for (int64_t t = lo; t <= hi; ++t) rtile[t] = (int32_t)j;
+    if (j == nnz)
+      for (int64_t t = hi + 1; t <= T; ++t) rtile[t] = (int32_t)nnz;
+  }
+}
+
+// Ordered re-assembly: the block gathers the values of its tile's
+// contributions in sorted order into LDS (one independent gather per
+// thread and position, perm read coalesced), then every output folds its
+// run from +0.0 in increasing k, reading LDS.  Runs longer than the LDS
+// stage fold straight from global memory.
+template <typename VT, int TP, int NT>
+__global__ void __launch_bounds__(NT)
+k_reuse(const int32_t* __restrict__ perm, const int32_t* __restrict__ seg,
+        const int32_t* __restrict__ rtile, const VT* __restrict__ ss,
+        VT* __restrict__ prS) {
+  constexpr int LCAP = 2 * TP;
+  __shared__ VT val[LCAP];
+  const int t = blockIdx.x;
+  const int J0 = rtile[t], J1 = rtile[t + 1];
+  if (J0 >= J1) return;
+  const int P0 = seg[J0], P1 = seg[J1];
+  if (P1 - P0 <= LCAP) {
+    for (int p = P0 + threadIdx.x; p < P1; p += NT) val[p - P0] = ss[perm[p]];
+    __syncthreads();
+    for (int j = J0 + threadIdx.x; j < J1; j += NT) {
+      const int a = seg[j] - P0, b = seg[j + 1] - P0;
+      VT acc = (VT)0;
+      int q = a;
+      for (; q + 4 <= b; q += 4) {
+        const VT v0 = val[q], v1 = val[q + 1], v2 = val[q + 2], v3 = val[q + 3];
+        acc = acc + v0;
+        acc = acc + v1;
+        acc = acc + v2;
+        acc = acc + v3;
+      }
+      for (; q < b; ++q) acc = acc + val[q];
+      prS[j] = acc;
+    }
+  } else {
+    for (int j = J0 + threadIdx.x; j < J1; j += NT) {
+      const int a = seg[j], b = seg[j + 1];
+      VT acc = (VT)0;
+      for (int q = a; q < b; ++q) acc = acc + ss[perm[q]];
+      prS[j] = acc;
+    }
   }
 }
 
