@@ -1,22 +1,29 @@
 // Device code of the gfx950 sparse-assembly pipeline.
 //
-// Fresh assembly of S = sparse(ii, jj, ss, m, n) (Section 2.1) runs as
-//   hist   column histogram of jj                (role of Part 1, Section 2.3.1,
-//                                                 but over columns)
-//   scan   single-pass decoupled look-back exclusive scan of the histogram
-//          -> triplet column pointers (collisions not yet removed, like the
-//          "pessimistic" row pointer of Part 1) and the chunk table
-//   bucket every triplet claims a slot in its column's bucket (device atomic
-//          on the column fill pointer) and stores (row, k, value) there
-//   chunk  one workgroup per window of the bucket array: in LDS it groups
-//          equal (column,row) pairs (hash), ranks the distinct rows of every
-//          column (rows increase within a column, as Part 3 guarantees),
-//          orders each pair's contributions by k and folds them from +0.0 in
-//          that order (the order of the serial post-processing); the chunk's
-//          output offset comes from a chained look-back over the chunks, in
-//          column order, which yields jcS (Part 4's running sum) as well.
-// The permutation of the contributions and the segment starts are kept for
-// pattern re-use; slot[k] is the paper's inverse rank irank (eqs. (2.2)-(2.3)).
+// Fresh assembly of S = sparse(ii, jj, ss, m, n) (Section 2.1).  Columns are
+// grouped into bins of w = 2^s consecutive columns, sized so an average bin
+// fills about half the LDS of one sort/fold workgroup.
+//   count    per-tile LDS histograms of bins (dense mode: a tiles x bins
+//            count matrix; claim mode: one device atomic per (tile, bin));
+//            out-of-range columns are flagged here (pre-processing listing)
+//   colscan  dense mode: column prefix sums of the count matrix, so every
+//            tile knows its exclusive offset in every bin
+//   binscan  single-pass decoupled look-back scan of the bin totals
+//   scatter  every triplet goes to its bin as (row << s | in-bin column, k,
+//            value), ranked inside the tile by an LDS atomic; slot mode
+//            instead gives every bin a fixed place and claims space per
+//            (tile, bin) in one pass, falling back to count-first when a bin
+//            overflows
+//   bin      one workgroup per bin: equal (column,row) pairs are grouped by
+//            an LDS hash, the distinct rows of every column are ranked (rows
+//            increase within a column, as Part 3 of Section 2.3 yields),
+//            each pair's contributions are put in increasing k and folded
+//            from +0.0 in that order (the serial post-processing order);
+//            the bin's output offset comes from a chained look-back over the
+//            bins, which also gives jcS (Part 4's running sum).
+// The sorted order of the contributions (perm) and the first sorted
+// position of every output (seg) are kept for pattern re-use; slot[k] is
+// the paper's inverse rank irank (Section 2.2, eqs. (2.2)-(2.3)).
 #pragma once
 
 #include <hip/hip_runtime.h>
