@@ -17,6 +17,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from forming packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a ticket taken by one lane is not needed at once: no wave-wide atomic
+    # rewrite that waits for its result on the spot
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wno-unused-result", "-Wno-unused-value",
 ]
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -103,14 +104,43 @@ hipError_t launch(int stage, hipStream_t s, F&& f) {
 // ---------------------------------------------------------------------------
 // device properties
 // ---------------------------------------------------------------------------
-int num_cus() {
-  int dev = 0, cus = 0;
+// Per-device values are looked up once (device ids below kMaxDev).
+constexpr int kMaxDev = 64;
+
+int cur_device() {
+  int dev = 0;
   hipGetDevice(&dev);
+  return (dev >= 0 && dev < kMaxDev) ? dev : 0;
+}
+
+int num_cus() {
+  static std::atomic<int> cache[kMaxDev];
+  const int dev = cur_device();
+  int cus = cache[dev].load(std::memory_order_relaxed);
+  if (cus > 0) return cus;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
           hipSuccess ||
       cus <= 0)
     cus = 256;
+  cache[dev].store(cus, std::memory_order_relaxed);
   return cus;
+}
+
+// Blocks of `kernel` that fit the device at once (persistent launches).
+template <typename K>
+int64_t resident(K kernel, int block) {
+  // one cache per kernel instantiation (each is launched with one block size)
+  static std::atomic<int> cache[kMaxDev];
+  const int dev = cur_device();
+  int per = cache[dev].load(std::memory_order_relaxed);
+  if (per <= 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) !=
+            hipSuccess ||
+        per <= 0)
+      per = 1;
+    cache[dev].store(per, std::memory_order_relaxed);
+  }
+  return (int64_t)per * num_cus();
 }
 
 int grid_for(int64_t n, int block, int per_cu = 8) {
@@ -411,7 +441,7 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   // 1. bin counts (the slot mode has none)
   if (mode != kSlot) e = launch(kHist, stream, [&] {
     if (mode == kDense)
-      hipLaunchKernelGGL(fsp::k_count_dense<BATCHED>, dim3((unsigned)g.T), dim3(blk),
+      hipLaunchKernelGGL(fsp::k_count_dense<BATCHED>, dim3((unsigned)(8 * ((g.T + 7) / 8))), dim3(blk),
                          (size_t)B * 4, stream, jj, L, n, bd, s, B, (int32_t)g.TS,
                          cntmat, ctrl);
     else
@@ -438,7 +468,7 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   // 3. scatter into the bins
   e = launch(kBucket, stream, [&] {
     if (mode == kDense)
-      hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED>), dim3((unsigned)g.T),
+      hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED>), dim3((unsigned)(8 * ((g.T + 7) / 8))),
                          dim3(blk), (size_t)B * 4, stream, ii, jj, ss, L, m, n, bd,
                          s, B, (int32_t)g.TS, cntmat, binstart, bucket, bcol, packed,
                          ctrl);
@@ -473,14 +503,28 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   a.phase = g_phase;
 #endif
   a.rshift = packed ? s : 0;
+  {
+    // rank cells: split a column's rows into 2^nbl ranges so that a range
+    // holds about two distinct rows of an average column, within the LDS
+    // table of cap + 1 cells
+    const int64_t per_col = std::max<int64_t>(1, L / std::max<int64_t>(1, N));
+    int nbl = 0;
+    while ((int64_t(4) << nbl) <= per_col && ((int64_t)g.w << (nbl + 1)) <= tu.cap) ++nbl;
+    int rowbits = 0;
+    while ((int64_t(1) << rowbits) < mmax) ++rowbits;
+    a.nbl = nbl;
+    a.bsh = std::max(0, rowbits - nbl);
+  }
   const uint32_t* bcol_in = packed ? nullptr : bcol;
   int32_t* colptr_g = at<int32_t>(ws, lo.colptr);
   const int kc = kernel_cap(tu.cap);
   const int nt = std::max(kc / 8, std::min(tu.cblock, kc));  // <= 8 triplets per thread
+  fsp::BinSrc src{binstart, binfill, bcol_in, slotcap, (int32_t)B, &ctrl->tick_chunk};
   e = launch(kChunk, stream, [&] {
 #define FSP_BIN(C, T)                                                          \
-  hipLaunchKernelGGL((fsp::k_bin<VT, C, T>), dim3((unsigned)B), dim3(T), 0,    \
-                     stream, a, binstart, binfill, slotcap, bcol_in, colptr_g, s, B)
+  hipLaunchKernelGGL((fsp::k_bin<VT, C, T>),                                   \
+                     dim3((unsigned)std::min<int64_t>(B, resident(fsp::k_bin<VT, C, T>, T))), \
+                     dim3(T), 0, stream, a, src, colptr_g, s)
     if (kc == 1024) {
       if (nt <= 256) FSP_BIN(1024, 256); else if (nt <= 512) FSP_BIN(1024, 512); else FSP_BIN(1024, 1024);
     } else if (kc == 2048) {

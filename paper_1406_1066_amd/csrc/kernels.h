@@ -96,25 +96,50 @@ __device__ __forceinline__ void st_status(uint64_t* p, uint64_t v) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// Cross-lane moves for wave scans, done by DPP on the VALU instead of LDS
+// permutes.  CTRL: 0x110 + n = row_shr:n (n lanes up inside a row of 16),
+// 0x142 = row_bcast:15 (lane 15 of each row into the next row), 0x143 =
+// row_bcast:31 (lane 31 into rows 2 and 3).  ROWS masks the rows written;
+// lanes without a source or outside ROWS read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp0(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp0(uint64_t v) {
+  const uint32_t lo = dpp0<CTRL, ROWS>((uint32_t)v);
+  const uint32_t hi = dpp0<CTRL, ROWS>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive sum over the 64 lanes (Hillis-Steele inside rows, then the row
+// totals carried across rows).
 template <typename T>
 __device__ __forceinline__ T wave_incl_sum(T x) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    T y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
+  x += dpp0<0x111, 0xf>(x);
+  x += dpp0<0x112, 0xf>(x);
+  x += dpp0<0x114, 0xf>(x);
+  x += dpp0<0x118, 0xf>(x);
+  x += dpp0<0x142, 0xa>(x);
+  x += dpp0<0x143, 0xc>(x);
   return x;
 }
 
 __device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x = x > y ? x : y;
-  }
+  x = max(x, dpp0<0x111, 0xf>(x));
+  x = max(x, dpp0<0x112, 0xf>(x));
+  x = max(x, dpp0<0x114, 0xf>(x));
+  x = max(x, dpp0<0x118, 0xf>(x));
+  x = max(x, dpp0<0x142, 0xa>(x));
+  x = max(x, dpp0<0x143, 0xc>(x));
   return x;
+}
+
+__device__ __forceinline__ uint32_t lane63(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+__device__ __forceinline__ uint64_t lane63(uint64_t v) {
+  return ((uint64_t)lane63((uint32_t)(v >> 32)) << 32) | lane63((uint32_t)v);
 }
 
 // Exclusive block-wide sum of one value per thread.  All threads call it.
@@ -157,20 +182,52 @@ __device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t* sWave) 
 }
 
 // In-place exclusive prefix sum of arr[0..S) in LDS; returns the total.
-// Each thread scans a contiguous run of the array.  All threads call it.
+// Up to 256 entries one wave scans four per lane; longer arrays are cut into
+// one contiguous run per thread.  All threads call it; sWave holds NT/64 + 1
+// words, and the caller must pass a barrier before calling it again.
 template <int NT>
 __device__ uint32_t lds_excl_scan(uint32_t* arr, int S, uint32_t* sWave) {
+  constexpr int NW = NT / 64;
+  const int wid = threadIdx.x >> 6;
+  if (S <= 256) {
+    if (wid == 0) {
+      const int i0 = lane_id() * 4;
+      uint32_t v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = i0 + u < S ? arr[i0 + u] : 0u;
+      const uint32_t sum = (v[0] + v[1]) + (v[2] + v[3]);
+      const uint32_t inc = wave_incl_sum(sum);
+      uint32_t run = inc - sum;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (i0 + u < S) arr[i0 + u] = run;
+        run += v[u];
+      }
+      if (lane_id() == 63) sWave[NW] = inc;
+    }
+    __syncthreads();
+    return sWave[NW];
+  }
   const int ipt = (S + NT - 1) / NT;
   const int lo = min(S, (int)threadIdx.x * ipt);
   const int hi = min(S, lo + ipt);
   uint32_t acc = 0;
   for (int i = lo; i < hi; ++i) acc += arr[i];
-  uint32_t total;
-  uint32_t run = block_excl_sum<NT>(acc, sWave, total);
+  const uint32_t x = wave_incl_sum(acc);
+  if (lane_id() == 63) sWave[wid] = x;
+  __syncthreads();
+  uint32_t pre = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const uint32_t t = sWave[w];
+    pre += (w < wid) ? t : 0u;
+    total += t;
+  }
+  uint32_t run = pre + x - acc;
   for (int i = lo; i < hi; ++i) {
-    uint32_t x = arr[i];
+    const uint32_t y = arr[i];
     arr[i] = run;
-    run += x;
+    run += y;
   }
   __syncthreads();
   return total;
@@ -219,7 +276,7 @@ __device__ int64_t lookback(uint64_t* status, int q, uint64_t agg) {
     }
     uint64_t v = (lane <= pl) ? (s & kValMask) : 0ull;
     v = wave_incl_sum(v);
-    excl += (int64_t)__shfl(v, 63, 64);
+    excl += (int64_t)lane63(v);
     if (pl < 64) break;
     pred -= 64;
   }
@@ -235,14 +292,27 @@ __device__ __forceinline__ void lookback_publish(uint64_t* status, int q,
     st_status(&status[q], (q == 0 ? kFlagPrefix : kFlagAgg) | agg);
 }
 
-__device__ int64_t lookback_wait(uint64_t* status, int q, uint64_t agg) {
+// First read of the 64 words before tile q, issued ahead of lookback_wait so
+// that its latency overlaps other work.  Any state it sees is usable: an
+// aggregate stays that tile's aggregate, and a word not yet written is read
+// again by lookback_wait.
+__device__ __forceinline__ uint64_t lookback_probe(const uint64_t* status, int q) {
+  const int idx = q - 1 - lane_id();
+  return idx >= 0 ? ld_status(&status[idx]) : kFlagPrefix;
+}
+
+__device__ int64_t lookback_wait(uint64_t* status, int q, uint64_t agg,
+                                 uint64_t probe) {
   const int lane = lane_id();
   if (q == 0) return 0;
   int64_t excl = 0;
   int pred = q - 1;
+  bool first = true;
   for (;;) {
     const int idx = pred - lane;
-    const uint64_t s = (idx >= 0) ? ld_status(&status[idx]) : kFlagPrefix;
+    const uint64_t s = first ? probe
+                             : ((idx >= 0) ? ld_status(&status[idx]) : kFlagPrefix);
+    first = false;
     const uint32_t flag = (uint32_t)(s >> 62);
     const uint64_t inval = __ballot(flag == 0);
     const uint64_t pref = __ballot(flag == 2);
@@ -254,7 +324,7 @@ __device__ int64_t lookback_wait(uint64_t* status, int q, uint64_t agg) {
     }
     uint64_t v = (lane <= pl) ? (s & kValMask) : 0ull;
     v = wave_incl_sum(v);
-    excl += (int64_t)__shfl(v, 63, 64);
+    excl += (int64_t)lane63(v);
     if (pl < 64) break;
     pred -= 64;
   }
@@ -437,6 +507,18 @@ k_scan_excl(const uint32_t* __restrict__ in, int32_t n, int32_t* __restrict__ ou
   }
 }
 
+// Tile of the dense passes handled by this block.  Workgroups are dealt to
+// the 8 XCDs in turn (block i to XCD i mod 8); giving XCD x the consecutive
+// tiles [x*per, (x+1)*per) means that the scatter writes of neighbouring
+// tiles into a bin land in the same L2 and leave it as whole lines.  The
+// grid has 8*per blocks; those past the last tile return at once.
+__device__ __forceinline__ int64_t xcd_tile(int64_t L, int32_t TS) {
+  const int64_t T = (L + TS - 1) / TS;
+  const int64_t per = (T + 7) >> 3;
+  const int64_t t = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  return t < T ? t : -1;
+}
+
 // dense mode, pass 1: per-tile bin histogram -> row `tile` of cnt[T][B]
 template <bool BATCHED>
 __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
@@ -445,7 +527,9 @@ __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
                               Ctrl* ctrl) {
   extern __shared__ uint32_t hist[];
   __shared__ int sB;
-  const int64_t t0 = (int64_t)blockIdx.x * TS;
+  const int64_t tile = xcd_tile(L, TS);
+  if (tile < 0) return;
+  const int64_t t0 = tile * TS;
   const int64_t t1 = min(L, t0 + TS);
   for (int i = threadIdx.x; i < B; i += blockDim.x) hist[i] = 0u;
   int b = tile_first_mat<BATCHED>(bd, t0, L, &sB);
@@ -459,7 +543,7 @@ __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
     atomicAdd(&hist[g >> s], 1u);
   }
   __syncthreads();
-  uint32_t* row = cnt + (int64_t)blockIdx.x * B;
+  uint32_t* row = cnt + tile * B;
   for (int i = threadIdx.x; i < B; i += blockDim.x) row[i] = hist[i];
   if (bad) atomicOr(&ctrl->err, kErrCol);
 }
@@ -533,9 +617,11 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
                                 Ctrl* ctrl) {
   extern __shared__ uint32_t ctr[];
   __shared__ int sB;
-  const int64_t t0 = (int64_t)blockIdx.x * TS;
+  const int64_t tile = xcd_tile(L, TS);
+  if (tile < 0) return;
+  const int64_t t0 = tile * TS;
   const int64_t t1 = min(L, t0 + TS);
-  const uint32_t* orow = offs + (int64_t)blockIdx.x * B;
+  const uint32_t* orow = offs + tile * B;
   for (int i = threadIdx.x; i < B; i += blockDim.x)
     ctr[i] = (uint32_t)binstart[i] + orow[i];
   int b = tile_first_mat<BATCHED>(bd, t0, L, &sB);
@@ -740,6 +826,8 @@ struct ChunkArgs {
   uint64_t* phase;           // per-bin phase timestamps (profiling builds only)
   int32_t rshift;            // rows are stored as (row << rshift) | column
   int64_t pshift;            // compact triplet position = bucket position + pshift
+  int32_t nbl;               // rank buckets per column: 2^nbl row ranges
+  int32_t bsh;               // row >> bsh is the row's range
 };
 
 // Look-back words of the bin kernel carry two running sums at once: the
@@ -747,6 +835,15 @@ struct ChunkArgs {
 constexpr uint64_t kLow31 = (1ull << 31) - 1;
 __device__ __forceinline__ uint64_t pack_agg(uint64_t triplets, uint64_t pairs) {
   return (triplets << 31) | pairs;
+}
+
+// Rank cell of a row word inside its in-bin column.  Rows past m (flagged as
+// an index error, but still binned) are clamped into the last range.
+template <typename VT>
+__device__ __forceinline__ uint32_t rank_cell(const ChunkArgs<VT>& a, uint32_t c,
+                                              uint32_t rword) {
+  const uint32_t b = (rword >> a.rshift) >> a.bsh;
+  return (c << a.nbl) + min(b, (1u << a.nbl) - 1u);
 }
 
 // Phase timestamps of the bin kernel, compiled in only with
@@ -1228,17 +1325,71 @@ __device__ int64_t chunk_slow(ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x,
 // bin kernel: one workgroup per bin of w consecutive columns
 // ---------------------------------------------------------------------------
 
-// Fast path: the bin's triplets fit the LDS.  Columns are known per triplet
-// (bcol), so equal (column,row) pairs are grouped by hashing straight away;
-// the distinct rows of each column are ranked, contributions of a pair are
-// put in increasing k and folded from +0.0.  Returns base + distinct count.
+// Where the bins are and how blocks take them.
+struct BinSrc {
+  const int32_t* binstart;  // [B+1] (counted modes)
+  const uint32_t* binfill;  // [B] (fixed-capacity mode)
+  const uint32_t* bcol;     // in-bin columns, or null for packed keys
+  int32_t slotcap;          // > 0: bin q owns places [q*slotcap, (q+1)*slotcap)
+  int32_t B;
+  uint32_t* tick;
+};
+
+// A bin's range in the bucket and, when it fits the LDS, its entries in
+// registers: the bin kernel loads the next bin while finishing the current.
+template <typename VT, int EPT>
+struct BinRegs {
+  int q, e0, e1;
+  Entry<VT> en[EPT];
+};
+
+// Issue the loads of bin q's range.  The same three words are read in every
+// mode (binstart always has B+1 entries and binfill B), and nothing is
+// computed from them yet, so the loads stay in flight until bin_range.
+template <typename VT, int EPT>
+__device__ __forceinline__ void bin_bounds(const BinSrc& src, BinRegs<VT, EPT>& r,
+                                           uint32_t& fill) {
+  r.e0 = src.binstart[r.q];
+  r.e1 = src.binstart[r.q + 1];
+  fill = src.binfill[r.q];
+}
+
+template <typename VT, int EPT>
+__device__ __forceinline__ void bin_range(const BinSrc& src, BinRegs<VT, EPT>& r,
+                                          uint32_t fill) {
+  if (src.slotcap > 0) {
+    r.e0 = r.q * src.slotcap;
+    r.e1 = r.e0 + (int)min(fill, (uint32_t)src.slotcap);
+  }
+}
+
+template <typename VT, int NT, int EPT>
+__device__ __forceinline__ void bin_load(const ChunkArgs<VT>& a, const BinSrc& src,
+                                         BinRegs<VT, EPT>& r) {
+  const int span = r.e1 - r.e0;
+  if (span > a.cap) return;  // slow path: read from the bucket there
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = threadIdx.x + j * NT;
+    if (i < span) r.en[j] = load_entry<VT>(&a.bucket[r.e0 + i]);
+  }
+}
+
+// Fast path: the bin's triplets fit the LDS and are already in registers.
+// Columns are known per triplet, so equal (column,row) pairs are grouped by
+// hashing straight away; the distinct rows of each column are ranked,
+// contributions of a pair are put in increasing k and folded from +0.0.
+// Meanwhile the next bin (ticket `tk`, taken by thread 0) has its range and
+// entries fetched into `nx`.  Returns base + distinct count.
 template <typename VT, int CAP, int NT>
-__device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__ bcol,
-                            const ChunkCtx<VT, CAP, NT>& x, int q, int c0, int c1,
-                            int e0, int e1) {
+__device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
+                            const ChunkCtx<VT, CAP, NT>& x,
+                            const BinRegs<VT, CAP / NT>& cur, int c0, int c1,
+                            uint32_t tk, BinRegs<VT, CAP / NT>& nx) {
   constexpr int EPT = CAP / NT;
   constexpr int H = 2 * CAP;
   const int tid = threadIdx.x;
+  const int q = cur.q, e0 = cur.e0, e1 = cur.e1;
   const int span = e1 - e0;
   const int wc = c1 - c0;
   const uint32_t cmask = (1u << a.rshift) - 1u;  // packed keys only
@@ -1250,20 +1401,23 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
   uint32_t* cnt = x.cnt();
   uint32_t* cd = x.cd();
 
+  // distinct rows are counted per (column, row range) cell, so one scan
+  // gives both the column offsets and a coarse rank; a row is then compared
+  // only with the rows of its own cell
+  const int ncell = wc << a.nbl;
   for (int i = tid; i < H; i += NT) ht[i] = kEmpty;
   for (int i = tid; i < span; i += NT) cnt[i] = 0u;
-  for (int i = tid; i <= wc; i += NT) cd[i] = 0u;
+  for (int i = tid; i <= ncell; i += NT) cd[i] = 0u;
   uint32_t kr[EPT];
   VT vr[EPT];
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int i = tid + j * NT;
     if (i < span) {
-      const Entry<VT> en = load_entry<VT>(&a.bucket[e0 + i]);
-      row[i] = en.row;
-      col[i] = bcol ? bcol[e0 + i] : (en.row & cmask);
-      kr[j] = en.k;
-      vr[j] = en.v;
+      row[i] = cur.en[j].row;
+      col[i] = src.bcol ? src.bcol[e0 + i] : (cur.en[j].row & cmask);
+      kr[j] = cur.en[j].k;
+      vr[j] = cur.en[j].v;
     }
   }
   __syncthreads();
@@ -1286,38 +1440,44 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
       }
       const uint32_t arr = atomicAdd(&cnt[rep], 1u);
       repa[j] = rep | (arr << 16);
-      dpos[j] = (rep == (uint32_t)i) ? atomicAdd(&cd[c], 1u) : kEmpty;
+      dpos[j] = (rep == (uint32_t)i) ? atomicAdd(&cd[rank_cell(a, c, r)], 1u) : kEmpty;
     }
   }
+  if (tid == 0) x.misc()[7] = tk;
   __syncthreads();
+  // next bin: its range now, its entries once the placement is done
+  nx.q = (int)x.misc()[7];
+  uint32_t nfill = 0;
+  if (nx.q < src.B) bin_bounds(src, nx, nfill);
 
   FSP_PHASE(a, q, 3)
   // distinct pairs per column -> offsets; publish the bin's count now, read
   // the prefix of the earlier bins only when emitting
-  const uint32_t D = lds_excl_scan<NT>(cd, wc + 1, x.wave());
+  const uint32_t D = lds_excl_scan<NT>(cd, ncell + 1, x.wave());
   if (tid < 64) lookback_publish(a.status, q, pack_agg((uint64_t)span, D));
   uint32_t* dlist = x.dlist();
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int i = tid + j * NT;
     if (i < span && dpos[j] != kEmpty) {
-      const uint32_t d = cd[col[i]] + dpos[j];
+      const uint32_t r = row[i];
+      const uint32_t d = cd[rank_cell(a, col[i], r)] + dpos[j];
       dlist[d] = (uint32_t)i;
-      drow[d] = row[i];
+      drow[d] = r;
     }
   }
   __syncthreads();
 
   FSP_PHASE(a, q, 4)
-  // rank the distinct rows of every column
+  // rank the distinct rows of every cell
   uint32_t* gout = x.gout();
   uint32_t* gs = x.gs();
   uint32_t* grow = x.grow();
   for (int d = tid; d < (int)D; d += NT) {
     const uint32_t i = dlist[d];
-    const uint32_t c = col[i];
     const uint32_t r0 = drow[d];
-    const uint32_t lo = cd[c], hi = cd[c + 1];
+    const uint32_t cell = rank_cell(a, col[i], r0);
+    const uint32_t lo = cd[cell], hi = cd[cell + 1];
     // count smaller rows; eight independent reads in flight per step
     uint32_t r8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     uint32_t t = lo;
@@ -1362,6 +1522,12 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
       mgrp[posr[j]] = orr[j];
     }
   }
+  if (nx.q < src.B) {
+    bin_range(src, nx, nfill);
+    bin_load<VT, NT, EPT>(a, src, nx);
+  }
+  uint64_t probe = 0;
+  if (tid < 64) probe = lookback_probe(a.status, q);
   __syncthreads();
   // order each group by k: values go straight to their sorted place (the
   // column-end / count arrays are free by now), so do the k of the plan
@@ -1387,7 +1553,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
   }
   FSP_PHASE(a, q, 7)
   if (tid < 64) {
-    const int64_t b = lookback_wait(a.status, q, pack_agg((uint64_t)span, D));
+    const int64_t b = lookback_wait(a.status, q, pack_agg((uint64_t)span, D), probe);
     if (tid == 0) {
       x.misc()[1] = b & kLow31;
       x.misc()[5] = (b >> 31) + span;  // compact triplets up to this bin's end
@@ -1433,7 +1599,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const uint32_t* __restrict__
     if (a.seg) a.seg[out] = (int32_t)(e0 + g0 + pshift);
   }
   if (over) atomicOr(&a.ctrl->err, kErrCap);
-  for (int c = tid; c < wc; c += NT) a.jcS[c0 + c] = (int32_t)(base + cd[c]);
+  for (int c = tid; c < wc; c += NT) a.jcS[c0 + c] = (int32_t)(base + cd[c << a.nbl]);
   FSP_PHASE(a, q, 8)
   return base + D;
 }
@@ -1476,46 +1642,64 @@ __device__ int64_t bin_slow(ChunkArgs<VT> a, const uint32_t* __restrict__ bcol,
   return chunk_slow<VT, CAP, NT>(a, x, q, c0, c1);
 }
 
+// Persistent: every block takes bins in ticket order until none is left,
+// fetching the next bin while the current one is processed.  A block waits
+// in the look-back only for bins with smaller tickets, each of which
+// publishes its own count before it waits, so every wait ends.
 template <typename VT, int CAP, int NT>
 __global__ void __launch_bounds__(NT)
-k_bin(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
-      const uint32_t* __restrict__ binfill, int32_t slotcap,
-      const uint32_t* __restrict__ bcol, int32_t* __restrict__ colptr_g,
-      int32_t s, int32_t B) {
+k_bin(ChunkArgs<VT> a, BinSrc src, int32_t* __restrict__ colptr_g, int32_t s) {
+  constexpr int EPT = CAP / NT;
   __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<CAP>::kBytes];
   ChunkCtx<VT, CAP, NT> x{smem};
   int64_t* misc = x.misc();
-#ifdef FSP_PHASE_TIMING
-  const uint64_t tstart = wall_clock64();
-#endif
-  if (threadIdx.x == 0) misc[0] = (int64_t)atomicAdd(&a.ctrl->tick_chunk, 1u);
-  __syncthreads();
-  const int q = (int)misc[0];
-#ifdef FSP_PHASE_TIMING
-  if (a.phase && threadIdx.x == 0) a.phase[(int64_t)q * 16] = tstart;
-#endif
   const int N = a.N;
-  const int c0 = (int)min((int64_t)N, (int64_t)q << s);
-  const int c1 = (int)min((int64_t)N, ((int64_t)q + 1) << s);
-  // bin q's triplets: [binstart[q], binstart[q+1]), or, with fixed-capacity
-  // bins, the first binfill[q] places of [q*slotcap, (q+1)*slotcap)
-  int e0, e1;
-  if (slotcap > 0) {
-    e0 = q * slotcap;
-    e1 = e0 + (int)min(binfill[q], (uint32_t)slotcap);
-  } else {
-    e0 = binstart[q];
-    e1 = binstart[q + 1];
+  const int B = src.B;
+  if (threadIdx.x == 0) misc[0] = (int64_t)atomicAdd(src.tick, 1u);
+  __syncthreads();
+  BinRegs<VT, EPT> cur, nx;
+  cur.q = (int)misc[0];
+  if (cur.q < B) {
+    uint32_t fill;
+    bin_bounds(src, cur, fill);
+    bin_range(src, cur, fill);
+    bin_load<VT, NT, EPT>(a, src, cur);
   }
-  int64_t end;
-  if (e1 - e0 <= a.cap)
-    end = bin_fast<VT, CAP, NT>(a, bcol, x, q, c0, c1, e0, e1);
-  else
-    end = bin_slow<VT, CAP, NT>(a, bcol, colptr_g, x, q, c0, c1, e0, e1);
-  if (q == B - 1 && threadIdx.x == 0) {
-    a.jcS[N] = (int32_t)end;
-    a.ctrl->nnz = end;
-    if (a.seg) a.seg[end] = (int32_t)misc[5];
+  while (cur.q < B) {
+    const int q = cur.q;
+#ifdef FSP_PHASE_TIMING
+    if (a.phase && threadIdx.x == 0) a.phase[(int64_t)q * 16] = wall_clock64();
+#endif
+    const int c0 = (int)min((int64_t)N, (int64_t)q << s);
+    const int c1 = (int)min((int64_t)N, ((int64_t)q + 1) << s);
+    // ticket of the next bin; only thread 0 holds (and later reads) it, so
+    // the value needs no merge with the other lanes and no early wait
+    uint32_t tk;
+    if (threadIdx.x == 0) tk = atomicAdd(src.tick, 1u);
+    int64_t end = 0;
+    if (cur.e1 - cur.e0 <= a.cap) {
+      end = bin_fast<VT, CAP, NT>(a, src, x, cur, c0, c1, tk, nx);
+    } else {
+      end = bin_slow<VT, CAP, NT>(a, src.bcol, colptr_g, x, q, c0, c1, cur.e0,
+                                  cur.e1);
+      __syncthreads();
+      if (threadIdx.x == 0) misc[7] = (int64_t)tk;
+      __syncthreads();
+      nx.q = (int)misc[7];
+      if (nx.q < B) {
+        uint32_t fill;
+        bin_bounds(src, nx, fill);
+        bin_range(src, nx, fill);
+        bin_load<VT, NT, EPT>(a, src, nx);
+      }
+    }
+    if (q == B - 1 && threadIdx.x == 0) {
+      a.jcS[N] = (int32_t)end;
+      a.ctrl->nnz = end;
+      if (a.seg) a.seg[end] = (int32_t)misc[5];
+    }
+    __syncthreads();  // the LDS is reused by the next bin
+    cur = nx;
   }
 }
 
