@@ -243,6 +243,12 @@ fsparse_status fsparse_timing_enable(int on);
 int fsparse_timing_read(double *ms, int64_t *launches, int max_stages);
 const char *fsparse_stage_name(int stage);
 
+/* Restricts timing to the stages whose bit (1 << stage) is set in
+ * stage_mask (all stages by default), so that a timed run carries events
+ * only around the launches it reports.  The setting is process-wide and
+ * stays until changed. */
+fsparse_status fsparse_timing_select(uint32_t stage_mask);
+
 /* Plain device-to-device copy kernel (16-byte vector loads/stores) used to
  * measure attainable HBM bandwidth and to calibrate byte counters.  bytes
  * must be a multiple of 16 and both pointers 16-byte aligned. */

@@ -86,6 +86,7 @@ fsparse_set_tuning = _sig("fsparse_set_tuning", _st,
 fsparse_get_tuning = _sig("fsparse_get_tuning", _st,
                           [ctypes.POINTER(FsparseTuning)])
 fsparse_timing_enable = _sig("fsparse_timing_enable", _st, [ctypes.c_int])
+fsparse_timing_select = _sig("fsparse_timing_select", _st, [ctypes.c_uint32])
 fsparse_timing_read = _sig("fsparse_timing_read", ctypes.c_int,
                            [ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(_i64), ctypes.c_int])
@@ -100,5 +101,6 @@ EXPORTS = [
     "fsparse_plan_destroy",
     "fsparse_plan_query", "fsparse_set_tuning", "fsparse_get_tuning",
     "fsparse_timing_enable", "fsparse_timing_read", "fsparse_stage_name",
+    "fsparse_timing_select",
     "fsparse_stream_copy",
 ]

@@ -421,12 +421,26 @@ def get_tuning() -> dict:
 
 
 class timing:
-    """Context manager: per-stage HIP-event times of the enclosed calls."""
+    """Context manager: per-stage HIP-event times of the enclosed calls.
+
+    ``stages`` (names) limits the events to those stages' launches; the
+    others then run without events in between.
+    """
 
     NSTAGES = 16
 
+    def __init__(self, stages=None):
+        self.mask = 0xFFFFFFFF
+        if stages is not None:
+            names = [L.fsparse_stage_name(s).decode()
+                     for s in range(self.NSTAGES)]
+            self.mask = 0
+            for nm in stages:
+                self.mask |= 1 << names.index(nm)
+
     def __enter__(self):
         L.fsparse_timing_read(None, None, 0)   # drop stale records
+        L.fsparse_timing_select(self.mask)
         L.fsparse_timing_enable(1)
         self.ms = {}
         self.launches = {}
@@ -446,6 +460,7 @@ class timing:
     def __exit__(self, *exc):
         self.read()
         L.fsparse_timing_enable(0)
+        L.fsparse_timing_select(0xFFFFFFFF)
         return False
 
 

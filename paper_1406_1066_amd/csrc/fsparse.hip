@@ -64,6 +64,7 @@ struct Rec {
   hipEvent_t a, b;
 };
 bool g_timing = false;
+uint32_t g_stage_mask = 0xFFFFFFFFu;  // stages bracketed while timing
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;  // recycled timing events
 double g_ms[kNumStages];
@@ -74,7 +75,7 @@ hipError_t launch(int stage, hipStream_t s, F&& f) {
   bool timing;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    timing = g_timing;
+    timing = g_timing && stage >= 0 && stage < 32 && ((g_stage_mask >> stage) & 1u);
   }
   if (!timing) {
     f();
@@ -208,8 +209,17 @@ Geom make_geom(int64_t L, int64_t N, int cap, int force_mode) {
   g.B = std::max<int64_t>(1, (N + w - 1) / w);
   g.dense = g.B <= kDenseBins;
   if (g.dense) {
+    // tiles x bins count matrix: at most kDenseMatrix words, and while at
+    // least 512 tiles remain, at most L/4 words (its passes then move about
+    // a byte per triplet)
     g.TS = 4096;
-    while (((L + g.TS - 1) / g.TS) * g.B > kDenseMatrix && g.TS < (1 << 22)) g.TS *= 2;
+    for (;;) {
+      const int64_t T = (L + g.TS - 1) / g.TS;
+      const bool big = T * g.B > kDenseMatrix;
+      const bool heavy = T * g.B > L / 4 && T / 2 >= 512;
+      if (!(big || heavy) || g.TS >= (1 << 22)) break;
+      g.TS *= 2;
+    }
   } else {
     g.TS = (int64_t)kClaimNT * kClaimIPT;
   }
@@ -1066,6 +1076,12 @@ fsparse_status fsparse_get_tuning(fsparse_tuning* t) {
 fsparse_status fsparse_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_timing = on != 0;
+  return FSPARSE_OK;
+}
+
+fsparse_status fsparse_timing_select(uint32_t stage_mask) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_stage_mask = stage_mask;
   return FSPARSE_OK;
 }
 

@@ -1423,24 +1423,45 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   __syncthreads();
 
   FSP_PHASE(a, q, 2)
-  // group equal (column,row) pairs
-  uint32_t repa[EPT], dpos[EPT];
+  // group equal (column,row) pairs.  The first probes of all of a thread's
+  // triplets are issued together, then collisions are resolved, then the
+  // group and cell counters are bumped, so the LDS atomics overlap.
+  uint32_t repa[EPT], dpos[EPT], hh[EPT], cell[EPT];
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int i = tid + j * NT;
     if (i < span) {
       const uint32_t c = col[i], r = row[i];
-      uint32_t h = pair_hash(c, r) & (H - 1);
-      uint32_t rep;
-      for (;;) {
-        const uint32_t old = atomicCAS(&ht[h], kEmpty, (uint32_t)i);
-        if (old == kEmpty) { rep = (uint32_t)i; break; }
-        if (col[old] == c && row[old] == r) { rep = old; break; }
-        h = (h + 1) & (H - 1);
+      cell[j] = rank_cell(a, c, r);
+      hh[j] = pair_hash(c, r) & (H - 1);
+      repa[j] = atomicCAS(&ht[hh[j]], kEmpty, (uint32_t)i);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = tid + j * NT;
+    if (i < span) {
+      // an empty slot was claimed (this triplet represents its pair), or the
+      // slot holds the same pair, or probing goes on
+      uint32_t old = repa[j], h = hh[j], rep = (uint32_t)i;
+      if (old != kEmpty) {
+        const uint32_t c = col[i], r = row[i];
+        while (old != kEmpty) {
+          if (col[old] == c && row[old] == r) { rep = old; break; }
+          h = (h + 1) & (H - 1);
+          old = atomicCAS(&ht[h], kEmpty, (uint32_t)i);
+        }
       }
-      const uint32_t arr = atomicAdd(&cnt[rep], 1u);
-      repa[j] = rep | (arr << 16);
-      dpos[j] = (rep == (uint32_t)i) ? atomicAdd(&cd[rank_cell(a, c, r)], 1u) : kEmpty;
+      repa[j] = rep;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = tid + j * NT;
+    if (i < span) {
+      const uint32_t arr = atomicAdd(&cnt[repa[j]], 1u);
+      dpos[j] = (repa[j] == (uint32_t)i) ? atomicAdd(&cd[cell[j]], 1u) : kEmpty;
+      repa[j] |= arr << 16;
     }
   }
   if (tid == 0) x.misc()[7] = tk;
@@ -1644,8 +1665,11 @@ __device__ int64_t bin_slow(ChunkArgs<VT> a, const uint32_t* __restrict__ bcol,
 
 // Persistent: every block takes bins in ticket order until none is left,
 // fetching the next bin while the current one is processed.  A block waits
-// in the look-back only for bins with smaller tickets, each of which
-// publishes its own count before it waits, so every wait ends.
+// in the look-back only for bins with smaller tickets.  Every started bin
+// publishes its count before it waits, and the smallest ticket not yet
+// published is always either being processed or the next bin of a block
+// whose current bin has only published bins before it, so every wait ends.
+// A block holds at most one ticket beyond the bin it processes.
 template <typename VT, int CAP, int NT>
 __global__ void __launch_bounds__(NT)
 k_bin(ChunkArgs<VT> a, BinSrc src, int32_t* __restrict__ colptr_g, int32_t s) {
