@@ -139,6 +139,12 @@ def main():
     import numpy as np
     import torch
 
+    # tuning choices are cached per device and input class; keep the cache
+    # where every process of this machine finds it
+    import tempfile
+    os.environ.setdefault("FSPARSE_TUNE_CACHE",
+                          os.path.join(tempfile.gettempdir(),
+                                       "fsparse_mi355x_tune.json"))
     import paper_1406_1066_amd as fs
     import workloads as W
 
