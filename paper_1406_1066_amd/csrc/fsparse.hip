@@ -242,6 +242,7 @@ struct Layout {
   int64_t mmax;  // largest m over the matrices (batched)
   size_t ctrl, scan_st, bin_st, bincnt, binfill, bmax, zero_end;
   size_t binstart, cntmat, bcol, colptr, bucket, tmp, perm, seg, islot, rtile;
+  size_t slowlist, slowd, slowb;
   size_t b_trip, b_col, b_m, b_n, jcg, nnzoff;
   size_t total;
   int64_t nscan;
@@ -271,6 +272,9 @@ Layout make_layout(int64_t L, int64_t N, int nb, int esize, const Tuning& tu) {
   o.seg = p;         p = al(p + 4 * (size_t)(L + 1));
   o.islot = p;       p = al(p + 4 * (size_t)L);
   o.rtile = p;       p = al(p + 4 * (size_t)(L / kReuseTP + 3));
+  o.slowlist = p;    p = al(p + 4 * (size_t)B);
+  o.slowd = p;       p = al(p + 4 * (size_t)B);
+  o.slowb = p;       p = al(p + 8 * (size_t)B);
   o.b_trip = p;      p = al(p + 8 * (size_t)(nb + 1));
   o.b_col = p;       p = al(p + 8 * (size_t)(nb + 1));
   o.b_m = p;         p = al(p + 4 * (size_t)nb);
@@ -472,7 +476,8 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   if (mode != kSlot) e = launch(kScan, stream, [&] {
     hipLaunchKernelGGL((fsp::k_scan_excl<kScanNT, kScanIPT>), dim3((unsigned)lo.nscan),
                        dim3(kScanNT), 0, stream, bincnt, B, binstart,
-                       at<uint64_t>(ws, lo.scan_st), &ctrl->tick_scan);
+                       at<uint64_t>(ws, lo.scan_st), &ctrl->tick_scan,
+                       (uint32_t)tu.cap, &ctrl->nslow, at<int32_t>(ws, lo.slowlist));
   });
   if (e != hipSuccess) return e;
   // 3. scatter into the bins
@@ -529,12 +534,25 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   int32_t* colptr_g = at<int32_t>(ws, lo.colptr);
   const int kc = kernel_cap(tu.cap);
   const int nt = std::max(kc / 8, std::min(tu.cblock, kc));  // <= 8 triplets per thread
-  fsp::BinSrc src{binstart, binfill, bcol_in, slotcap, (int32_t)B, &ctrl->tick_chunk};
+  int32_t* slowlist = at<int32_t>(ws, lo.slowlist);
+  uint32_t* slowd = at<uint32_t>(ws, lo.slowd);
+  uint64_t* slowb = at<uint64_t>(ws, lo.slowb);
+  fsp::BinSrc src{binstart, binfill, bcol_in, slotcap, (int32_t)B, &ctrl->tick_chunk,
+                  slowd, slowb};
+  const unsigned sgrid = (unsigned)num_cus();
+  // bins longer than the LDS: counted before the bin kernel, emitted after
   e = launch(kChunk, stream, [&] {
 #define FSP_BIN(C, T)                                                          \
-  hipLaunchKernelGGL((fsp::k_bin<VT, C, T>),                                   \
-                     dim3((unsigned)std::min<int64_t>(B, resident(fsp::k_bin<VT, C, T>, T))), \
-                     dim3(T), 0, stream, a, src, colptr_g, s)
+  do {                                                                         \
+    hipLaunchKernelGGL((fsp::k_slow_count<VT, C, T>), dim3(sgrid), dim3(T), 0,  \
+                       stream, a, binstart, bcol_in, colptr_g, s, slowlist,   \
+                       slowd);                                                 \
+    hipLaunchKernelGGL((fsp::k_bin<VT, C, T>),                                 \
+                       dim3((unsigned)std::min<int64_t>(B, resident(fsp::k_bin<VT, C, T>, T))), \
+                       dim3(T), 0, stream, a, src, s);                         \
+    hipLaunchKernelGGL((fsp::k_slow_emit<VT, C, T>), dim3(sgrid), dim3(T), 0,   \
+                       stream, a, binstart, colptr_g, s, slowlist, slowb);     \
+  } while (0)
     if (kc == 1024) {
       if (nt <= 256) FSP_BIN(1024, 256); else if (nt <= 512) FSP_BIN(1024, 512); else FSP_BIN(1024, 1024);
     } else if (kc == 2048) {

@@ -47,7 +47,7 @@ struct Ctrl {
   uint32_t err;
   uint32_t tick_scan;
   uint32_t tick_chunk;
-  uint32_t pad0;
+  uint32_t nslow;  // bins longer than the LDS capacity, listed by the bin scan
   int64_t nnz;
   int64_t ltot;
   int32_t rmin, rmax, cmin, cmax;  // dims pass
@@ -474,10 +474,12 @@ __device__ __forceinline__ int tile_first_mat(const BatchDesc& bd, int64_t t0,
 
 // Exclusive scan of in[0..n) (decoupled look-back) into out[0..n]; out[n]
 // is the total.
+// Bins above `cap` are appended to slowlist (count in *nslow).
 template <int NT, int IPT>
 __global__ void __launch_bounds__(NT)
 k_scan_excl(const uint32_t* __restrict__ in, int32_t n, int32_t* __restrict__ out,
-            uint64_t* status, uint32_t* ticket) {
+            uint64_t* status, uint32_t* ticket, uint32_t cap,
+            uint32_t* __restrict__ nslow, int32_t* __restrict__ slowlist) {
   __shared__ uint32_t sWave[NT / 64];
   __shared__ int sTile;
   __shared__ int64_t sBase;
@@ -504,6 +506,7 @@ k_scan_excl(const uint32_t* __restrict__ in, int32_t n, int32_t* __restrict__ ou
   for (int j = 0; j < IPT; ++j) {
     if (i0 + j <= n) out[i0 + j] = (int32_t)run;
     run += v[j];
+    if (v[j] > cap) slowlist[atomicAdd(nslow, 1u)] = (int32_t)(i0 + j);
   }
 }
 
@@ -1247,78 +1250,61 @@ __device__ void long_emit(const ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x
 
 // Columns [cb, cl) whose triplets do not fit the LDS at once: they are taken
 // in batches of consecutive columns that fit, and columns longer than the
-// capacity take the long path.  Two sweeps: count, look-back, emit.
+// capacity take the long path.  One sweep either counts the distinct pairs
+// (emit false; long columns are sorted here) or emits them from output
+// offset `off` on (a.pshift set).  Returns the offset after the last pair.
 template <typename VT, int CAP, int NT>
-__device__ int64_t chunk_slow(ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x,
-                              int q, int cb, int cl) {
+__device__ int64_t chunk_sweep(ChunkArgs<VT>& a, const ChunkCtx<VT, CAP, NT>& x,
+                               int cb, int cl, bool emit, int64_t off) {
   int64_t* misc = x.misc();
-  int64_t base = 0;
-  for (int sweep = 0; sweep < 2; ++sweep) {
-    int64_t off = base;
-    int c = cb;
-    while (c < cl) {
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        // largest ce in (c, cl] with colptr[ce] - colptr[c] <= cap
-        const int64_t lim = (int64_t)a.colptr[c] + a.cap;
-        int lo = c, hi = cl;  // colptr[lo] - colptr[c] <= cap
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (a.colptr[mid] <= lim) lo = mid; else hi = mid - 1;
-        }
-        misc[2] = (lo == c) ? c + 1 : lo;
-        misc[3] = (lo == c) ? 1 : 0;
+  int c = cb;
+  while (c < cl) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      // largest ce in (c, cl] with colptr[ce] - colptr[c] <= cap
+      const int64_t lim = (int64_t)a.colptr[c] + a.cap;
+      int lo = c, hi = cl;  // colptr[lo] - colptr[c] <= cap
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.colptr[mid] <= lim) lo = mid; else hi = mid - 1;
       }
-      __syncthreads();
-      const int ce = (int)misc[2];
-      const bool is_long = misc[3] != 0;
-      const int e0 = a.colptr[c], e1 = a.colptr[ce];
-      uint32_t D;
-      if (is_long) {
-        int where;
-        if (sweep == 0) {
-          where = long_sort<VT, CAP, NT>(a, x, e0, e1 - e0);
-        } else {
-          // same pass count as in the first sweep
-          where = 1;
-          for (int w = a.cap; w < e1 - e0; w <<= 1) where ^= 1;
-        }
-        const Entry<VT>* s = where ? a.tmp : a.bucket;
-        D = long_count<VT, NT>(s, e0, e1 - e0, x.wave());
-        if (sweep == 1) {
-          if (threadIdx.x == 0) a.jcS[c] = (int32_t)off;
-          long_emit<VT, CAP, NT>(a, x, s, e0, e1 - e0, off);
-        }
-      } else if (sweep == 0) {
-        D = batch<VT, CAP, NT, false>(a, x, c, ce, e0, e1,
-                                      [](uint32_t) -> int64_t { return 0; });
-        __syncthreads();
-      } else {
-        const int64_t o = off;
-        D = batch<VT, CAP, NT, true>(a, x, c, ce, e0, e1,
-                                     [o](uint32_t) -> int64_t { return o; });
-      }
-      off += D;
-      c = ce;
+      misc[2] = (lo == c) ? c + 1 : lo;
+      misc[3] = (lo == c) ? 1 : 0;
     }
     __syncthreads();
-    if (sweep == 0) {
-      const int64_t e0c = a.colptr[cb < cl ? cb : cl];
-      const int64_t e1c = a.colptr[cl];
-      if (threadIdx.x < 64) {
-        const int64_t b = lookback(a.status, q,
-                                   pack_agg((uint64_t)(e1c - e0c), (uint64_t)(off - base)));
-        if (threadIdx.x == 0) misc[4] = b;
+    const int ce = (int)misc[2];
+    const bool is_long = misc[3] != 0;
+    const int e0 = a.colptr[c], e1 = a.colptr[ce];
+    uint32_t D;
+    if (is_long) {
+      int where;
+      if (!emit) {
+        where = long_sort<VT, CAP, NT>(a, x, e0, e1 - e0);
+      } else {
+        // same pass count as in the counting sweep
+        where = 1;
+        for (int w = a.cap; w < e1 - e0; w <<= 1) where ^= 1;
       }
+      const Entry<VT>* s = where ? a.tmp : a.bucket;
+      D = long_count<VT, NT>(s, e0, e1 - e0, x.wave());
+      if (emit) {
+        if (threadIdx.x == 0) a.jcS[c] = (int32_t)off;
+        long_emit<VT, CAP, NT>(a, x, s, e0, e1 - e0, off);
+      }
+    } else if (!emit) {
+      D = batch<VT, CAP, NT, false>(a, x, c, ce, e0, e1,
+                                    [](uint32_t) -> int64_t { return 0; });
       __syncthreads();
-      base = misc[4] & kLow31;
-      a.pshift = (misc[4] >> 31) - e0c;
-      if (threadIdx.x == 0) misc[5] = (misc[4] >> 31) + (e1c - e0c);
     } else {
-      return off;  // base + distinct count of the chunk
+      const int64_t o = off;
+      D = batch<VT, CAP, NT, true>(a, x, c, ce, e0, e1,
+                                   [o](uint32_t) -> int64_t { return o; });
     }
+    off += D;
+    c = ce;
   }
-  return base;
+  __syncthreads();
+  return off;
 }
 
 // ---------------------------------------------------------------------------
@@ -1333,6 +1319,8 @@ struct BinSrc {
   int32_t slotcap;          // > 0: bin q owns places [q*slotcap, (q+1)*slotcap)
   int32_t B;
   uint32_t* tick;
+  const uint32_t* slowD;    // distinct pairs of each slow bin
+  uint64_t* slowB;          // look-back prefix of each slow bin (written)
 };
 
 // A bin's range in the bucket and, when it fits the LDS, its entries in
@@ -1625,15 +1613,21 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   return base + D;
 }
 
-// Slow path: the bin holds more triplets than the LDS.  Sort it by column
-// into the scratch array (counting sort in LDS over the bin's columns), write
-// the bin's column pointers, and hand over to the batched / long-column
-// processing, which reads the column-sorted copy.
+// Bins with more triplets than the LDS holds ("slow" bins) are listed by the
+// bin scan and handled outside the bin kernel: k_slow_count sorts each by
+// column into the scratch array and counts its distinct pairs, the bin
+// kernel only passes that count through the look-back (recording the
+// prefix), and k_slow_emit emits the bin from the recorded prefix.  Between
+// the two, the bin kernel touches no slow bin's data.
+
+// Column-sorts slow bin [e0, e1) (columns [c0, c1)) into the scratch array
+// by a counting sort in LDS, writes its column pointers, and points `a` at
+// the sorted copy.
 template <typename VT, int CAP, int NT>
-__device__ int64_t bin_slow(ChunkArgs<VT> a, const uint32_t* __restrict__ bcol,
-                            int32_t* __restrict__ colptr_g,
-                            const ChunkCtx<VT, CAP, NT>& x, int q, int c0, int c1,
-                            int e0, int e1) {
+__device__ void slow_sort(ChunkArgs<VT>& a, const uint32_t* __restrict__ bcol,
+                          int32_t* __restrict__ colptr_g,
+                          const ChunkCtx<VT, CAP, NT>& x, int c0, int c1, int e0,
+                          int e1) {
   const int tid = threadIdx.x;
   const int span = e1 - e0;
   const int wc = c1 - c0;
@@ -1660,7 +1654,62 @@ __device__ int64_t bin_slow(ChunkArgs<VT> a, const uint32_t* __restrict__ bcol,
   Entry<VT>* t = a.bucket;
   a.bucket = a.tmp;
   a.tmp = t;
-  return chunk_slow<VT, CAP, NT>(a, x, q, c0, c1);
+}
+
+// Range of bin q in the bucket (counted modes; slow bins never occur with
+// fixed-capacity bins).
+__device__ __forceinline__ void slow_range(const int32_t* __restrict__ binstart, int q,
+                                           int& e0, int& e1) {
+  e0 = binstart[q];
+  e1 = binstart[q + 1];
+}
+
+template <typename VT, int CAP, int NT>
+__global__ void __launch_bounds__(NT)
+k_slow_count(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
+             const uint32_t* __restrict__ bcol, int32_t* __restrict__ colptr_g,
+             int32_t s, const int32_t* __restrict__ slowlist,
+             uint32_t* __restrict__ slowD) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<CAP>::kBytes];
+  ChunkCtx<VT, CAP, NT> x{smem};
+  const int nslow = (int)a.ctrl->nslow;
+  for (int i = blockIdx.x; i < nslow; i += gridDim.x) {
+    const int q = slowlist[i];
+    int e0, e1;
+    slow_range(binstart, q, e0, e1);
+    const int c0 = (int)min((int64_t)a.N, (int64_t)q << s);
+    const int c1 = (int)min((int64_t)a.N, ((int64_t)q + 1) << s);
+    ChunkArgs<VT> b = a;
+    slow_sort<VT, CAP, NT>(b, bcol, colptr_g, x, c0, c1, e0, e1);
+    const int64_t D = chunk_sweep<VT, CAP, NT>(b, x, c0, c1, false, 0);
+    if (threadIdx.x == 0) slowD[q] = (uint32_t)D;
+  }
+}
+
+template <typename VT, int CAP, int NT>
+__global__ void __launch_bounds__(NT)
+k_slow_emit(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
+            int32_t* __restrict__ colptr_g, int32_t s,
+            const int32_t* __restrict__ slowlist,
+            const uint64_t* __restrict__ slowB) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<CAP>::kBytes];
+  ChunkCtx<VT, CAP, NT> x{smem};
+  const int nslow = (int)a.ctrl->nslow;
+  for (int i = blockIdx.x; i < nslow; i += gridDim.x) {
+    const int q = slowlist[i];
+    int e0, e1;
+    slow_range(binstart, q, e0, e1);
+    const int c0 = (int)min((int64_t)a.N, (int64_t)q << s);
+    const int c1 = (int)min((int64_t)a.N, ((int64_t)q + 1) << s);
+    ChunkArgs<VT> b = a;
+    b.colptr = colptr_g;  // the copy sorted by k_slow_count
+    Entry<VT>* t = b.bucket;
+    b.bucket = b.tmp;
+    b.tmp = t;
+    const uint64_t pre = slowB[q];
+    b.pshift = (int64_t)(pre >> 31) - e0;
+    chunk_sweep<VT, CAP, NT>(b, x, c0, c1, true, (int64_t)(pre & kLow31));
+  }
 }
 
 // Persistent: every block takes bins in ticket order until none is left,
@@ -1672,7 +1721,7 @@ __device__ int64_t bin_slow(ChunkArgs<VT> a, const uint32_t* __restrict__ bcol,
 // A block holds at most one ticket beyond the bin it processes.
 template <typename VT, int CAP, int NT>
 __global__ void __launch_bounds__(NT)
-k_bin(ChunkArgs<VT> a, BinSrc src, int32_t* __restrict__ colptr_g, int32_t s) {
+k_bin(ChunkArgs<VT> a, BinSrc src, int32_t s) {
   constexpr int EPT = CAP / NT;
   __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<CAP>::kBytes];
   ChunkCtx<VT, CAP, NT> x{smem};
@@ -1704,9 +1753,20 @@ k_bin(ChunkArgs<VT> a, BinSrc src, int32_t* __restrict__ colptr_g, int32_t s) {
     if (cur.e1 - cur.e0 <= a.cap) {
       end = bin_fast<VT, CAP, NT>(a, src, x, cur, c0, c1, tk, nx);
     } else {
-      end = bin_slow<VT, CAP, NT>(a, src.bcol, colptr_g, x, q, c0, c1, cur.e0,
-                                  cur.e1);
+      // a slow bin: counted before this kernel, emitted after it; here its
+      // count only passes through the look-back
+      const int span = cur.e1 - cur.e0;
+      if (threadIdx.x < 64) {
+        const uint32_t D = src.slowD[q];
+        const int64_t b = lookback(a.status, q, pack_agg((uint64_t)span, D));
+        if (threadIdx.x == 0) {
+          src.slowB[q] = (uint64_t)b;
+          misc[1] = (b & kLow31) + D;
+          misc[5] = (b >> 31) + span;  // compact triplets up to this bin's end
+        }
+      }
       __syncthreads();
+      end = misc[1];
       if (threadIdx.x == 0) misc[7] = (int64_t)tk;
       __syncthreads();
       nx.q = (int)misc[7];
