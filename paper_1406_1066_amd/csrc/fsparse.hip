@@ -520,11 +520,11 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   a.rshift = packed ? s : 0;
   {
     // rank cells: split a column's rows into 2^nbl ranges so that a range
-    // holds about two distinct rows of an average column, within the LDS
-    // table of cap + 1 cells
+    // holds about two distinct rows of an average column, with at most 256
+    // cells per bin (one wave then scans them)
     const int64_t per_col = std::max<int64_t>(1, L / std::max<int64_t>(1, N));
     int nbl = 0;
-    while ((int64_t(4) << nbl) <= per_col && ((int64_t)g.w << (nbl + 1)) <= tu.cap) ++nbl;
+    while ((int64_t(4) << nbl) <= per_col && ((int64_t)g.w << (nbl + 1)) <= 256) ++nbl;
     int rowbits = 0;
     while ((int64_t(1) << rowbits) < mmax) ++rowbits;
     a.nbl = nbl;

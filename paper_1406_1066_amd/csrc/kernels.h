@@ -1504,11 +1504,36 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   if (tid == 0) gs[D] = 0;
   __syncthreads();
   FSP_PHASE(a, q, 5)
-  lds_excl_scan<NT>(gs, (int)D + 1, x.wave());
+  // every pair occurs once (common for scattered inputs): group o is the
+  // single place o, so there is nothing to scan and nothing to order by k
+  const bool uniq = D == (uint32_t)span;
+  if (!uniq) lds_excl_scan<NT>(gs, (int)D + 1, x.wave());
   FSP_PHASE(a, q, 6)
 
-  // place triplets into their groups, then order each group by k
+  VT* sval = reinterpret_cast<VT*>(x.cend());  // free since the rank
+  uint32_t* mk = row;
+  uint32_t* mgrp = col;
   uint32_t posr[EPT], orr[EPT];
+  uint32_t spos[EPT];  // sorted position of a triplet (own, or placed)
+  uint64_t probe = 0;
+  if (uniq) {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int i = tid + j * NT;
+      if (i < span) {
+        const uint32_t o = gout[i];
+        orr[j] = o;
+        spos[j] = o;
+        sval[o] = vr[j];
+      }
+    }
+    if (nx.q < src.B) {
+      bin_range(src, nx, nfill);
+      bin_load<VT, NT, EPT>(a, src, nx);
+    }
+    if (tid < 64) probe = lookback_probe(a.status, q);
+  } else {
+  // place triplets into their groups, then order each group by k
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int i = tid + j * NT;
@@ -1520,8 +1545,6 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   }
   __syncthreads();
   VT* mval = x.mval();
-  uint32_t* mk = row;
-  uint32_t* mgrp = col;
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int i = tid + j * NT;
@@ -1535,13 +1558,10 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
     bin_range(src, nx, nfill);
     bin_load<VT, NT, EPT>(a, src, nx);
   }
-  uint64_t probe = 0;
   if (tid < 64) probe = lookback_probe(a.status, q);
   __syncthreads();
-  // order each group by k: values go straight to their sorted place (the
-  // column-end / count arrays are free by now), so do the k of the plan
-  VT* sval = reinterpret_cast<VT*>(x.cend());
-  uint32_t spos[EPT];  // sorted position of this thread's placed triplets
+  // order each group by k: values go straight to their sorted place, so do
+  // the k of the plan
 #pragma unroll
   for (int jj = 0; jj < EPT; ++jj) {
     const int p = tid + jj * NT;
@@ -1560,6 +1580,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
     sval[g0 + rk] = mval[p];
     spos[jj] = g0 + rk;
   }
+  }
   FSP_PHASE(a, q, 7)
   if (tid < 64) {
     const int64_t b = lookback_wait(a.status, q, pack_agg((uint64_t)span, D), probe);
@@ -1575,18 +1596,30 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   // emit
   const int64_t base = x.misc()[1];
   const int64_t pshift = x.misc()[6];
+  // perm and slot: from the thread's own triplets (uniq), else from the
+  // placed ones
   if (a.perm) {
 #pragma unroll
     for (int jj = 0; jj < EPT; ++jj) {
       const int p = tid + jj * NT;
-      if (p < span) a.perm[e0 + spos[jj] + pshift] = (int32_t)mk[p];
+      if (p < span) a.perm[e0 + spos[jj] + pshift] = (int32_t)(uniq ? kr[jj] : mk[p]);
     }
   }
-  if (a.slot)
-    for (int p = tid; p < span; p += NT) a.slot[mk[p]] = (int32_t)(base + mgrp[p]);
+  if (a.slot) {
+    if (uniq) {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int i = tid + j * NT;
+        if (i < span) a.slot[kr[j]] = (int32_t)(base + orr[j]);
+      }
+    } else {
+      for (int p = tid; p < span; p += NT) a.slot[mk[p]] = (int32_t)(base + mgrp[p]);
+    }
+  }
   bool over = false;
   for (int o = tid; o < (int)D; o += NT) {
-    const uint32_t g0 = gs[o], g1 = gs[o + 1];
+    const uint32_t g0 = uniq ? (uint32_t)o : gs[o];
+    const uint32_t g1 = uniq ? (uint32_t)o + 1u : gs[o + 1];
     // left fold from +0.0 in increasing k; loads four ahead
     VT acc = (VT)0;
     uint32_t t = g0;
