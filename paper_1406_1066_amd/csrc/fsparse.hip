@@ -128,6 +128,11 @@ int num_cus() {
 }
 
 // Blocks of `kernel` that fit the device at once (persistent launches).
+// The larger of the runtime's occupancy figure and one computed from the
+// kernel's own LDS and register use (64 KB of VGPRs per SIMD lane group: 512
+// per lane, at most 8 waves per SIMD, 4 SIMDs per CU).  More blocks than
+// fit is harmless for the ticket-driven kernels (late blocks find no work),
+// fewer would leave CUs idle.
 template <typename K>
 int64_t resident(K kernel, int block) {
   // one cache per kernel instantiation (each is launched with one block size)
@@ -135,10 +140,25 @@ int64_t resident(K kernel, int block) {
   const int dev = cur_device();
   int per = cache[dev].load(std::memory_order_relaxed);
   if (per <= 0) {
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) !=
-            hipSuccess ||
-        per <= 0)
-      per = 1;
+    int api = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&api, kernel, block, 0) !=
+        hipSuccess)
+      api = 0;
+    int own = 0;
+    hipFuncAttributes fa{};
+    int lds_cu = 0;
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel)) == hipSuccess &&
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              dev) == hipSuccess &&
+        lds_cu > 0) {
+      const int by_lds = fa.sharedSizeBytes > 0 ? lds_cu / (int)fa.sharedSizeBytes : 32;
+      const int regs = std::max(8, (fa.numRegs + 7) / 8 * 8);
+      const int wpsimd = std::min(8, 512 / regs);
+      const int wblk = (block + 63) / 64;
+      const int by_waves = (4 * wpsimd) / std::max(1, wblk);
+      own = std::min(by_lds, by_waves);
+    }
+    per = std::max(1, std::max(api, own));
     cache[dev].store(per, std::memory_order_relaxed);
   }
   return (int64_t)per * num_cus();
@@ -175,6 +195,7 @@ constexpr int kScanNT = 256;
 constexpr int kScanIPT = 16;
 constexpr int64_t kScanTile = (int64_t)kScanNT * kScanIPT;
 constexpr int64_t kDenseBins = 16384;       // LDS counters of the dense mode
+constexpr int kBinFill = 80;                // percent of the capacity per bin
 constexpr int64_t kDenseMatrix = 8 << 20;   // tiles x bins counters
 constexpr int kClaimNT = 256;
 constexpr int kClaimIPT = 16;
@@ -200,7 +221,11 @@ Geom make_geom(int64_t L, int64_t N, int cap, int force_mode) {
   Geom g{};
   int64_t w = 1;
   if (L > 0) {
-    const double target = (double)std::max(1, cap / 2) * (double)N / (double)L;
+    // an average bin fills kBinFill percent of the LDS capacity: a bin's
+    // cost is mostly latency, so fuller bins mean fewer of them; a bin that
+    // still overflows takes the slow path
+    const double target =
+        std::max(1.0, (double)cap * kBinFill / 100.0) * (double)N / (double)L;
     while (w * 2 <= target && w * 2 <= cap) w *= 2;
   }
   g.w = w;
