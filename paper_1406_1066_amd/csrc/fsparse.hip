@@ -566,17 +566,21 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
                   slowd, slowb};
   const unsigned sgrid = (unsigned)num_cus();
   // bins longer than the LDS: counted before the bin kernel, emitted after
+  // (fixed-capacity bins never are)
+  const bool may_slow = mode != kSlot;
   e = launch(kChunk, stream, [&] {
 #define FSP_BIN(C, T)                                                          \
   do {                                                                         \
-    hipLaunchKernelGGL((fsp::k_slow_count<VT, C, T>), dim3(sgrid), dim3(T), 0,  \
-                       stream, a, binstart, bcol_in, colptr_g, s, slowlist,   \
-                       slowd);                                                 \
+    if (may_slow)                                                              \
+      hipLaunchKernelGGL((fsp::k_slow_count<VT, C, T>), dim3(sgrid), dim3(T), 0, \
+                         stream, a, binstart, bcol_in, colptr_g, s, slowlist, \
+                         slowd);                                               \
     hipLaunchKernelGGL((fsp::k_bin<VT, C, T>),                                 \
                        dim3((unsigned)std::min<int64_t>(B, resident(fsp::k_bin<VT, C, T>, T))), \
                        dim3(T), 0, stream, a, src, s);                         \
-    hipLaunchKernelGGL((fsp::k_slow_emit<VT, C, T>), dim3(sgrid), dim3(T), 0,   \
-                       stream, a, binstart, colptr_g, s, slowlist, slowb);     \
+    if (may_slow)                                                              \
+      hipLaunchKernelGGL((fsp::k_slow_emit<VT, C, T>), dim3(sgrid), dim3(T), 0, \
+                         stream, a, binstart, colptr_g, s, slowlist, slowb);   \
   } while (0)
     if (kc == 1024) {
       if (nt <= 256) FSP_BIN(1024, 256); else if (nt <= 512) FSP_BIN(1024, 512); else FSP_BIN(1024, 1024);
