@@ -447,16 +447,34 @@ __device__ __forceinline__ Entry<float> load_entry<float>(const Entry<float>* p)
 // (tile, bin) that the tile touches.
 // ---------------------------------------------------------------------------
 
-// Global column of triplet e; `b` walks forward over the matrices.
+// The matrix of the triplets a thread visits, in increasing order: its index,
+// triplet end, column offset and dimensions, kept in registers.
+struct MatCur {
+  int b;
+  int64_t end, coff;
+  int32_t nd, md;
+};
+
 template <bool BATCHED>
-__device__ __forceinline__ int64_t global_col(const BatchDesc& bd, int& b,
+__device__ __forceinline__ void mat_cur(const BatchDesc& bd, MatCur& c, int b) {
+  if (!BATCHED) return;
+  c.b = b;
+  c.end = bd.trip_off[b + 1];
+  c.coff = bd.col_off[b];
+  c.nd = bd.ndim[b];
+  c.md = bd.mdim[b];
+}
+
+// Global column of triplet e; the cursor walks forward over the matrices.
+template <bool BATCHED>
+__device__ __forceinline__ int64_t global_col(const BatchDesc& bd, MatCur& cur,
                                               int64_t e, int32_t c, int32_t n,
                                               int32_t m, int32_t& mb, bool& ok) {
   if (BATCHED) {
-    while (bd.trip_off[b + 1] <= e) ++b;
-    ok = (uint32_t)c < (uint32_t)bd.ndim[b];
-    mb = bd.mdim[b];
-    return bd.col_off[b] + c;
+    while (cur.end <= e) mat_cur<true>(bd, cur, cur.b + 1);
+    ok = (uint32_t)c < (uint32_t)cur.nd;
+    mb = cur.md;
+    return cur.coff + c;
   }
   ok = (uint32_t)c < (uint32_t)n;
   mb = m;
@@ -535,7 +553,8 @@ __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
   const int64_t t0 = tile * TS;
   const int64_t t1 = min(L, t0 + TS);
   for (int i = threadIdx.x; i < B; i += blockDim.x) hist[i] = 0u;
-  int b = tile_first_mat<BATCHED>(bd, t0, L, &sB);
+  MatCur b;
+  mat_cur<BATCHED>(bd, b, tile_first_mat<BATCHED>(bd, t0, L, &sB));
   __syncthreads();
   bool bad = false;
   int32_t mb;
@@ -627,7 +646,8 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
   const uint32_t* orow = offs + tile * B;
   for (int i = threadIdx.x; i < B; i += blockDim.x)
     ctr[i] = (uint32_t)binstart[i] + orow[i];
-  int b = tile_first_mat<BATCHED>(bd, t0, L, &sB);
+  MatCur b;
+  mat_cur<BATCHED>(bd, b, tile_first_mat<BATCHED>(bd, t0, L, &sB));
   __syncthreads();
   const uint32_t wmask = (1u << s) - 1u;
   bool badr = false;
@@ -657,7 +677,8 @@ __device__ __forceinline__ void tile_bins(const int32_t* __restrict__ jj,
                                           int32_t s, int64_t t0, int* sB,
                                           int32_t (&bn)[IPT], int32_t& lo,
                                           int32_t& hi, bool& bad) {
-  int b = tile_first_mat<BATCHED>(bd, t0, L, sB);
+  MatCur b;
+  mat_cur<BATCHED>(bd, b, tile_first_mat<BATCHED>(bd, t0, L, sB));
   lo = INT32_MAX;
   hi = -1;
   int32_t mb;
@@ -770,7 +791,8 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
     __syncthreads();
   }
   const uint32_t wmask = (1u << s) - 1u;
-  int b = BATCHED ? sB : 0;
+  MatCur b;
+  mat_cur<BATCHED>(bd, b, BATCHED ? sB : 0);
   bool badr = false, over = false;
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
@@ -1830,15 +1852,25 @@ __global__ void k_batched_jcs(const int32_t* __restrict__ jcg,
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t b = idx; b <= nb; b += stride) nnz_off[b] = jcg[col_off[b]];
+  if (idx >= total) return;
+  // matrix b owns positions [col_off[b] + b, col_off[b+1] + b + 1); a thread's
+  // positions increase, so after one search its matrix only moves forward
+  int lo = 0, hi = nb;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (col_off[mid] + mid <= idx) lo = mid; else hi = mid;
+  }
+  int64_t first = col_off[lo], start = first + lo, next = col_off[lo + 1] + lo + 1;
+  int32_t jb = jcg[first];
   for (; idx < total; idx += stride) {
-    // matrix b owns positions [col_off[b] + b, col_off[b+1] + b + 1)
-    int lo = 0, hi = nb;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (col_off[mid] + mid <= idx) lo = mid; else hi = mid;
+    while (idx >= next) {
+      ++lo;
+      first = col_off[lo];
+      start = next;
+      next = col_off[lo + 1] + lo + 1;
+      jb = jcg[first];
     }
-    const int64_t c = idx - (col_off[lo] + lo);
-    jcS[idx] = jcg[col_off[lo] + c] - jcg[col_off[lo]];
+    jcS[idx] = jcg[first + (idx - start)] - jb;
   }
 }
 
