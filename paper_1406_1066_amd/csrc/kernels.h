@@ -1447,24 +1447,28 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
       repa[j] = atomicCAS(&ht[hh[j]], kEmpty, (uint32_t)i);
     }
   }
+  FSP_PHASE(a, q, 10)
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int i = tid + j * NT;
     if (i < span) {
       // an empty slot was claimed (this triplet represents its pair), or the
-      // slot holds the same pair, or probing goes on
-      uint32_t old = repa[j], h = hh[j], rep = (uint32_t)i;
+      // slot holds the same pair, or probing goes on, by growing steps
+      // (triangular probing visits every slot of the power-of-two table and
+      // does not build the long runs that one-slot steps do)
+      uint32_t old = repa[j], h = hh[j], rep = (uint32_t)i, step = 1;
       if (old != kEmpty) {
         const uint32_t c = col[i], r = row[i];
         while (old != kEmpty) {
           if (col[old] == c && row[old] == r) { rep = old; break; }
-          h = (h + 1) & (H - 1);
+          h = (h + step++) & (H - 1);
           old = atomicCAS(&ht[h], kEmpty, (uint32_t)i);
         }
       }
       repa[j] = rep;
     }
   }
+  FSP_PHASE(a, q, 11)
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int i = tid + j * NT;
@@ -1474,7 +1478,9 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
       repa[j] |= arr << 16;
     }
   }
+  FSP_PHASE(a, q, 12)
   if (tid == 0) x.misc()[7] = tk;
+  FSP_PHASE(a, q, 13)
   __syncthreads();
   // next bin: its range now, its entries once the placement is done
   nx.q = (int)x.misc()[7];
