@@ -1510,24 +1510,43 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   uint32_t* gout = x.gout();
   uint32_t* gs = x.gs();
   uint32_t* grow = x.grow();
-  for (int d = tid; d < (int)D; d += NT) {
-    const uint32_t i = dlist[d];
-    const uint32_t r0 = drow[d];
-    const uint32_t cell = rank_cell(a, col[i], r0);
-    const uint32_t lo = cd[cell], hi = cd[cell + 1];
-    // count smaller rows; eight independent reads in flight per step
-    uint32_t r8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    uint32_t t = lo;
-    for (; t + 8 <= hi; t += 8) {
+  // (EPT distinct rows per thread at a time, so that their loads overlap)
+  for (int d0 = tid; d0 < (int)D; d0 += EPT * NT) {
+    uint32_t di[EPT], dr[EPT], lo[EPT], hi[EPT];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) r8[u] += drow[t + u] < r0 ? 1u : 0u;
+    for (int u = 0; u < EPT; ++u) {
+      const int d = d0 + u * NT;
+      di[u] = kEmpty;
+      if (d < (int)D) {
+        di[u] = dlist[d];
+        dr[u] = drow[d];
+      }
     }
-    uint32_t rk = ((r8[0] + r8[1]) + (r8[2] + r8[3])) + ((r8[4] + r8[5]) + (r8[6] + r8[7]));
-    for (; t < hi; ++t) rk += drow[t] < r0 ? 1u : 0u;
-    const uint32_t o = lo + rk;
-    gout[i] = o;
-    gs[o] = cnt[i];
-    grow[o] = r0;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      if (di[u] != kEmpty) {
+        const uint32_t cell = rank_cell(a, col[di[u]], dr[u]);
+        lo[u] = cd[cell];
+        hi[u] = cd[cell + 1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      if (di[u] == kEmpty) continue;
+      // count smaller rows, four reads in flight per step; reads past the
+      // cell's end stay inside the LDS block and are masked out
+      const uint32_t r0 = dr[u], e = hi[u];
+      uint32_t rk = 0;
+      for (uint32_t t = lo[u]; t < e; t += 4) {
+        const uint32_t v0 = drow[t], v1 = drow[t + 1], v2 = drow[t + 2], v3 = drow[t + 3];
+        rk += (v0 < r0 ? 1u : 0u) + ((t + 1 < e && v1 < r0) ? 1u : 0u) +
+              ((t + 2 < e && v2 < r0) ? 1u : 0u) + ((t + 3 < e && v3 < r0) ? 1u : 0u);
+      }
+      const uint32_t o = lo[u] + rk;
+      gout[di[u]] = o;
+      gs[o] = cnt[di[u]];
+      grow[o] = r0;
+    }
   }
   if (tid == 0) gs[D] = 0;
   __syncthreads();
