@@ -204,13 +204,15 @@ constexpr int kReuseTP = 2048;              // sorted positions per re-use tile
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Column bins: w = 2^s columns per bin, sized so that an average bin holds
-// about half the sort stage's LDS capacity.
+// Column bins: w columns per bin (2^s >= w), sized so that an average bin
+// fills kBinFill percent of the bin kernel's LDS capacity.
 enum BinMode { kDense = 0, kSlot = 1, kClaim = 2 };
 
 struct Geom {
   int s;
   int64_t w, B, TS, T;
+  uint32_t mul;     // bin of g = (g * mul) >> sh  (exact for g < 2^31)
+  int sh;
   bool dense;
   int mode;         // BinMode
   int64_t slotcap;  // fixed bin capacity of the slot mode
@@ -226,11 +228,19 @@ Geom make_geom(int64_t L, int64_t N, int cap, int force_mode) {
     // still overflows takes the slow path
     const double target =
         std::max(1.0, (double)cap * kBinFill / 100.0) * (double)N / (double)L;
-    while (w * 2 <= target && w * 2 <= cap) w *= 2;
+    w = (int64_t)std::min<double>(target, (double)cap);
+    w = std::max<int64_t>(1, w);
   }
   g.w = w;
   g.s = 0;
   while ((int64_t(1) << g.s) < w) ++g.s;
+  if ((int64_t(1) << g.s) == w) {
+    g.mul = 1u;
+    g.sh = g.s;
+  } else {
+    g.sh = 31 + g.s;
+    g.mul = (uint32_t)(((uint64_t(1) << g.sh) + (uint64_t)w - 1) / (uint64_t)w);
+  }
   g.B = std::max<int64_t>(1, (N + w - 1) / w);
   g.dense = g.B <= kDenseBins;
   if (g.dense) {
@@ -470,7 +480,8 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   uint32_t* cntmat = at<uint32_t>(ws, lo.cntmat);
   uint32_t* bcol = at<uint32_t>(ws, lo.bcol);
   Entry<VT>* bucket = at<Entry<VT>>(ws, lo.bucket);
-  const int s = g.s, B = (int)g.B;
+  const int s = g.s, B = (int)g.B, w = (int)g.w;
+  const fsp::BinGeo G{g.mul, g.sh, w, s};
   const int blk = tu.sblock;
   // rows and in-bin columns share one word when (m << s) fits 32 bits
   int64_t mmax = m;
@@ -481,12 +492,12 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   if (mode != kSlot) e = launch(kHist, stream, [&] {
     if (mode == kDense)
       hipLaunchKernelGGL(fsp::k_count_dense<BATCHED>, dim3((unsigned)(8 * ((g.T + 7) / 8))), dim3(blk),
-                         (size_t)B * 4, stream, jj, L, n, bd, s, B, (int32_t)g.TS,
+                         (size_t)B * 4, stream, jj, L, n, bd, G, B, (int32_t)g.TS,
                          cntmat, ctrl);
     else
       hipLaunchKernelGGL((fsp::k_count_claim<BATCHED, kClaimNT, kClaimIPT>),
                          dim3((unsigned)g.T), dim3(kClaimNT),
-                         (size_t)kClaimWindow * 4, stream, jj, L, n, bd, s,
+                         (size_t)kClaimWindow * 4, stream, jj, L, n, bd, G,
                          kClaimWindow, bincnt, ctrl);
   });
   if (e != hipSuccess) return e;
@@ -510,13 +521,13 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
     if (mode == kDense)
       hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED>), dim3((unsigned)(8 * ((g.T + 7) / 8))),
                          dim3(blk), (size_t)B * 4, stream, ii, jj, ss, L, m, n, bd,
-                         s, B, (int32_t)g.TS, cntmat, binstart, bucket, bcol, packed,
+                         G, B, (int32_t)g.TS, cntmat, binstart, bucket, bcol, packed,
                          ctrl);
     else
       hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, kClaimNT, kClaimIPT>),
                          dim3((unsigned)g.T), dim3(kClaimNT),
                          (size_t)kClaimWindow * 4, stream, ii, jj, ss, L, m, n, bd,
-                         s, kClaimWindow, binstart, slotcap, binfill, bucket, bcol,
+                         G, kClaimWindow, binstart, slotcap, binfill, bucket, bcol,
                          packed, ctrl);
   });
   if (e != hipSuccess) return e;
@@ -573,14 +584,14 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   do {                                                                         \
     if (may_slow)                                                              \
       hipLaunchKernelGGL((fsp::k_slow_count<VT, C, T>), dim3(sgrid), dim3(T), 0, \
-                         stream, a, binstart, bcol_in, colptr_g, s, slowlist, \
+                         stream, a, binstart, bcol_in, colptr_g, w, slowlist, \
                          slowd);                                               \
     hipLaunchKernelGGL((fsp::k_bin<VT, C, T>),                                 \
                        dim3((unsigned)std::min<int64_t>(B, resident(fsp::k_bin<VT, C, T>, T))), \
-                       dim3(T), 0, stream, a, src, s);                         \
+                       dim3(T), 0, stream, a, src, w);                         \
     if (may_slow)                                                              \
       hipLaunchKernelGGL((fsp::k_slow_emit<VT, C, T>), dim3(sgrid), dim3(T), 0, \
-                         stream, a, binstart, colptr_g, s, slowlist, slowb);   \
+                         stream, a, binstart, colptr_g, w, slowlist, slowb);   \
   } while (0)
     if (kc == 1024) {
       if (nt <= 256) FSP_BIN(1024, 256); else if (nt <= 512) FSP_BIN(1024, 512); else FSP_BIN(1024, 1024);

@@ -439,13 +439,34 @@ __device__ __forceinline__ Entry<float> load_entry<float>(const Entry<float>* p)
 
 // ---------------------------------------------------------------------------
 // Column bins.  Global column g (matrix b's column c is col_off[b] + c) lies
-// in bin g >> s; a bin is w = 2^s consecutive columns, and the bin kernel
-// handles one bin per workgroup.  Bin pointers come from per-tile LDS
+// in bin g / w; a bin is w consecutive columns (any w, not only powers of
+// two, so that bins can be sized to the LDS), and the bin kernel handles one
+// bin per workgroup.  Bin pointers come from per-tile LDS
 // histograms: either a dense tiles x bins count matrix whose column prefix
 // sums give every tile its exclusive offset in every bin (no device-wide
 // atomics at all), or, with too many bins for that, one global claim per
 // (tile, bin) that the tile touches.
 // ---------------------------------------------------------------------------
+
+// Bin geometry.  g / w is one multiply-high and a shift: for w = 2^s,
+// mul = 1 and sh = s; otherwise, with l = ceil(log2 w), sh = 31 + l and
+// mul = ceil(2^sh / w) < 2^32, and since mul * w - 2^sh < w <= 2^l the
+// quotient is exact for every g < 2^31 (Granlund and Montgomery, division by
+// invariant integers, 1994).  An in-bin column g - w * bin takes s = l bits.
+struct BinGeo {
+  uint32_t mul;
+  int32_t sh;
+  int32_t w;
+  int32_t s;
+};
+
+__device__ __forceinline__ uint32_t bin_of(const BinGeo& G, int64_t g) {
+  return (uint32_t)(((uint64_t)(uint32_t)g * G.mul) >> G.sh);
+}
+
+__device__ __forceinline__ uint32_t bin_col(const BinGeo& G, int64_t g, uint32_t q) {
+  return (uint32_t)g - q * (uint32_t)G.w;
+}
 
 // The matrix of the triplets a thread visits, in increasing order: its index,
 // triplet end, column offset and dimensions, kept in registers.
@@ -543,7 +564,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t L, int32_t TS) {
 // dense mode, pass 1: per-tile bin histogram -> row `tile` of cnt[T][B]
 template <bool BATCHED>
 __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
-                              int32_t n, BatchDesc bd, int32_t s, int32_t B,
+                              int32_t n, BatchDesc bd, BinGeo G, int32_t B,
                               int32_t TS, uint32_t* __restrict__ cnt,
                               Ctrl* ctrl) {
   extern __shared__ uint32_t hist[];
@@ -562,7 +583,7 @@ __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
     bool ok;
     const int64_t g = global_col<BATCHED>(bd, b, e, jj[e] - 1, n, 0, mb, ok);
     if (!ok) { bad = true; continue; }
-    atomicAdd(&hist[g >> s], 1u);
+    atomicAdd(&hist[bin_of(G, g)], 1u);
   }
   __syncthreads();
   uint32_t* row = cnt + tile * B;
@@ -631,7 +652,7 @@ template <typename VT, bool BATCHED>
 __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
                                 const int32_t* __restrict__ jj,
                                 const VT* __restrict__ ss, int64_t L, int32_t m,
-                                int32_t n, BatchDesc bd, int32_t s, int32_t B,
+                                int32_t n, BatchDesc bd, BinGeo G, int32_t B,
                                 int32_t TS, const uint32_t* __restrict__ offs,
                                 const int32_t* __restrict__ binstart,
                                 Entry<VT>* __restrict__ bucket,
@@ -649,7 +670,6 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
   MatCur b;
   mat_cur<BATCHED>(bd, b, tile_first_mat<BATCHED>(bd, t0, L, &sB));
   __syncthreads();
-  const uint32_t wmask = (1u << s) - 1u;
   bool badr = false;
   for (int64_t e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
     bool ok;
@@ -658,13 +678,14 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
     if (!ok) continue;  // flagged by the count pass
     const int32_t r = ii[e] - 1;
     badr |= (uint32_t)r >= (uint32_t)mb;
-    const uint32_t p = atomicAdd(&ctr[g >> s], 1u);
+    const uint32_t q = bin_of(G, g);
+    const uint32_t c = bin_col(G, g, q);
+    const uint32_t p = atomicAdd(&ctr[q], 1u);
     if (packed) {
-      store_entry<VT>(&bucket[p], ((uint32_t)r << s) | ((uint32_t)g & wmask),
-                      (uint32_t)e, ss[e]);
+      store_entry<VT>(&bucket[p], ((uint32_t)r << G.s) | c, (uint32_t)e, ss[e]);
     } else {
       store_entry<VT>(&bucket[p], (uint32_t)r, (uint32_t)e, ss[e]);
-      bcol[p] = (uint32_t)g & wmask;
+      bcol[p] = c;
     }
   }
   if (badr) atomicOr(&ctrl->err, kErrRow);
@@ -674,7 +695,7 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
 template <bool BATCHED, int NT, int IPT>
 __device__ __forceinline__ void tile_bins(const int32_t* __restrict__ jj,
                                           int64_t L, int32_t n, const BatchDesc& bd,
-                                          int32_t s, int64_t t0, int* sB,
+                                          const BinGeo& G, int64_t t0, int* sB,
                                           int32_t (&bn)[IPT], int32_t& lo,
                                           int32_t& hi, bool& bad) {
   MatCur b;
@@ -690,7 +711,7 @@ __device__ __forceinline__ void tile_bins(const int32_t* __restrict__ jj,
       bool ok;
       const int64_t g = global_col<BATCHED>(bd, b, e, jj[e] - 1, n, 0, mb, ok);
       if (ok) {
-        bn[j] = (int32_t)(g >> s);
+        bn[j] = (int32_t)bin_of(G, g);
         lo = min(lo, bn[j]);
         hi = max(hi, bn[j]);
       } else {
@@ -724,7 +745,7 @@ __device__ __forceinline__ void block_minmax(int32_t& lo, int32_t& hi,
 template <bool BATCHED, int NT, int IPT>
 __global__ void __launch_bounds__(NT)
 k_count_claim(const int32_t* __restrict__ jj, int64_t L, int32_t n,
-              BatchDesc bd, int32_t s, int32_t WMAX,
+              BatchDesc bd, BinGeo G, int32_t WMAX,
               uint32_t* __restrict__ bincnt, Ctrl* ctrl) {
   extern __shared__ uint32_t hist[];
   __shared__ int sB;
@@ -732,7 +753,7 @@ k_count_claim(const int32_t* __restrict__ jj, int64_t L, int32_t n,
   const int64_t t0 = (int64_t)blockIdx.x * NT * IPT;
   int32_t bn[IPT], lo, hi;
   bool bad = false;
-  tile_bins<BATCHED, NT, IPT>(jj, L, n, bd, s, t0, &sB, bn, lo, hi, bad);
+  tile_bins<BATCHED, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, lo, hi, bad);
   block_minmax<NT>(lo, hi, &sLo, &sHi);
   if (bad) atomicOr(&ctrl->err, kErrCol);
   if (hi < lo) return;
@@ -757,7 +778,7 @@ template <typename VT, bool BATCHED, int NT, int IPT>
 __global__ void __launch_bounds__(NT)
 k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
                 const VT* __restrict__ ss, int64_t L, int32_t m, int32_t n,
-                BatchDesc bd, int32_t s, int32_t WMAX,
+                BatchDesc bd, BinGeo G, int32_t WMAX,
                 const int32_t* __restrict__ binstart, int32_t slotcap,
                 uint32_t* __restrict__ binfill, Entry<VT>* __restrict__ bucket,
                 uint32_t* __restrict__ bcol, int packed, Ctrl* ctrl) {
@@ -767,7 +788,7 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
   const int64_t t0 = (int64_t)blockIdx.x * NT * IPT;
   int32_t bn[IPT], lo, hi;
   bool bad = false;
-  tile_bins<BATCHED, NT, IPT>(jj, L, n, bd, s, t0, &sB, bn, lo, hi, bad);
+  tile_bins<BATCHED, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, lo, hi, bad);
   block_minmax<NT>(lo, hi, &sLo, &sHi);
   if (hi < lo) return;
   const int width = hi - lo + 1;
@@ -790,7 +811,6 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
     }
     __syncthreads();
   }
-  const uint32_t wmask = (1u << s) - 1u;
   MatCur b;
   mat_cur<BATCHED>(bd, b, BATCHED ? sB : 0);
   bool badr = false, over = false;
@@ -814,12 +834,12 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
       over = true;  // this bin is full: the call is redone in two passes
       continue;
     }
+    const uint32_t c = bin_col(G, g, (uint32_t)bn[j]);
     if (packed) {
-      store_entry<VT>(&bucket[p], ((uint32_t)r << s) | ((uint32_t)g & wmask),
-                      (uint32_t)e, ss[e]);
+      store_entry<VT>(&bucket[p], ((uint32_t)r << G.s) | c, (uint32_t)e, ss[e]);
     } else {
       store_entry<VT>(&bucket[p], (uint32_t)r, (uint32_t)e, ss[e]);
-      bcol[p] = (uint32_t)g & wmask;
+      bcol[p] = c;
     }
   }
   if (badr) atomicOr(&ctrl->err, kErrRow);
@@ -1748,7 +1768,7 @@ template <typename VT, int CAP, int NT>
 __global__ void __launch_bounds__(NT)
 k_slow_count(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
              const uint32_t* __restrict__ bcol, int32_t* __restrict__ colptr_g,
-             int32_t s, const int32_t* __restrict__ slowlist,
+             int32_t w, const int32_t* __restrict__ slowlist,
              uint32_t* __restrict__ slowD) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<CAP>::kBytes];
   ChunkCtx<VT, CAP, NT> x{smem};
@@ -1757,8 +1777,8 @@ k_slow_count(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
     const int q = slowlist[i];
     int e0, e1;
     slow_range(binstart, q, e0, e1);
-    const int c0 = (int)min((int64_t)a.N, (int64_t)q << s);
-    const int c1 = (int)min((int64_t)a.N, ((int64_t)q + 1) << s);
+    const int c0 = (int)min((int64_t)a.N, (int64_t)q * w);
+    const int c1 = (int)min((int64_t)a.N, ((int64_t)q + 1) * w);
     ChunkArgs<VT> b = a;
     slow_sort<VT, CAP, NT>(b, bcol, colptr_g, x, c0, c1, e0, e1);
     const int64_t D = chunk_sweep<VT, CAP, NT>(b, x, c0, c1, false, 0);
@@ -1769,7 +1789,7 @@ k_slow_count(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
 template <typename VT, int CAP, int NT>
 __global__ void __launch_bounds__(NT)
 k_slow_emit(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
-            int32_t* __restrict__ colptr_g, int32_t s,
+            int32_t* __restrict__ colptr_g, int32_t w,
             const int32_t* __restrict__ slowlist,
             const uint64_t* __restrict__ slowB) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<CAP>::kBytes];
@@ -1779,8 +1799,8 @@ k_slow_emit(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
     const int q = slowlist[i];
     int e0, e1;
     slow_range(binstart, q, e0, e1);
-    const int c0 = (int)min((int64_t)a.N, (int64_t)q << s);
-    const int c1 = (int)min((int64_t)a.N, ((int64_t)q + 1) << s);
+    const int c0 = (int)min((int64_t)a.N, (int64_t)q * w);
+    const int c1 = (int)min((int64_t)a.N, ((int64_t)q + 1) * w);
     ChunkArgs<VT> b = a;
     b.colptr = colptr_g;  // the copy sorted by k_slow_count
     Entry<VT>* t = b.bucket;
@@ -1801,7 +1821,7 @@ k_slow_emit(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
 // A block holds at most one ticket beyond the bin it processes.
 template <typename VT, int CAP, int NT>
 __global__ void __launch_bounds__(NT)
-k_bin(ChunkArgs<VT> a, BinSrc src, int32_t s) {
+k_bin(ChunkArgs<VT> a, BinSrc src, int32_t w) {
   constexpr int EPT = CAP / NT;
   __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<CAP>::kBytes];
   ChunkCtx<VT, CAP, NT> x{smem};
@@ -1823,8 +1843,8 @@ k_bin(ChunkArgs<VT> a, BinSrc src, int32_t s) {
 #ifdef FSP_PHASE_TIMING
     if (a.phase && threadIdx.x == 0) a.phase[(int64_t)q * 16] = wall_clock64();
 #endif
-    const int c0 = (int)min((int64_t)N, (int64_t)q << s);
-    const int c1 = (int)min((int64_t)N, ((int64_t)q + 1) << s);
+    const int c0 = (int)min((int64_t)N, (int64_t)q * w);
+    const int c1 = (int)min((int64_t)N, ((int64_t)q + 1) * w);
     // ticket of the next bin; only thread 0 holds (and later reads) it, so
     // the value needs no merge with the other lanes and no early wait
     uint32_t tk;
