@@ -483,10 +483,11 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   const int s = g.s, B = (int)g.B, w = (int)g.w;
   const fsp::BinGeo G{g.mul, g.sh, w, s};
   const int blk = tu.sblock;
-  // rows and in-bin columns share one word when (m << s) fits 32 bits
+  // rows and in-bin columns share one word when (m << s) fits 32 bits with
+  // the all-ones word to spare (the bin kernel's empty hash slot)
   int64_t mmax = m;
   if (BATCHED) mmax = lo.mmax;
-  const int packed = (mmax <= (int64_t(1) << (32 - s))) ? 1 : 0;
+  const int packed = (mmax < (int64_t(1) << (32 - s))) ? 1 : 0;
   const int32_t slotcap = mode == kSlot ? (int32_t)g.slotcap : 0;
   // 1. bin counts (the slot mode has none)
   if (mode != kSlot) e = launch(kHist, stream, [&] {

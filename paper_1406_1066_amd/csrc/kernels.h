@@ -1423,6 +1423,9 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   const int span = e1 - e0;
   const int wc = c1 - c0;
   const uint32_t cmask = (1u << a.rshift) - 1u;  // packed keys only
+  // packed words are unique keys of the (column, row) pairs (never kEmpty):
+  // the hash table then holds the keys themselves
+  const bool keyed = src.bcol == nullptr;
   FSP_PHASE(a, q, 1)
   uint32_t* ht = x.ht();
   uint32_t* row = x.row();
@@ -1445,7 +1448,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
     const int i = tid + j * NT;
     if (i < span) {
       row[i] = cur.en[j].row;
-      col[i] = src.bcol ? src.bcol[e0 + i] : (cur.en[j].row & cmask);
+      if (!keyed) col[i] = src.bcol[e0 + i];
       kr[j] = cur.en[j].k;
       vr[j] = cur.en[j].v;
     }
@@ -1457,6 +1460,47 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   // triplets are issued together, then collisions are resolved, then the
   // group and cell counters are bumped, so the LDS atomics overlap.
   uint32_t repa[EPT], dpos[EPT], hh[EPT], cell[EPT];
+  if (keyed) {
+    // the table holds keys; a probe ends at an empty slot (claimed: this
+    // triplet represents its pair) or at its own key.  Representatives then
+    // leave their index beside the slot (hidx: the column-start and
+    // column-end arrays, unused with packed keys, 2*CAP words).
+    uint32_t* hidx = col;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int i = tid + j * NT;
+      if (i < span) {
+        const uint32_t r = row[i];
+        cell[j] = rank_cell(a, r & cmask, r);
+        hh[j] = pair_hash(r & cmask, r) & (H - 1);
+        repa[j] = atomicCAS(&ht[hh[j]], kEmpty, r);
+      }
+    }
+    FSP_PHASE(a, q, 10)
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int i = tid + j * NT;
+      if (i < span) {
+        // triangular probing: growing steps visit every slot of the
+        // power-of-two table without building long runs
+        const uint32_t r = row[i];
+        uint32_t old = repa[j], h = hh[j], step = 1;
+        while (old != kEmpty && old != r) {
+          h = (h + step++) & (H - 1);
+          old = atomicCAS(&ht[h], kEmpty, r);
+        }
+        hh[j] = h;
+        repa[j] = old == kEmpty ? (uint32_t)i : kEmpty;
+        if (old == kEmpty) hidx[h] = (uint32_t)i;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int i = tid + j * NT;
+      if (i < span && repa[j] == kEmpty) repa[j] = hidx[hh[j]];
+    }
+  } else {
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int i = tid + j * NT;
@@ -1488,6 +1532,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
       repa[j] = rep;
     }
   }
+  }
   FSP_PHASE(a, q, 11)
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
@@ -1518,7 +1563,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
     const int i = tid + j * NT;
     if (i < span && dpos[j] != kEmpty) {
       const uint32_t r = row[i];
-      const uint32_t d = cd[rank_cell(a, col[i], r)] + dpos[j];
+      const uint32_t d = cd[rank_cell(a, keyed ? (r & cmask) : col[i], r)] + dpos[j];
       dlist[d] = (uint32_t)i;
       drow[d] = r;
     }
@@ -1545,7 +1590,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       if (di[u] != kEmpty) {
-        const uint32_t cell = rank_cell(a, col[di[u]], dr[u]);
+        const uint32_t cell = rank_cell(a, keyed ? (dr[u] & cmask) : col[di[u]], dr[u]);
         lo[u] = cd[cell];
         hi[u] = cd[cell + 1];
       }
