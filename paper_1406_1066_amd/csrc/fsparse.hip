@@ -299,9 +299,10 @@ Layout make_layout(int64_t L, int64_t N, int nb, int esize, const Tuning& tu) {
   o.binstart = p;    p = al(p + 4 * (size_t)(B + 1));
   o.cntmat = p;      p = al(p + (o.g.dense ? 4 * (size_t)o.g.T * B : 0));
   const int64_t nb_places = std::max(L, o.g.nslot);
-  o.bcol = p;        p = al(p + 4 * (size_t)nb_places);
+  // one spare place past the end of the bucket (and of bcol)
+  o.bcol = p;        p = al(p + 4 * (size_t)(nb_places + 1));
   o.colptr = p;      p = al(p + 4 * (size_t)(N + 1));
-  o.bucket = p;      p = al(p + (size_t)esize * nb_places);
+  o.bucket = p;      p = al(p + (size_t)esize * (nb_places + 1));
   o.tmp = p;         p = al(p + (size_t)esize * L);
   o.perm = p;        p = al(p + 4 * (size_t)L);
   o.seg = p;         p = al(p + 4 * (size_t)(L + 1));
@@ -519,17 +520,32 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   if (e != hipSuccess) return e;
   // 3. scatter into the bins
   e = launch(kBucket, stream, [&] {
-    if (mode == kDense)
-      hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED>), dim3((unsigned)(8 * ((g.T + 7) / 8))),
-                         dim3(blk), (size_t)B * 4, stream, ii, jj, ss, L, m, n, bd,
-                         G, B, (int32_t)g.TS, cntmat, binstart, bucket, bcol, packed,
-                         ctrl);
-    else
-      hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, kClaimNT, kClaimIPT>),
-                         dim3((unsigned)g.T), dim3(kClaimNT),
-                         (size_t)kClaimWindow * 4, stream, ii, jj, ss, L, m, n, bd,
-                         G, kClaimWindow, binstart, slotcap, binfill, bucket, bcol,
-                         packed, ctrl);
+    if (mode == kDense) {
+      if (packed)
+        hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED, true>), dim3((unsigned)(8 * ((g.T + 7) / 8))),
+                           dim3(blk), (size_t)B * 4, stream, ii, jj, ss, L, m, n, bd,
+                           G, B, (int32_t)g.TS, cntmat, binstart, bucket, bcol,
+                           (uint32_t)std::max<int64_t>(L, g.nslot), ctrl);
+      else
+        hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED, false>), dim3((unsigned)(8 * ((g.T + 7) / 8))),
+                           dim3(blk), (size_t)B * 4, stream, ii, jj, ss, L, m, n, bd,
+                           G, B, (int32_t)g.TS, cntmat, binstart, bucket, bcol,
+                           (uint32_t)std::max<int64_t>(L, g.nslot), ctrl);
+    } else {
+      const uint32_t trash = (uint32_t)std::max<int64_t>(L, g.nslot);
+      if (packed)
+        hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, true, kClaimNT, kClaimIPT>),
+                           dim3((unsigned)g.T), dim3(kClaimNT),
+                           (size_t)kClaimWindow * 4, stream, ii, jj, ss, L, m, n, bd,
+                           G, kClaimWindow, binstart, slotcap, binfill, bucket, bcol,
+                           trash, ctrl);
+      else
+        hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, false, kClaimNT, kClaimIPT>),
+                           dim3((unsigned)g.T), dim3(kClaimNT),
+                           (size_t)kClaimWindow * 4, stream, ii, jj, ss, L, m, n, bd,
+                           G, kClaimWindow, binstart, slotcap, binfill, bucket, bcol,
+                           trash, ctrl);
+    }
   });
   if (e != hipSuccess) return e;
   // 4. one workgroup per bin: group, rank, order, fold, emit

@@ -561,6 +561,11 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t L, int32_t TS) {
   return t < T ? t : -1;
 }
 
+// triplets whose loads one thread of the dense count (scatter) pass keeps
+// in flight
+constexpr int kDenseU = 8;
+constexpr int kScatterU = 4;
+
 // dense mode, pass 1: per-tile bin histogram -> row `tile` of cnt[T][B]
 template <bool BATCHED>
 __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
@@ -579,11 +584,21 @@ __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
   __syncthreads();
   bool bad = false;
   int32_t mb;
-  for (int64_t e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
-    bool ok;
-    const int64_t g = global_col<BATCHED>(bd, b, e, jj[e] - 1, n, 0, mb, ok);
-    if (!ok) { bad = true; continue; }
-    atomicAdd(&hist[bin_of(G, g)], 1u);
+  // kDenseU column loads in flight per thread, then their counts
+  const int64_t nt = blockDim.x;
+  for (int64_t eb = t0 + threadIdx.x; eb < t1; eb += kDenseU * nt) {
+    int32_t cj[kDenseU];
+#pragma unroll
+    for (int u = 0; u < kDenseU; ++u) cj[u] = jj[min(eb + u * nt, t1 - 1)];  // no branch
+#pragma unroll
+    for (int u = 0; u < kDenseU; ++u) {
+      const int64_t e = eb + u * nt;
+      if (e >= t1) break;
+      bool ok;
+      const int64_t g = global_col<BATCHED>(bd, b, e, cj[u] - 1, n, 0, mb, ok);
+      if (!ok) { bad = true; continue; }
+      atomicAdd(&hist[bin_of(G, g)], 1u);
+    }
   }
   __syncthreads();
   uint32_t* row = cnt + tile * B;
@@ -648,7 +663,7 @@ k_colscan(uint32_t* __restrict__ cnt, int32_t T, int32_t B,
 
 // dense mode, pass 3: scatter (row, k, value) and the in-bin column into
 // the bins; the position inside the bin is an LDS atomic rank
-template <typename VT, bool BATCHED>
+template <typename VT, bool BATCHED, bool PACKED>
 __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
                                 const int32_t* __restrict__ jj,
                                 const VT* __restrict__ ss, int64_t L, int32_t m,
@@ -656,7 +671,7 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
                                 int32_t TS, const uint32_t* __restrict__ offs,
                                 const int32_t* __restrict__ binstart,
                                 Entry<VT>* __restrict__ bucket,
-                                uint32_t* __restrict__ bcol, int packed,
+                                uint32_t* __restrict__ bcol, uint32_t trash,
                                 Ctrl* ctrl) {
   extern __shared__ uint32_t ctr[];
   __shared__ int sB;
@@ -671,21 +686,46 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
   mat_cur<BATCHED>(bd, b, tile_first_mat<BATCHED>(bd, t0, L, &sB));
   __syncthreads();
   bool badr = false;
-  for (int64_t e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
-    bool ok;
-    int32_t mb;
-    const int64_t g = global_col<BATCHED>(bd, b, e, jj[e] - 1, n, m, mb, ok);
-    if (!ok) continue;  // flagged by the count pass
-    const int32_t r = ii[e] - 1;
-    badr |= (uint32_t)r >= (uint32_t)mb;
-    const uint32_t q = bin_of(G, g);
-    const uint32_t c = bin_col(G, g, q);
-    const uint32_t p = atomicAdd(&ctr[q], 1u);
-    if (packed) {
-      store_entry<VT>(&bucket[p], ((uint32_t)r << G.s) | c, (uint32_t)e, ss[e]);
-    } else {
-      store_entry<VT>(&bucket[p], (uint32_t)r, (uint32_t)e, ss[e]);
-      bcol[p] = c;
+  // the loads of kScatterU triplets are issued together, then their LDS
+  // ranks, then their stores (a triplet without a place, past the tile or
+  // with a bad column, is stored to the spare place `trash`, so that the
+  // stores need no branch)
+  const int64_t nt = blockDim.x;
+  for (int64_t eb = t0 + threadIdx.x; eb < t1; eb += kScatterU * nt) {
+    int32_t cj[kScatterU], ri[kScatterU];
+    VT sv[kScatterU];
+#pragma unroll
+    for (int u = 0; u < kScatterU; ++u) {
+      const int64_t e = eb + u * nt;
+      if (e < t1) {
+        cj[u] = jj[e];
+        ri[u] = ii[e];
+        sv[u] = ss[e];
+      }
+    }
+    uint32_t pos[kScatterU], key[kScatterU], bc[kScatterU];
+#pragma unroll
+    for (int u = 0; u < kScatterU; ++u) {
+      const int64_t e = eb + u * nt;
+      pos[u] = trash;
+      if (e < t1) {
+        bool ok;
+        int32_t mb;
+        const int64_t g = global_col<BATCHED>(bd, b, e, cj[u] - 1, n, m, mb, ok);
+        if (ok) {  // a bad column is flagged by the count pass
+          const int32_t r = ri[u] - 1;
+          badr |= (uint32_t)r >= (uint32_t)mb;
+          const uint32_t q = bin_of(G, g);
+          bc[u] = bin_col(G, g, q);
+          key[u] = PACKED ? (((uint32_t)r << G.s) | bc[u]) : (uint32_t)r;
+          pos[u] = atomicAdd(&ctr[q], 1u);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kScatterU; ++u) {
+      store_entry<VT>(&bucket[pos[u]], key[u], (uint32_t)(eb + u * nt), sv[u]);
+      if (!PACKED) bcol[pos[u]] = bc[u];
     }
   }
   if (badr) atomicOr(&ctrl->err, kErrRow);
@@ -696,20 +736,24 @@ template <bool BATCHED, int NT, int IPT>
 __device__ __forceinline__ void tile_bins(const int32_t* __restrict__ jj,
                                           int64_t L, int32_t n, const BatchDesc& bd,
                                           const BinGeo& G, int64_t t0, int* sB,
-                                          int32_t (&bn)[IPT], int32_t& lo,
-                                          int32_t& hi, bool& bad) {
+                                          int32_t (&bn)[IPT], int32_t (&cj)[IPT],
+                                          int32_t& lo, int32_t& hi, bool& bad) {
   MatCur b;
   mat_cur<BATCHED>(bd, b, tile_first_mat<BATCHED>(bd, t0, L, sB));
   lo = INT32_MAX;
   hi = -1;
   int32_t mb;
+  // all column loads in flight at once (clamped index: no branch)
+#pragma unroll
+  for (int j = 0; j < IPT; ++j)
+    cj[j] = jj[min(t0 + (int64_t)j * NT + threadIdx.x, L - 1)];
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const int64_t e = t0 + (int64_t)j * NT + threadIdx.x;
     bn[j] = -1;
     if (e < L) {
       bool ok;
-      const int64_t g = global_col<BATCHED>(bd, b, e, jj[e] - 1, n, 0, mb, ok);
+      const int64_t g = global_col<BATCHED>(bd, b, e, cj[j] - 1, n, 0, mb, ok);
       if (ok) {
         bn[j] = (int32_t)bin_of(G, g);
         lo = min(lo, bn[j]);
@@ -751,9 +795,9 @@ k_count_claim(const int32_t* __restrict__ jj, int64_t L, int32_t n,
   __shared__ int sB;
   __shared__ int32_t sLo, sHi;
   const int64_t t0 = (int64_t)blockIdx.x * NT * IPT;
-  int32_t bn[IPT], lo, hi;
+  int32_t bn[IPT], cj[IPT], lo, hi;
   bool bad = false;
-  tile_bins<BATCHED, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, lo, hi, bad);
+  tile_bins<BATCHED, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, cj, lo, hi, bad);
   block_minmax<NT>(lo, hi, &sLo, &sHi);
   if (bad) atomicOr(&ctrl->err, kErrCol);
   if (hi < lo) return;
@@ -774,21 +818,21 @@ k_count_claim(const int32_t* __restrict__ jj, int64_t L, int32_t n,
   }
 }
 
-template <typename VT, bool BATCHED, int NT, int IPT>
+template <typename VT, bool BATCHED, bool PACKED, int NT, int IPT>
 __global__ void __launch_bounds__(NT)
 k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
                 const VT* __restrict__ ss, int64_t L, int32_t m, int32_t n,
                 BatchDesc bd, BinGeo G, int32_t WMAX,
                 const int32_t* __restrict__ binstart, int32_t slotcap,
                 uint32_t* __restrict__ binfill, Entry<VT>* __restrict__ bucket,
-                uint32_t* __restrict__ bcol, int packed, Ctrl* ctrl) {
+                uint32_t* __restrict__ bcol, uint32_t trash, Ctrl* ctrl) {
   extern __shared__ uint32_t hist[];
   __shared__ int sB;
   __shared__ int32_t sLo, sHi;
   const int64_t t0 = (int64_t)blockIdx.x * NT * IPT;
-  int32_t bn[IPT], lo, hi;
+  int32_t bn[IPT], cj[IPT], lo, hi;
   bool bad = false;
-  tile_bins<BATCHED, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, lo, hi, bad);
+  tile_bins<BATCHED, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, cj, lo, hi, bad);
   block_minmax<NT>(lo, hi, &sLo, &sHi);
   if (hi < lo) return;
   const int width = hi - lo + 1;
@@ -814,32 +858,52 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
   MatCur b;
   mat_cur<BATCHED>(bd, b, BATCHED ? sB : 0);
   bool badr = false, over = false;
+  // kScatterU triplets at a time: their loads together, then their places,
+  // then their stores (a triplet without a place goes to the spare place
+  // `trash`, so that the stores need no branch)
 #pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    if (bn[j] < 0) continue;
-    const int64_t e = t0 + (int64_t)j * NT + threadIdx.x;
-    bool ok;
-    int32_t mb;
-    const int64_t g = global_col<BATCHED>(bd, b, e, jj[e] - 1, n, m, mb, ok);
-    const int32_t r = ii[e] - 1;
-    badr |= (uint32_t)r >= (uint32_t)mb;
-    uint32_t p;
-    if (narrow) {
-      p = hist[bn[j] - lo] + rk[j];
-    } else {
-      const uint32_t c = atomicAdd(&binfill[bn[j]], 1u);
-      p = (slotcap > 0 ? (uint32_t)bn[j] * (uint32_t)slotcap : (uint32_t)binstart[bn[j]]) + c;
+  for (int j0 = 0; j0 < IPT; j0 += kScatterU) {
+    int32_t ri[kScatterU];
+    VT sv[kScatterU];
+#pragma unroll
+    for (int u = 0; u < kScatterU; ++u) {
+      const int64_t e = min(t0 + (int64_t)(j0 + u) * NT + threadIdx.x, L - 1);
+      ri[u] = ii[e];
+      sv[u] = ss[e];
     }
-    if (slotcap > 0 && p - (uint32_t)bn[j] * (uint32_t)slotcap >= (uint32_t)slotcap) {
-      over = true;  // this bin is full: the call is redone in two passes
-      continue;
+    uint32_t pos[kScatterU], key[kScatterU], bc[kScatterU];
+#pragma unroll
+    for (int u = 0; u < kScatterU; ++u) {
+      const int j = j0 + u;
+      const int64_t e = t0 + (int64_t)j * NT + threadIdx.x;
+      pos[u] = trash;
+      if (bn[j] >= 0) {
+        bool ok;
+        int32_t mb;
+        const int64_t g = global_col<BATCHED>(bd, b, e, cj[j] - 1, n, m, mb, ok);
+        const int32_t r = ri[u] - 1;
+        badr |= (uint32_t)r >= (uint32_t)mb;
+        uint32_t p;
+        if (narrow) {
+          p = hist[bn[j] - lo] + rk[j];
+        } else {
+          const uint32_t c = atomicAdd(&binfill[bn[j]], 1u);
+          p = (slotcap > 0 ? (uint32_t)bn[j] * (uint32_t)slotcap : (uint32_t)binstart[bn[j]]) + c;
+        }
+        if (slotcap > 0 && p - (uint32_t)bn[j] * (uint32_t)slotcap >= (uint32_t)slotcap) {
+          over = true;  // this bin is full: the call is redone in two passes
+        } else {
+          bc[u] = bin_col(G, g, (uint32_t)bn[j]);
+          key[u] = PACKED ? (((uint32_t)r << G.s) | bc[u]) : (uint32_t)r;
+          pos[u] = p;
+        }
+      }
     }
-    const uint32_t c = bin_col(G, g, (uint32_t)bn[j]);
-    if (packed) {
-      store_entry<VT>(&bucket[p], ((uint32_t)r << G.s) | c, (uint32_t)e, ss[e]);
-    } else {
-      store_entry<VT>(&bucket[p], (uint32_t)r, (uint32_t)e, ss[e]);
-      bcol[p] = c;
+#pragma unroll
+    for (int u = 0; u < kScatterU; ++u) {
+      store_entry<VT>(&bucket[pos[u]], key[u],
+                      (uint32_t)(t0 + (int64_t)(j0 + u) * NT + threadIdx.x), sv[u]);
+      if (!PACKED) bcol[pos[u]] = bc[u];
     }
   }
   if (badr) atomicOr(&ctrl->err, kErrRow);
@@ -1656,6 +1720,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
     }
   }
   __syncthreads();
+  FSP_PHASE(a, q, 14)
   VT* mval = x.mval();
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
@@ -1672,6 +1737,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   }
   if (tid < 64) probe = lookback_probe(a.status, q);
   __syncthreads();
+  FSP_PHASE(a, q, 15)
   // order each group by k: values go straight to their sorted place, so do
   // the k of the plan
 #pragma unroll
