@@ -219,7 +219,7 @@ struct Geom {
   int64_t nslot;    // bucket places of the slot mode
 };
 
-Geom make_geom(int64_t L, int64_t N, int cap, int force_mode) {
+Geom make_geom(int64_t L, int64_t N, int cap, int force_mode, int blk) {
   Geom g{};
   int64_t w = 1;
   if (L > 0) {
@@ -255,6 +255,12 @@ Geom make_geom(int64_t L, int64_t N, int cap, int force_mode) {
       if (!(big || heavy) || g.TS >= (1 << 22)) break;
       g.TS *= 2;
     }
+    // between R and 2R tiles (R: the blocks of the dense passes that fit on
+    // the chip at once, about 16 waves per CU), R larger tiles leave no
+    // part-empty second round
+    const int64_t R = (int64_t)num_cus() * std::max(1, 1024 / std::max(64, blk));
+    const int64_t T = (L + g.TS - 1) / g.TS;
+    if (T > R && T < 2 * R) g.TS = (L + R - 1) / R;
   } else {
     g.TS = (int64_t)kClaimNT * kClaimIPT;
   }
@@ -285,7 +291,7 @@ struct Layout {
 
 Layout make_layout(int64_t L, int64_t N, int nb, int esize, const Tuning& tu) {
   Layout o{};
-  o.g = make_geom(L, N, tu.cap, tu.bmode);
+  o.g = make_geom(L, N, tu.cap, tu.bmode, tu.sblock);
   const int64_t B = o.g.B;
   o.nscan = (B + 1 + kScanTile - 1) / kScanTile;
   size_t p = 0;
