@@ -2068,7 +2068,19 @@ k_reuse(const int32_t* __restrict__ perm, const int32_t* __restrict__ seg,
   if (J0 >= J1) return;
   const int P0 = seg[J0], P1 = seg[J1];
   if (P1 - P0 <= LCAP) {
-    for (int p = P0 + threadIdx.x; p < P1; p += NT) val[p - P0] = ss[perm[p]];
+    // four positions per thread at a time: their index loads, then their
+    // gathers, all in flight together (clamped indices: no branch)
+    for (int p0 = P0 + threadIdx.x; p0 < P1; p0 += 4 * NT) {
+      int32_t pk[4];
+      VT v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pk[u] = perm[min(p0 + u * NT, P1 - 1)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = ss[pk[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (p0 + u * NT < P1) val[p0 + u * NT - P0] = v[u];
+    }
     __syncthreads();
     for (int j = J0 + threadIdx.x; j < J1; j += NT) {
       const int a = seg[j] - P0, b = seg[j + 1] - P0;
