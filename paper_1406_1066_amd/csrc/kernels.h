@@ -296,9 +296,11 @@ __device__ __forceinline__ void lookback_publish(uint64_t* status, int q,
 // that its latency overlaps other work.  Any state it sees is usable: an
 // aggregate stays that tile's aggregate, and a word not yet written is read
 // again by lookback_wait.
+// The first look-back window of bin q (q >= 1), loaded without a branch:
+// lanes before bin 0 read status[0], and lookback_wait treats them as
+// prefixes.  (No select here, so nothing waits for the load yet.)
 __device__ __forceinline__ uint64_t lookback_probe(const uint64_t* status, int q) {
-  const int idx = q - 1 - lane_id();
-  return idx >= 0 ? ld_status(&status[idx]) : kFlagPrefix;
+  return ld_status(&status[max(q - 1 - lane_id(), 0)]);
 }
 
 __device__ int64_t lookback_wait(uint64_t* status, int q, uint64_t agg,
@@ -310,8 +312,7 @@ __device__ int64_t lookback_wait(uint64_t* status, int q, uint64_t agg,
   bool first = true;
   for (;;) {
     const int idx = pred - lane;
-    const uint64_t s = first ? probe
-                             : ((idx >= 0) ? ld_status(&status[idx]) : kFlagPrefix);
+    const uint64_t s = (idx < 0) ? kFlagPrefix : (first ? probe : ld_status(&status[idx]));
     first = false;
     const uint32_t flag = (uint32_t)(s >> 62);
     const uint64_t inval = __ballot(flag == 0);
@@ -1440,32 +1441,45 @@ struct BinRegs {
 // Issue the loads of bin q's range.  The same three words are read in every
 // mode (binstart always has B+1 entries and binfill B), and nothing is
 // computed from them yet, so the loads stay in flight until bin_range.
+// One vector load with a different word per lane (lane 0 binstart[q],
+// lane 1 binstart[q+1], lane 2 binfill[q]): a wave-uniform load would be
+// moved to scalar registers, and waited for, at once.  A ticket past the
+// last bin reads bin B-1's words; bin_range then makes its range empty.
 template <typename VT, int EPT>
 __device__ __forceinline__ void bin_bounds(const BinSrc& src, BinRegs<VT, EPT>& r,
-                                           uint32_t& fill) {
-  r.e0 = src.binstart[r.q];
-  r.e1 = src.binstart[r.q + 1];
-  fill = src.binfill[r.q];
+                                           uint32_t& w) {
+  const int qc = min(r.q, src.B - 1);
+  const int lane = lane_id();
+  const uint32_t* p = lane == 2 ? &src.binfill[qc]
+                                : reinterpret_cast<const uint32_t*>(&src.binstart[qc + (lane & 1)]);
+  w = *p;
 }
 
 template <typename VT, int EPT>
 __device__ __forceinline__ void bin_range(const BinSrc& src, BinRegs<VT, EPT>& r,
-                                          uint32_t fill) {
+                                          uint32_t w) {
+  r.e0 = (int)__builtin_amdgcn_readlane(w, 0);
+  r.e1 = (int)__builtin_amdgcn_readlane(w, 1);
+  const uint32_t fill = __builtin_amdgcn_readlane(w, 2);
   if (src.slotcap > 0) {
     r.e0 = r.q * src.slotcap;
     r.e1 = r.e0 + (int)min(fill, (uint32_t)src.slotcap);
   }
+  if (r.q >= src.B) r.e0 = r.e1 = 0;
 }
 
+// The same EPT loads on every path (indices clamped into the bin, an empty
+// bin reading its first place, which is at most the bucket's spare place),
+// so that later waits for other loads never have to cover these.  A slow
+// bin's entries are not used (the slow path reads the bucket).
 template <typename VT, int NT, int EPT>
 __device__ __forceinline__ void bin_load(const ChunkArgs<VT>& a, const BinSrc& src,
                                          BinRegs<VT, EPT>& r) {
-  const int span = r.e1 - r.e0;
-  if (span > a.cap) return;  // slow path: read from the bucket there
+  const int last = max(r.e1 - r.e0 - 1, 0);
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int i = threadIdx.x + j * NT;
-    if (i < span) r.en[j] = load_entry<VT>(&a.bucket[r.e0 + i]);
+    r.en[j] = load_entry<VT>(&a.bucket[r.e0 + min(i, last)]);
   }
 }
 
@@ -1614,7 +1628,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   // next bin: its range now, its entries once the placement is done
   nx.q = (int)x.misc()[7];
   uint32_t nfill = 0;
-  if (nx.q < src.B) bin_bounds(src, nx, nfill);
+  bin_bounds(src, nx, nfill);
 
   FSP_PHASE(a, q, 3)
   // distinct pairs per column -> offsets; publish the bin's count now, read
@@ -1703,10 +1717,8 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
         sval[o] = vr[j];
       }
     }
-    if (nx.q < src.B) {
-      bin_range(src, nx, nfill);
-      bin_load<VT, NT, EPT>(a, src, nx);
-    }
+    bin_range(src, nx, nfill);
+    bin_load<VT, NT, EPT>(a, src, nx);
     if (tid < 64) probe = lookback_probe(a.status, q);
   } else {
   // place triplets into their groups, then order each group by k
@@ -1731,10 +1743,8 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
       mgrp[posr[j]] = orr[j];
     }
   }
-  if (nx.q < src.B) {
-    bin_range(src, nx, nfill);
-    bin_load<VT, NT, EPT>(a, src, nx);
-  }
+  bin_range(src, nx, nfill);
+  bin_load<VT, NT, EPT>(a, src, nx);
   if (tid < 64) probe = lookback_probe(a.status, q);
   __syncthreads();
   FSP_PHASE(a, q, 15)
