@@ -1,8 +1,9 @@
 // Device code of the gfx950 sparse-assembly pipeline.
 //
 // Fresh assembly of S = sparse(ii, jj, ss, m, n) (Section 2.1).  Columns are
-// grouped into bins of w = 2^s consecutive columns, sized so an average bin
-// fills about half the LDS of one sort/fold workgroup.
+// grouped into bins of w consecutive columns (any w; an in-bin column takes
+// s bits, 2^s >= w), sized so an average bin fills 80% of the LDS of one bin
+// workgroup.
 //   count    per-tile LDS histograms of bins (dense mode: a tiles x bins
 //            count matrix; claim mode: one device atomic per (tile, bin));
 //            out-of-range columns are flagged here (pre-processing listing)
@@ -20,7 +21,9 @@
 //            each pair's contributions are put in increasing k and folded
 //            from +0.0 in that order (the serial post-processing order);
 //            the bin's output offset comes from a chained look-back over the
-//            bins, which also gives jcS (Part 4's running sum).
+//            bins, which also gives jcS (Part 4's running sum).  A bin
+//            longer than the LDS is counted before this kernel and emitted
+//            after it (k_slow_count, k_slow_emit).
 // The sorted order of the contributions (perm) and the first sorted
 // position of every output (seg) are kept for pattern re-use; slot[k] is
 // the paper's inverse rank irank (Section 2.2, eqs. (2.2)-(2.3)).
