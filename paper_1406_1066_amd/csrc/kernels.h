@@ -1760,13 +1760,20 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
     const uint32_t o = mgrp[p];
     const uint32_t g0 = gs[o], g1 = gs[o + 1];
     const uint32_t kk = mk[p];
-    uint32_t r4[4] = {0u, 0u, 0u, 0u};
+    // eight reads in flight per step while eight remain, then four, then
+    // one at a time
+    uint32_t r8[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     uint32_t t = g0;
-    for (; t + 4 <= g1; t += 4) {
+    for (; t + 8 <= g1; t += 8) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) r4[u] += mk[t + u] < kk ? 1u : 0u;
+      for (int u = 0; u < 8; ++u) r8[u] += mk[t + u] < kk ? 1u : 0u;
     }
-    uint32_t rk = (r4[0] + r4[1]) + (r4[2] + r4[3]);
+    if (t + 4 <= g1) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) r8[u] += mk[t + u] < kk ? 1u : 0u;
+      t += 4;
+    }
+    uint32_t rk = ((r8[0] + r8[1]) + (r8[2] + r8[3])) + ((r8[4] + r8[5]) + (r8[6] + r8[7]));
     for (; t < g1; ++t) rk += mk[t] < kk ? 1u : 0u;
     sval[g0 + rk] = mval[p];
     spos[jj] = g0 + rk;
