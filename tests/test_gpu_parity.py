@@ -213,3 +213,33 @@ def test_huge_row_indices(fs):
     ii = rng.integers(m - 50, m + 1, size=5000).astype(np.int32)
     jj = rng.integers(1, 301, size=5000).astype(np.int32)
     check(fs, ii, jj, rng.standard_normal(5000), m, 300)
+
+
+@pytest.mark.parametrize("c,n,L", [(2048, 1000, 60_000), (2048, 3000, 100_000),
+                                   (64, 997, 20_000), (64, 300, 5_000),
+                                   (2048, 12_345, 9_000)])
+def test_bin_widths(fs, cap, c, n, L):
+    # average bin fill fixes the bin width: these give widths that are and
+    # are not powers of two, with a ragged last bin, and repeated pairs
+    cap(c)
+    t = W.uniform(L, 5000, n, seed=17 + n)
+    k = L // 5
+    ii = np.concatenate([t.ii, t.ii[:k]])
+    jj = np.concatenate([t.jj, t.jj[:k]])
+    ss = np.concatenate([t.ss, np.arange(k, dtype=np.float64) * 0.25])
+    check(fs, ii, jj, ss, t.m, t.n)
+
+
+@pytest.mark.parametrize("m", [2**30 - 1, 2**30])
+def test_packed_word_limit(fs, cap, m):
+    # with a 64-entry capacity, 300 columns and 5000 triplets the bins are 3
+    # columns wide (2 bits): rows below 2^30 share a word with the column (the
+    # largest such word is just below the hash table's empty mark), 2^30 rows
+    # do not
+    cap(64)
+    rng = np.random.default_rng(18)
+    ii = rng.integers(m - 40, m + 1, size=5000).astype(np.int32)
+    jj = rng.integers(1, 301, size=5000).astype(np.int32)
+    ii[:100] = m
+    jj[:100] = 300
+    check(fs, ii, jj, rng.standard_normal(5000), m, 300)
