@@ -1814,29 +1814,54 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
       for (int p = tid; p < span; p += NT) a.slot[mk[p]] = (int32_t)(base + mgrp[p]);
     }
   }
+  // a thread's outputs (at most EPT: D <= span <= CAP) go through each step
+  // together, so that their LDS reads overlap: bounds and rows, first terms,
+  // remaining terms, stores
   bool over = false;
-  for (int o = tid; o < (int)D; o += NT) {
-    const uint32_t g0 = uniq ? (uint32_t)o : gs[o];
-    const uint32_t g1 = uniq ? (uint32_t)o + 1u : gs[o + 1];
-    // left fold from +0.0 in increasing k; loads four ahead
-    VT acc = (VT)0;
-    uint32_t t = g0;
-    for (; t + 4 <= g1; t += 4) {
+  uint32_t g0[EPT], g1[EPT], rw[EPT];
+  VT acc[EPT];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int o = tid + u * NT;
+    g0[u] = 0u;
+    g1[u] = 0u;
+    if (o < (int)D) {
+      g0[u] = uniq ? (uint32_t)o : gs[o];
+      g1[u] = uniq ? (uint32_t)o + 1u : gs[o + 1];
+      rw[u] = grow[o];
+    }
+  }
+  // left fold from +0.0 in increasing k
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    acc[u] = (VT)0;
+    if (g0[u] < g1[u]) acc[u] = acc[u] + sval[g0[u]];
+  }
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    uint32_t t = g0[u] + 1u;
+    for (; t + 4 <= g1[u]; t += 4) {
       const VT v0 = sval[t], v1 = sval[t + 1], v2 = sval[t + 2], v3 = sval[t + 3];
-      acc = acc + v0;
-      acc = acc + v1;
-      acc = acc + v2;
-      acc = acc + v3;
+      acc[u] = acc[u] + v0;
+      acc[u] = acc[u] + v1;
+      acc[u] = acc[u] + v2;
+      acc[u] = acc[u] + v3;
     }
-    for (; t < g1; ++t) acc = acc + sval[t];
-    const int64_t out = base + o;
-    if (out < a.out_cap) {
-      a.irS[out] = (int32_t)(grow[o] >> a.rshift);
-      a.prS[out] = acc;
-    } else {
-      over = true;
+    for (; t < g1[u]; ++t) acc[u] = acc[u] + sval[t];
+  }
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int o = tid + u * NT;
+    if (o < (int)D) {
+      const int64_t out = base + o;
+      if (out < a.out_cap) {
+        a.irS[out] = (int32_t)(rw[u] >> a.rshift);
+        a.prS[out] = acc[u];
+      } else {
+        over = true;
+      }
+      if (a.seg) a.seg[out] = (int32_t)(e0 + g0[u] + pshift);
     }
-    if (a.seg) a.seg[out] = (int32_t)(e0 + g0 + pshift);
   }
   if (over) atomicOr(&a.ctrl->err, kErrCap);
   for (int c = tid; c < wc; c += NT) a.jcS[c0 + c] = (int32_t)(base + cd[c << a.nbl]);
