@@ -565,9 +565,18 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t L, int32_t TS) {
   return t < T ? t : -1;
 }
 
-// triplets whose loads one thread of the dense count (scatter) pass keeps
-// in flight
+// Element x of p by a 32-bit byte offset (x * sizeof(T) < 2^32): with p in
+// scalar registers the load needs one vector register for its address.
+template <typename T>
+__device__ __forceinline__ T ld_off32(const T* __restrict__ p, uint32_t x) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) +
+                                     x * (uint32_t)sizeof(T));
+}
+
+// triplets whose loads one thread keeps in flight: dense count, dense
+// scatter, claim scatter
 constexpr int kDenseU = 8;
+constexpr int kDenseSU = 8;
 constexpr int kScatterU = 4;
 
 // dense mode, pass 1: per-tile bin histogram -> row `tile` of cnt[T][B]
@@ -690,26 +699,33 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
   mat_cur<BATCHED>(bd, b, tile_first_mat<BATCHED>(bd, t0, L, &sB));
   __syncthreads();
   bool badr = false;
-  // the loads of kScatterU triplets are issued together, then their LDS
+  // the loads of kDenseSU triplets are issued together, then their LDS
   // ranks, then their stores (a triplet without a place, past the tile or
   // with a bad column, is stored to the spare place `trash`, so that the
   // stores need no branch)
+  // (loads address the tile's arrays by 32-bit offsets from tile bases held
+  // in scalar registers, which keeps eight triplets' loads within the
+  // register budget)
   const int64_t nt = blockDim.x;
-  for (int64_t eb = t0 + threadIdx.x; eb < t1; eb += kScatterU * nt) {
-    int32_t cj[kScatterU], ri[kScatterU];
-    VT sv[kScatterU];
+  const int32_t* __restrict__ jt = jj + t0;
+  const int32_t* __restrict__ it = ii + t0;
+  const VT* __restrict__ st = ss + t0;
+  for (int64_t eb = t0 + threadIdx.x; eb < t1; eb += kDenseSU * nt) {
+    int32_t cj[kDenseSU], ri[kDenseSU];
+    VT sv[kDenseSU];
 #pragma unroll
-    for (int u = 0; u < kScatterU; ++u) {
+    for (int u = 0; u < kDenseSU; ++u) {
       const int64_t e = eb + u * nt;
       if (e < t1) {
-        cj[u] = jj[e];
-        ri[u] = ii[e];
-        sv[u] = ss[e];
+        const uint32_t x = (uint32_t)(e - t0);
+        cj[u] = ld_off32(jt, x);
+        ri[u] = ld_off32(it, x);
+        sv[u] = ld_off32(st, x);
       }
     }
-    uint32_t pos[kScatterU], key[kScatterU], bc[kScatterU];
+    uint32_t pos[kDenseSU], key[kDenseSU], bc[kDenseSU];
 #pragma unroll
-    for (int u = 0; u < kScatterU; ++u) {
+    for (int u = 0; u < kDenseSU; ++u) {
       const int64_t e = eb + u * nt;
       pos[u] = trash;
       if (e < t1) {
@@ -727,7 +743,7 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
       }
     }
 #pragma unroll
-    for (int u = 0; u < kScatterU; ++u) {
+    for (int u = 0; u < kDenseSU; ++u) {
       store_entry<VT>(&bucket[pos[u]], key[u], (uint32_t)(eb + u * nt), sv[u]);
       if (!PACKED) bcol[pos[u]] = bc[u];
     }
