@@ -293,7 +293,9 @@ Layout make_layout(int64_t L, int64_t N, int nb, int esize, const Tuning& tu) {
   Layout o{};
   o.g = make_geom(L, N, tu.cap, tu.bmode, tu.sblock);
   const int64_t B = o.g.B;
-  o.nscan = (B + 1 + kScanTile - 1) / kScanTile;
+  // look-back words: scan tiles of the bin scan, or 64-bin groups of the
+  // dense column scan
+  o.nscan = std::max<int64_t>((B + 1 + kScanTile - 1) / kScanTile, (B + 63) / 64);
   size_t p = 0;
   o.ctrl = p;        p = al(p + sizeof(Ctrl));
   o.scan_st = p;     p = al(p + 8 * (size_t)o.nscan);
@@ -509,20 +511,23 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
                          kClaimWindow, bincnt, ctrl);
   });
   if (e != hipSuccess) return e;
+  // 2. bin pointers (dense mode: with the column scan of the count matrix)
   if (mode == kDense) {
     e = launch(kColScan, stream, [&] {
-      hipLaunchKernelGGL(fsp::k_colscan<1024>, dim3((unsigned)((B + 63) / 64)),
-                         dim3(1024), 0, stream, cntmat, (int32_t)g.T, B, bincnt);
+      hipLaunchKernelGGL(fsp::k_colscan_bins<1024>, dim3((unsigned)((B + 63) / 64)),
+                         dim3(1024), 0, stream, cntmat, (int32_t)g.T, B, binstart,
+                         at<uint64_t>(ws, lo.scan_st), &ctrl->tick_scan,
+                         (uint32_t)tu.cap, &ctrl->nslow, at<int32_t>(ws, lo.slowlist));
     });
-    if (e != hipSuccess) return e;
+  } else if (mode != kSlot) {
+    e = launch(kScan, stream, [&] {
+      hipLaunchKernelGGL((fsp::k_scan_excl<kScanNT, kScanIPT>),
+                         dim3((unsigned)((B + 1 + kScanTile - 1) / kScanTile)),
+                         dim3(kScanNT), 0, stream, bincnt, B, binstart,
+                         at<uint64_t>(ws, lo.scan_st), &ctrl->tick_scan,
+                         (uint32_t)tu.cap, &ctrl->nslow, at<int32_t>(ws, lo.slowlist));
+    });
   }
-  // 2. bin pointers
-  if (mode != kSlot) e = launch(kScan, stream, [&] {
-    hipLaunchKernelGGL((fsp::k_scan_excl<kScanNT, kScanIPT>), dim3((unsigned)lo.nscan),
-                       dim3(kScanNT), 0, stream, bincnt, B, binstart,
-                       at<uint64_t>(ws, lo.scan_st), &ctrl->tick_scan,
-                       (uint32_t)tu.cap, &ctrl->nslow, at<int32_t>(ws, lo.slowlist));
-  });
   if (e != hipSuccess) return e;
   // 3. scatter into the bins
   e = launch(kBucket, stream, [&] {

@@ -619,18 +619,28 @@ __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
   if (bad) atomicOr(&ctrl->err, kErrCol);
 }
 
-// dense mode, pass 2: for every bin, exclusive prefix over the tiles (in
-// place) and the bin total.  A block takes 64 bins (one per lane, so every
-// row access is coalesced) and splits the tiles into NT/64 segments that are
-// summed in parallel and then rewritten as running prefixes.
+// dense mode, pass 2 and the bin pointers in one kernel: the column prefix
+// sums of the count matrix give every tile its offset inside every bin, and
+// the bin totals, chained over groups of 64 bins by a look-back, give the
+// bin pointers (binstart[B] is the total).  A block takes 64 bins (one per
+// lane, so every row access is coalesced) and splits the tiles into NT/64
+// segments that are summed in parallel and then rewritten as running
+// prefixes.  Groups are taken by ticket, so a group waits only for groups
+// already started.  Bins above `cap` are appended to slowlist.
 template <int NT>
 __global__ void __launch_bounds__(NT)
-k_colscan(uint32_t* __restrict__ cnt, int32_t T, int32_t B,
-          uint32_t* __restrict__ tot) {
+k_colscan_bins(uint32_t* __restrict__ cnt, int32_t T, int32_t B,
+               int32_t* __restrict__ binstart, uint64_t* status, uint32_t* ticket,
+               uint32_t cap, uint32_t* __restrict__ nslow,
+               int32_t* __restrict__ slowlist) {
   constexpr int NSEG = NT / 64;
   __shared__ uint32_t part[NSEG][64];
+  __shared__ int sG;
+  if (threadIdx.x == 0) sG = (int)atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int grp = sG;
   const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
-  const int b = blockIdx.x * 64 + lane;
+  const int b = grp * 64 + lane;
   const int per = (T + NSEG - 1) / NSEG;
   const int t0 = min(T, seg * per), t1 = min(T, t0 + per);
   uint32_t sum = 0;
@@ -654,8 +664,17 @@ k_colscan(uint32_t* __restrict__ cnt, int32_t T, int32_t B,
     run += k < seg ? v : 0u;
     all += v;
   }
+  if (seg == 0) {
+    const uint32_t mine = b < B ? all : 0u;
+    const uint32_t inc = wave_incl_sum(mine);
+    const int64_t base = lookback(status, grp, (uint64_t)lane63(inc));
+    if (b < B) {
+      binstart[b] = (int32_t)(base + inc - mine);
+      if (mine > cap) slowlist[atomicAdd(nslow, 1u)] = b;
+    }
+    if (b == B - 1) binstart[B] = (int32_t)(base + inc);
+  }
   if (b >= B) return;
-  if (seg == 0) tot[b] = all;
   int t = t0;
   for (; t + 8 <= t1; t += 8) {
     uint32_t c[8];
