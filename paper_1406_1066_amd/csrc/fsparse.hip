@@ -282,7 +282,7 @@ struct Layout {
   Geom g;
   int64_t mmax;  // largest m over the matrices (batched)
   size_t ctrl, scan_st, bin_st, bincnt, binfill, bmax, zero_end;
-  size_t binstart, cntmat, bcol, colptr, bucket, tmp, perm, seg, islot, rtile;
+  size_t binstart, cntmat, tilebad, bcol, colptr, bucket, tmp, perm, seg, islot, rtile;
   size_t slowlist, slowd, slowb;
   size_t b_trip, b_col, b_m, b_n, jcg, nnzoff;
   size_t total;
@@ -306,6 +306,7 @@ Layout make_layout(int64_t L, int64_t N, int nb, int esize, const Tuning& tu) {
   o.zero_end = p;
   o.binstart = p;    p = al(p + 4 * (size_t)(B + 1));
   o.cntmat = p;      p = al(p + (o.g.dense ? 4 * (size_t)o.g.T * B : 0));
+  o.tilebad = p;     p = al(p + (o.g.dense ? 4 * (size_t)o.g.T : 0));
   const int64_t nb_places = std::max(L, o.g.nslot);
   // one spare place past the end of the bucket (and of bcol)
   o.bcol = p;        p = al(p + 4 * (size_t)(nb_places + 1));
@@ -478,11 +479,15 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   Ctrl* ctrl = at<Ctrl>(ws, lo.ctrl);
   hipError_t e;
   const int64_t zwords = (int64_t)(lo.zero_end / 4);
-  e = launch(kInit, stream, [&] {
-    hipLaunchKernelGGL(fsp::k_zero, dim3(grid_for(zwords, 256, 4)), dim3(256), 0,
-                       stream, at<uint32_t>(ws, 0), zwords);
-  });
-  if (e != hipSuccess) return e;
+  // the dense count pass clears the control block and look-back words
+  // itself; the other modes need them cleared first
+  if (mode != kDense) {
+    e = launch(kInit, stream, [&] {
+      hipLaunchKernelGGL(fsp::k_zero, dim3(grid_for(zwords, 256, 4)), dim3(256), 0,
+                         stream, at<uint32_t>(ws, 0), zwords);
+    });
+    if (e != hipSuccess) return e;
+  }
   uint32_t* bincnt = at<uint32_t>(ws, lo.bincnt);
   uint32_t* binfill = at<uint32_t>(ws, lo.binfill);
   int32_t* binstart = at<int32_t>(ws, lo.binstart);
@@ -503,7 +508,8 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
     if (mode == kDense)
       hipLaunchKernelGGL(fsp::k_count_dense<BATCHED>, dim3((unsigned)(8 * ((g.T + 7) / 8))), dim3(blk),
                          (size_t)B * 4, stream, jj, L, n, bd, G, B, (int32_t)g.TS,
-                         cntmat, ctrl);
+                         cntmat, at<uint32_t>(ws, 0), zwords,
+                         at<uint32_t>(ws, lo.tilebad));
     else
       hipLaunchKernelGGL((fsp::k_count_claim<BATCHED, kClaimNT, kClaimIPT>),
                          dim3((unsigned)g.T), dim3(kClaimNT),
@@ -517,7 +523,8 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
       hipLaunchKernelGGL(fsp::k_colscan_bins<1024>, dim3((unsigned)((B + 63) / 64)),
                          dim3(1024), 0, stream, cntmat, (int32_t)g.T, B, binstart,
                          at<uint64_t>(ws, lo.scan_st), &ctrl->tick_scan,
-                         (uint32_t)tu.cap, &ctrl->nslow, at<int32_t>(ws, lo.slowlist));
+                         (uint32_t)tu.cap, &ctrl->nslow, at<int32_t>(ws, lo.slowlist),
+                         at<uint32_t>(ws, lo.tilebad), ctrl);
     });
   } else if (mode != kSlot) {
     e = launch(kScan, stream, [&] {

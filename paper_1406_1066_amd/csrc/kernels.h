@@ -579,14 +579,22 @@ constexpr int kDenseU = 8;
 constexpr int kDenseSU = 8;
 constexpr int kScatterU = 4;
 
-// dense mode, pass 1: per-tile bin histogram -> row `tile` of cnt[T][B]
+// dense mode, pass 1: per-tile bin histogram -> row `tile` of cnt[T][B].
+// As the first kernel of the call it also clears the control block and the
+// look-back words (zero[0..zwords)), which no later kernel of the call uses
+// before it is done; so it reports a bad column not in the control block
+// but in its own word tilebad[tile], which the column scan reads.
 template <bool BATCHED>
 __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
                               int32_t n, BatchDesc bd, BinGeo G, int32_t B,
                               int32_t TS, uint32_t* __restrict__ cnt,
-                              Ctrl* ctrl) {
+                              uint32_t* __restrict__ zero, int64_t zwords,
+                              uint32_t* __restrict__ tilebad) {
   extern __shared__ uint32_t hist[];
   __shared__ int sB;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < zwords;
+       i += (int64_t)gridDim.x * blockDim.x)
+    zero[i] = 0u;
   const int64_t tile = xcd_tile(L, TS);
   if (tile < 0) return;
   const int64_t t0 = tile * TS;
@@ -616,7 +624,8 @@ __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
   __syncthreads();
   uint32_t* row = cnt + tile * B;
   for (int i = threadIdx.x; i < B; i += blockDim.x) row[i] = hist[i];
-  if (bad) atomicOr(&ctrl->err, kErrCol);
+  const int anybad = __syncthreads_or(bad ? 1 : 0);
+  if (threadIdx.x == 0) tilebad[tile] = anybad ? 1u : 0u;
 }
 
 // dense mode, pass 2 and the bin pointers in one kernel: the column prefix
@@ -626,19 +635,26 @@ __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
 // lane, so every row access is coalesced) and splits the tiles into NT/64
 // segments that are summed in parallel and then rewritten as running
 // prefixes.  Groups are taken by ticket, so a group waits only for groups
-// already started.  Bins above `cap` are appended to slowlist.
+// already started.  Bins above `cap` are appended to slowlist.  The first
+// group also raises the bad-column flag from the count pass's tile words.
 template <int NT>
 __global__ void __launch_bounds__(NT)
 k_colscan_bins(uint32_t* __restrict__ cnt, int32_t T, int32_t B,
                int32_t* __restrict__ binstart, uint64_t* status, uint32_t* ticket,
                uint32_t cap, uint32_t* __restrict__ nslow,
-               int32_t* __restrict__ slowlist) {
+               int32_t* __restrict__ slowlist,
+               const uint32_t* __restrict__ tilebad, Ctrl* ctrl) {
   constexpr int NSEG = NT / 64;
   __shared__ uint32_t part[NSEG][64];
   __shared__ int sG;
   if (threadIdx.x == 0) sG = (int)atomicAdd(ticket, 1u);
   __syncthreads();
   const int grp = sG;
+  if (grp == 0) {
+    int bad = 0;
+    for (int i = threadIdx.x; i < T; i += NT) bad |= tilebad[i] ? 1 : 0;
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&ctrl->err, kErrCol);
+  }
   const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
   const int b = grp * 64 + lane;
   const int per = (T + NSEG - 1) / NSEG;
