@@ -53,7 +53,12 @@ def _dt(dtype) -> int:
     raise TypeError("values must be float64 or float32, got %s" % dtype)
 
 
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream():
+    if _raw_stream is not None:
+        return ctypes.c_void_p(_raw_stream(torch.cuda.current_device()))
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
@@ -64,6 +69,9 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 def _dev_i32(x, device) -> torch.Tensor:
+    if (isinstance(x, torch.Tensor) and x.dtype == torch.int32 and
+            x.device == device and x.is_contiguous()):
+        return x
     t = torch.as_tensor(x)
     if t.dtype != torch.int32:
         t = t.to(torch.int32)
@@ -170,9 +178,8 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
         m = dm if m is None else m
         n = dn if n is None else n
     m, n = int(m), int(n)
-    need = workspace_bytes(Ln, n, 1, ss.dtype)
-    if ws is None or ws.numel() < need:
-        ws = _workspace(need, dev)
+    if ws is None:
+        ws = _workspace(workspace_bytes(Ln, n, 1, ss.dtype), dev)
     slot = None
     if out is not None:
         jcS, irS0, prS0 = out[0], out[1], out[2]
@@ -203,6 +210,11 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
         if st == L.E_CAPACITY and info.nnz > cap and irS0 is None:
             cap = int(info.nnz)       # retry with the reported size
             continue
+        if st == L.E_CAPACITY:
+            need = workspace_bytes(Ln, n, 1, ss.dtype)
+            if ws.numel() < need:     # a given workspace that is too small
+                ws = _workspace(need, dev)
+                continue
         _check(st, "fsparse_assemble")
         break
     nnz = int(info.nnz)
