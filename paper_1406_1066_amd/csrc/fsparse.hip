@@ -474,7 +474,7 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
                         int64_t N, const Layout& lo, const Tuning& tu,
                         void* ws, int32_t* jcS_target, int32_t* irS, VT* prS,
                         int64_t cap, int32_t* slot, bool keep_plan,
-                        int mode, hipStream_t stream) {
+                        int mode, hipStream_t stream, Ctrl* hostctrl = nullptr) {
   const Geom& g = lo.g;
   Ctrl* ctrl = at<Ctrl>(ws, lo.ctrl);
   hipError_t e;
@@ -585,6 +585,7 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   a.slot = slot;
   a.perm = keep_plan ? at<int32_t>(ws, lo.perm) : nullptr;
   a.seg = keep_plan ? at<int32_t>(ws, lo.seg) : nullptr;
+  a.hostctrl = hostctrl;
 #ifdef FSP_PHASE_TIMING
   a.phase = g_phase;
 #endif
@@ -809,15 +810,15 @@ fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
         e = run_pipeline<double, false>(ii, jj, (const double*)ss, len, (int32_t)m,
                                         (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
                                         (double*)prS, cap, slot_used, keep, mode,
-                                        stream);
+                                        stream, h);
       else
         e = run_pipeline<float, false>(ii, jj, (const float*)ss, len, (int32_t)m,
                                        (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
                                        (float*)prS, cap, slot_used, keep, mode,
-                                       stream);
+                                       stream, h);
       if (e != hipSuccess) return FSPARSE_E_HIP;
       if (keep && launch_reuse_tiles(ws, lo, len, stream) != hipSuccess) return FSPARSE_E_HIP;
-      HIPCHK(hipMemcpyAsync(h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+      // the bin kernel's last block has written err and nnz into h
       HIPCHK(hipStreamSynchronize(stream));
       // a full fixed-capacity bin: count first and redo
       if ((h->err & fsp::kErrSlot) && mode == kSlot) {
@@ -833,7 +834,7 @@ fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
       info->nzmax = std::max<int64_t>(nzmax, nnz);
     }
     if (err & (fsp::kErrCol | fsp::kErrRow)) return FSPARSE_E_INDEX;
-    if (err & fsp::kErrCap) return FSPARSE_E_CAPACITY;
+    if ((err & fsp::kErrCap) || nnz > cap) return FSPARSE_E_CAPACITY;
     if (flags & FSPARSE_ATOMIC) {
       if (!slot_used) {
         // the atomic sum needs the slot map: use the internal one

@@ -988,6 +988,7 @@ struct ChunkArgs {
   int32_t* perm;             // [Ltot] or null: k of the p-th sorted triplet
   int32_t* seg;              // [nnz+1] or null: first sorted position of slot
   uint64_t* phase;           // per-bin phase timestamps (profiling builds only)
+  Ctrl* hostctrl;            // host-visible copy of err and nnz, or null
   int32_t rshift;            // rows are stored as (row << rshift) | column
   int64_t pshift;            // compact triplet position = bucket position + pshift
   int32_t nbl;               // rank buckets per column: 2^nbl row ranges
@@ -2088,6 +2089,15 @@ k_bin(ChunkArgs<VT> a, BinSrc src, int32_t w) {
       a.jcS[N] = (int32_t)end;
       a.ctrl->nnz = end;
       if (a.seg) a.seg[end] = (int32_t)misc[5];
+      if (a.hostctrl) {
+        // nnz and the error bits of the earlier kernels go straight to
+        // host-visible memory (visible to the host once the call's stream
+        // is synchronized); a capacity overflow shows as nnz > capacity
+        const uint32_t err =
+            __hip_atomic_load(&a.ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.hostctrl->err, err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&a.hostctrl->nnz, end, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
     }
     __syncthreads();  // the LDS is reused by the next bin
     cur = nx;
