@@ -43,13 +43,16 @@ def kernel_hash() -> str:
 def stage_bytes(stage, L, nnz, n, vb, eb, plan=False, slot=False):
     """Algorithmic bytes of one launch of a stage: every array the stage
     must read or write, touched once.  eb = bytes of one binned triplet
-    (row, k, value), vb = bytes of one value."""
+    (row and in-bin column in one word, k, value), vb = bytes of one value.
+    (Inputs whose rows and in-bin columns do not share a word add a 4-byte
+    column per triplet to the scatter and the bin kernel; none of the
+    configured workloads does.)"""
     if stage == "count":
         return 4 * L
     if stage == "scatter":
-        return (8 + vb) * L + (eb + 4) * L
+        return (8 + vb) * L + eb * L
     if stage == "bin":
-        b = (eb + 4) * L + (4 + vb) * nnz + 4 * (n + 1)
+        b = eb * L + (4 + vb) * nnz + 4 * (n + 1)
         if slot:
             b += 4 * L
         if plan:
