@@ -196,6 +196,7 @@ constexpr int kScanIPT = 16;
 constexpr int64_t kScanTile = (int64_t)kScanNT * kScanIPT;
 constexpr int64_t kDenseBins = 16384;       // LDS counters of the dense mode
 constexpr int kBinFill = 80;                // percent of the capacity per bin
+constexpr int kSlotFill = 88;               // the same with fixed-capacity bins
 constexpr int64_t kDenseMatrix = 8 << 20;   // tiles x bins counters
 constexpr int kClaimNT = 256;
 constexpr int kClaimIPT = 16;
@@ -219,15 +220,13 @@ struct Geom {
   int64_t nslot;    // bucket places of the slot mode
 };
 
-Geom make_geom(int64_t L, int64_t N, int cap, int force_mode, int blk) {
-  Geom g{};
+// Bin width for an average fill of `fill` percent of the capacity, and the
+// multiply-shift that divides by it.
+void set_width(Geom& g, int64_t L, int64_t N, int cap, int fill) {
   int64_t w = 1;
   if (L > 0) {
-    // an average bin fills kBinFill percent of the LDS capacity: a bin's
-    // cost is mostly latency, so fuller bins mean fewer of them; a bin that
-    // still overflows takes the slow path
     const double target =
-        std::max(1.0, (double)cap * kBinFill / 100.0) * (double)N / (double)L;
+        std::max(1.0, (double)cap * fill / 100.0) * (double)N / (double)L;
     w = (int64_t)std::min<double>(target, (double)cap);
     w = std::max<int64_t>(1, w);
   }
@@ -242,7 +241,28 @@ Geom make_geom(int64_t L, int64_t N, int cap, int force_mode, int blk) {
     g.mul = (uint32_t)(((uint64_t(1) << g.sh) + (uint64_t)w - 1) / (uint64_t)w);
   }
   g.B = std::max<int64_t>(1, (N + w - 1) / w);
-  g.dense = g.B <= kDenseBins;
+}
+
+Geom make_geom(int64_t L, int64_t N, int cap, int force_mode, int blk) {
+  Geom g{};
+  // an average bin fills kBinFill percent of the LDS capacity: a bin's cost
+  // is mostly latency, so fuller bins mean fewer of them; a bin that still
+  // overflows takes the slow path
+  set_width(g, L, N, cap, kBinFill);
+  // few bins: a tiles x bins count matrix gives the tile offsets (dense);
+  // many bins: every bin gets a fixed place of `cap` triplets so one pass
+  // (claims per tile and bin) places the triplets, and an overflowing bin
+  // makes the call fall back to counting first (kClaim)
+  const bool fits_dense = g.B <= kDenseBins;
+  const bool fits_slot = g.B * (int64_t)cap < (int64_t(1) << 31);
+  g.mode = fits_dense ? kDense : (fits_slot ? kSlot : kClaim);
+  if (force_mode == 1 + kDense && fits_dense) g.mode = kDense;
+  if (force_mode == 1 + kSlot && fits_slot) g.mode = kSlot;
+  if (force_mode == 1 + kClaim) g.mode = kClaim;
+  // fixed places: fuller bins still (kSlotFill; a place overflows only far
+  // out in the tail of a bin's size)
+  if (g.mode == kSlot) set_width(g, L, N, cap, kSlotFill);
+  g.dense = g.mode == kDense;
   if (g.dense) {
     // tiles x bins count matrix: at most kDenseMatrix words, and while at
     // least 512 tiles remain, at most L/4 words (its passes then move about
@@ -262,18 +282,10 @@ Geom make_geom(int64_t L, int64_t N, int cap, int force_mode, int blk) {
     const int64_t T = (L + g.TS - 1) / g.TS;
     if (T > R && T < 2 * R) g.TS = (L + R - 1) / R;
   } else {
-    g.TS = (int64_t)kClaimNT * kClaimIPT;
+    g.TS = (int64_t)kClaimNT * kClaimIPT;  // the claim kernels' tile
   }
   g.T = std::max<int64_t>(1, (L + g.TS - 1) / g.TS);
-  // many bins: give every bin a fixed place of `cap` triplets so one pass
-  // (claims per tile and bin) places the triplets; an overflowing bin makes
-  // the call fall back to counting first (kClaim)
   g.slotcap = cap;
-  g.mode = g.dense ? kDense
-                   : (g.B * (int64_t)cap < (int64_t(1) << 31) ? kSlot : kClaim);
-  if (force_mode == 1 + kDense && g.dense) g.mode = kDense;
-  if (force_mode == 1 + kSlot && g.B * (int64_t)cap < (int64_t(1) << 31)) g.mode = kSlot;
-  if (force_mode == 1 + kClaim) g.mode = kClaim;
   g.nslot = g.mode == kSlot ? g.B * (int64_t)cap : 0;
   return g;
 }

@@ -243,3 +243,16 @@ def test_packed_word_limit(fs, cap, m):
     ii[:100] = m
     jj[:100] = 300
     check(fs, ii, jj, rng.standard_normal(5000), m, 300)
+
+
+@pytest.mark.parametrize("mode", ["slot", "claim"])
+def test_forced_modes_on_dense_geometry(fs, mode):
+    # 3M triplets over few bins: the dense passes would use tiles larger than
+    # the claim kernels' (one round of resident blocks); a forced claim or
+    # slot mode must still cover every triplet with its own tiles
+    fs.set_tuning(chunk_cap=2048, stream_block=512, bin_mode=mode)
+    try:
+        t = W.uniform(3_000_000, 20_000, 30_000, seed=19)
+        check(fs, t.ii, t.jj, t.ss, t.m, t.n)
+    finally:
+        fs.set_tuning(reset=True)
