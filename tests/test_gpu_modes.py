@@ -191,3 +191,28 @@ def test_batched_bad_index(fs):
         fs.assemble_batched(to_dev(np.array([1, 3], np.int32)),
                             to_dev(np.array([1, 1], np.int32)),
                             to_dev(np.ones(2)), [0, 1, 2], [2, 2], [2, 2])
+
+
+@pytest.mark.parametrize("mode", ["auto", "dense", "slot", "claim"])
+def test_batched_modes_fp32(fs, mode):
+    # every bin mode on a batch of single-precision matrices, bins spanning
+    # matrix boundaries (small capacity)
+    fs.set_tuning(chunk_cap=256, bin_mode=mode)
+    try:
+        mats = []
+        for s in (3, 40, 17, 9):
+            t = W.fem2d(s, 0.2, seed=200 + s, dtype=np.float32)
+            mats.append((t.ii, t.jj, t.ss, t.m, t.n))
+        u = W.uniform(20_000, 500, 300, seed=21, dtype=np.float32)
+        mats.append((u.ii, u.jj, u.ss, u.m, u.n))
+        ii, jj, ss, off = _batch_inputs(mats)
+        res = fs.assemble_batched(to_dev(ii), to_dev(jj), to_dev(ss), off,
+                                  [m[3] for m in mats], [m[4] for m in mats])
+        for b, (bi, bj, bs, bm, bn) in enumerate(mats):
+            ref = oracle.assemble(bi, bj, bs, bm, bn)
+            jc, ir, pr = res.matrix(b)
+            np.testing.assert_array_equal(jc.cpu().numpy(), ref.jcS)
+            np.testing.assert_array_equal(ir.cpu().numpy(), ref.irS)
+            assert pr.cpu().numpy().tobytes() == ref.prS.tobytes()
+    finally:
+        fs.set_tuning(reset=True)
