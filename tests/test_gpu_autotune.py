@@ -25,7 +25,10 @@ def test_autotune_small(tmp_path, monkeypatch):
         ii, jj, ss = to_dev(t.ii), to_dev(t.jj), to_dev(t.ss)
         r1 = autotune.tune(ii, jj, ss, t.m, t.n, reps=2)
         assert not r1["cached"]
-        assert len(r1["times_ms"]) == 8 + 3
+        ncand = 1
+        for v in autotune.DEFAULT_SPACE.values():
+            ncand *= len(v)
+        assert len(r1["times_ms"]) == ncand + len(autotune.REUSE_BLOCKS)
         cur = fs.get_tuning()
         for k, v in r1["best"].items():
             if k != "bin_mode":
