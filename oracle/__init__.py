@@ -8,7 +8,8 @@ its Python binding) never imports it and shares no code with it.
 one thread); ``brute`` holds an independent pure-Python dense accumulation
 used to pin the C oracle on tiny inputs.  ``backward`` and ``reassemble``
 are the definitions of the derivative of the assembled values with respect
-to the triplet values and of re-assembly with new values.
+to the triplet values and of re-assembly with new values; ``expand`` writes
+out the triplets of an index-expanded input.
 """
 from __future__ import annotations
 
@@ -171,6 +172,24 @@ def assemble_columns(ii, jj, ss, m: int, n: int, cols: Sequence[int],
         gslot = (np.asarray(full_jcS)[cj].astype(np.int64)
                  + (sub.slot.astype(np.int64) - sub.jcS[cj]))
     return out, kidx, gslot
+
+
+def expand(ii, jj, ss):
+    """The triplets of an index-expanded input, written out.
+
+    Section 2.1 mentions an extension of the input syntax in which indices
+    are used several times as the shapes of the inputs dictate, without
+    detail; the reading taken is broadcasting.  ii, jj and ss (at most 3-D)
+    broadcast by numpy's rules to one grid of shape (P, C, R), and triplet
+    k = r + R*(c + C*p) is the grid element (p, c, r): row-major order, the
+    same as Matlab's column-major order of an R x C x P array.  The expanded
+    call is, by definition, the assembly of these flat arrays.
+    """
+    shape = np.broadcast_shapes(np.shape(ii), np.shape(jj), np.shape(ss))
+    if len(shape) > 3:
+        raise ValueError("operands of at most 3 dimensions")
+    return tuple(np.ascontiguousarray(np.broadcast_to(np.asarray(a), shape))
+                 .reshape(-1) for a in (ii, jj, ss))
 
 
 from . import brute  # noqa: E402  (pure Python, no C)

@@ -324,3 +324,86 @@ def test_backward_definition_fd_and_scatter():
     Wd[pos] = torch.tensor(w)
     (D * Wd).sum().backward()
     assert s.grad.numpy().tobytes() == g.tobytes()
+
+
+# ---------------------------------------------------------------------------
+# index expansion (Section 2.1 mentions it; the reading is broadcasting)
+# ---------------------------------------------------------------------------
+def _expand_by_loops(ii, jj, ss):
+    """Triplets of a broadcast input, one grid point at a time."""
+    ops = [np.asarray(a) for a in (ii, jj, ss)]
+    ops = [a.reshape((1,) * (3 - a.ndim) + a.shape) for a in ops]
+    P = max(a.shape[0] for a in ops)
+    C = max(a.shape[1] for a in ops)
+    R = max(a.shape[2] for a in ops)
+    out = ([], [], [])
+    for p in range(P):
+        for c in range(C):
+            for r in range(R):          # r varies fastest: k = r + R*(c + C*p)
+                for o, a in zip(out, ops):
+                    o.append(a[p if a.shape[0] > 1 else 0,
+                               c if a.shape[1] > 1 else 0,
+                               r if a.shape[2] > 1 else 0])
+    return tuple(np.array(o, dtype=a.dtype) for o, a in zip(out, ops))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_expand_against_loops_and_brute_force(seed):
+    rng = np.random.default_rng(300 + seed)
+    P, C, R = (int(x) for x in rng.integers(1, 5, size=3))
+    shapes = []
+    for _ in range(3):
+        full = [P, C, R]
+        s = [d if rng.random() < 0.6 else 1 for d in full]
+        shapes.append(tuple(s[int(rng.integers(0, 3)):]))  # drop leading dims
+    ii = rng.integers(1, 5, size=shapes[0]).astype(np.int32)
+    jj = rng.integers(1, 4, size=shapes[1]).astype(np.int32)
+    ss = rng.integers(-3, 4, size=shapes[2]).astype(np.float64) * 0.5
+    try:
+        want = _expand_by_loops(ii, jj, ss)
+        np.broadcast_shapes(ii.shape, jj.shape, ss.shape)
+    except ValueError:
+        with pytest.raises(ValueError):
+            oracle.expand(ii, jj, ss)
+        return
+    got = oracle.expand(ii, jj, ss)
+    for g, w in zip(got, want):
+        assert g.dtype == w.dtype and np.array_equal(g, w)
+    r = oracle.assemble(*got, 4, 3)
+    jc, ir, pr, sl = brute.assemble(*want, 4, 3)
+    assert np.array_equal(r.jcS, jc) and np.array_equal(r.irS, ir)
+    assert r.prS.tobytes() == np.asarray(pr).tobytes()
+    assert np.array_equal(r.slot, sl)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_expand_fem_connectivity(dim):
+    # connectivity broadcast against itself gives the element-by-element
+    # emission of the generators (built with repeat/tile), and unit values
+    # count, on the diagonal, the elements around each node
+    t = W.fem2d(7, 0.2, seed=4) if dim == 2 else W.fem3d(4, 0.15, seed=4)
+    conn = t.meta["conn"]
+    ne, nv = conn.shape
+    K = t.ss.reshape(ne, nv, nv)
+    ii, jj, ss = oracle.expand(conn[:, :, None], conn[:, None, :], K)
+    assert np.array_equal(ii, t.ii) and np.array_equal(jj, t.jj)
+    assert ss.tobytes() == t.ss.tobytes()
+    L, nnz = (W.fem2d_counts if dim == 2 else W.fem3d_counts)(t.meta["s"])
+    assert ii.size == L
+    one = np.ones((1, 1, 1))
+    r = oracle.assemble(*oracle.expand(conn[:, :, None], conn[:, None, :], one),
+                        t.m, t.n)
+    assert r.nnz == nnz and r.prS.sum() == L
+    valence = np.bincount(conn.reshape(-1) - 1, minlength=t.n)
+    for c in range(t.n):
+        rows = r.irS[r.jcS[c]:r.jcS[c + 1]]
+        assert r.prS[r.jcS[c] + np.searchsorted(rows, c)] == valence[c]
+
+
+def test_expand_shape_errors():
+    with pytest.raises(ValueError):
+        oracle.expand(np.ones((2, 3), np.int32), np.ones((4,), np.int32),
+                      np.ones(1))
+    with pytest.raises(ValueError):
+        oracle.expand(np.ones((1, 1, 1, 2), np.int32), np.ones(2, np.int32),
+                      np.ones(2))

@@ -164,7 +164,8 @@ def fem2d(s: int, jitter: float = 0.2, seed: int = 0,
             K[:, a, b] = area * (gx[:, a] * gx[:, b] + gy[:, a] * gy[:, b])
     ii, jj, ss = _emit(conn, K, dtype)
     return Triplets(ii, jj, ss, s * s, s * s, f"fem2d(s={s})", per_elem=9,
-                    meta={"s": s, "elements": conn.shape[0]})
+                    meta={"s": s, "elements": conn.shape[0],
+                          "conn": (conn + 1).astype(np.int32)})
 
 
 _KUHN = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
@@ -240,7 +241,8 @@ def fem3d(s: int, jitter: float = 0.15, seed: int = 0,
                                         + gr[:, a, 2] * gr[:, b, 2])
     ii, jj, ss = _emit(conn, K, dtype)
     return Triplets(ii, jj, ss, N, N, f"fem3d(s={s})", per_elem=16,
-                    meta={"s": s, "elements": ne})
+                    meta={"s": s, "elements": ne,
+                          "conn": (conn + 1).astype(np.int32)})
 
 
 def element_scale(t: Triplets, step: int, seed: int) -> np.ndarray:
