@@ -131,6 +131,51 @@ fsparse_status fsparse_assemble(const int32_t *ii, const int32_t *jj,
                                 hipStream_t stream);
 
 /*
+ * Index expansion (Section 2.1 mentions an extension of the input syntax in
+ * which row and column indices are used several times as the shapes of the
+ * inputs dictate; the paper gives no detail, so this library defines it as
+ * broadcasting).  The triplets form a grid of shape[0] x shape[1] x shape[2]
+ * = R x C x P; triplet number k = r + R*(c + C*p) (Matlab's column-major
+ * order of an R x C x P array).  Each of ii, jj, ss is a dense array in the
+ * same order whose shape has, in every dimension d, either 1 (the operand is
+ * repeated along d) or shape[d].  Triplet k reads each operand at its (r,c,p)
+ * with the repeated dimensions' coordinates set to 0.
+ *
+ * Example, finite elements with nv nodes per element and P elements:
+ * ii = connectivity with shape {1, nv, P}, jj = the same array with shape
+ * {nv, 1, P}, ss = element matrices with shape {nv, nv, P}, where
+ * ss[r + nv*(c + nv*p)] couples row node c and column node r of element p.
+ * This reads nv indices per element instead of 2*nv*nv.
+ */
+typedef struct {
+  int64_t shape[3];     /* R, C, P; R*C*P <= 2^31 - 1 triplets   */
+  int64_t ii_shape[3];  /* each entry 1 or shape[d]                */
+  int64_t jj_shape[3];
+  int64_t ss_shape[3];
+} fsparse_expand;
+
+/*
+ * Fresh assembly of the expanded triplets: the same as fsparse_assemble on
+ * the len = R*C*P triplets that `x` describes (same arguments, outputs,
+ * errors and waits), without forming them.  Additional errors:
+ * FSPARSE_E_ARG for an operand dimension that is neither 1 nor the grid's,
+ * for R*C*P >= 2^31, and for FSPARSE_ATOMIC when ss is repeated along some
+ * dimension.  slot, the plan and fsparse_workspace_bytes count the expanded
+ * triplets (len = R*C*P); re-use (fsparse_assemble_reuse) and
+ * fsparse_backward then take and give values for all R*C*P triplets, in
+ * triplet order.  Default dimensions are the largest entries of ii and jj.
+ */
+fsparse_status fsparse_assemble_expand(const int32_t *ii, const int32_t *jj,
+                                       const void *ss, fsparse_dtype dt,
+                                       const fsparse_expand *x, int64_t m,
+                                       int64_t n, int64_t nzmax, unsigned flags,
+                                       int32_t *jcS, int64_t jcS_cap,
+                                       int32_t *irS, void *prS, int64_t cap,
+                                       int32_t *slot, void *ws, size_t ws_bytes,
+                                       fsparse_plan **plan, fsparse_info *info,
+                                       hipStream_t stream);
+
+/*
  * Pattern re-use: the values prS[0..nnz) of the matrix the plan was made
  * for, from new values ss[0..len) on the same (ii, jj) -- the repeated
  * assembly of Section 2.1 ("saving various types of information between

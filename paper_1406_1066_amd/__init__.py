@@ -10,6 +10,6 @@ from ._lib import LIB_PATH  # noqa: F401  (raises if the library is not built)
 from .api import (  # noqa: F401
     Assembled, Assembler, Batched, FsparseError, FsparseIndexError,
     SparseAssemble, assemble, assemble_batched, backward, dims, get_tuning,
-    reassemble, set_tuning, sparse, stream_copy, timing, to_torch_csc,
-    version, workspace_bytes,
+    reassemble, set_tuning, sparse, sparse_expand, stream_copy, timing,
+    to_torch_csc, version, workspace_bytes,
 )

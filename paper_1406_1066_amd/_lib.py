@@ -22,6 +22,12 @@ class FsparseInfo(ctypes.Structure):
                 ("nnz", ctypes.c_int64), ("nzmax", ctypes.c_int64)]
 
 
+class FsparseExpand(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int64 * 3), ("ii_shape", ctypes.c_int64 * 3),
+                ("jj_shape", ctypes.c_int64 * 3),
+                ("ss_shape", ctypes.c_int64 * 3)]
+
+
 class FsparseTuning(ctypes.Structure):
     _fields_ = [("chunk_cap", ctypes.c_int32), ("stream_block", ctypes.c_int32),
                 ("stream_items", ctypes.c_int32),
@@ -63,6 +69,11 @@ fsparse_assemble = _sig(
     [_vp, _vp, _vp, _st, _i64, _i64, _i64, _i64, _u, _vp, _i64, _vp, _vp,
      _i64, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp),
      ctypes.POINTER(FsparseInfo), _vp])
+fsparse_assemble_expand = _sig(
+    "fsparse_assemble_expand", _st,
+    [_vp, _vp, _vp, _st, ctypes.POINTER(FsparseExpand), _i64, _i64, _i64, _u,
+     _vp, _i64, _vp, _vp, _i64, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp),
+     ctypes.POINTER(FsparseInfo), _vp])
 fsparse_assemble_reuse = _sig("fsparse_assemble_reuse", _st,
                               [_vp, _vp, _vp, _u, _vp])
 fsparse_backward = _sig("fsparse_backward", _st,
@@ -96,7 +107,8 @@ fsparse_stream_copy = _sig("fsparse_stream_copy", _st,
 
 EXPORTS = [
     "fsparse_version", "fsparse_status_string", "fsparse_workspace_bytes",
-    "fsparse_dims", "fsparse_assemble", "fsparse_assemble_reuse",
+    "fsparse_dims", "fsparse_assemble", "fsparse_assemble_expand",
+    "fsparse_assemble_reuse",
     "fsparse_backward", "fsparse_assemble_batched", "fsparse_dims_batched",
     "fsparse_plan_destroy",
     "fsparse_plan_query", "fsparse_set_tuning", "fsparse_get_tuning",

@@ -172,12 +172,23 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
     Ln = ss.numel()
     if ii.numel() != Ln or jj.numel() != Ln:
         raise ValueError("ii, jj and ss must have the same length")
-    dt = _dt(ss.dtype)
     if m is None or n is None:
         dm, dn = dims(ii, jj)
         m = dm if m is None else m
         n = dn if n is None else n
-    m, n = int(m), int(n)
+
+    def call(*a):
+        return L.fsparse_assemble(_ptr(ii), _ptr(jj), _ptr(ss), _dt(ss.dtype),
+                                  Ln, *a)
+    return _fresh(call, Ln, int(m), int(n), ss, dev, nzmax, atomic, keep_slot,
+                  plan, cap, ws, out, "fsparse_assemble")
+
+
+def _fresh(call, Ln, m, n, ss, dev, nzmax, atomic, keep_slot, plan, cap, ws,
+           out, name) -> Assembled:
+    """Output buffers and the capacity / workspace retry around one fresh
+    assembly call ``call(m, n, nzmax, flags, jcS, jcS_cap, irS, prS, cap,
+    slot, ws, ws_bytes, plan_out, info, stream)``."""
     if ws is None:
         ws = _workspace(workspace_bytes(Ln, n, 1, ss.dtype), dev)
     slot = None
@@ -201,9 +212,8 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
             prS = torch.empty(max(cap, 1), dtype=ss.dtype, device=dev)
         info = L.FsparseInfo()
         ph = ctypes.c_void_p()
-        st = L.fsparse_assemble(
-            _ptr(ii), _ptr(jj), _ptr(ss), dt, Ln, m, n,
-            int(nzmax) if nzmax is not None else 0,
+        st = call(
+            m, n, int(nzmax) if nzmax is not None else 0,
             L.ATOMIC if atomic else L.ORDERED, _ptr(jcS), jcS.numel(),
             _ptr(irS), _ptr(prS), cap, _ptr(slot), _ptr(ws), ws.numel(),
             ctypes.byref(ph) if plan else None, ctypes.byref(info), _stream())
@@ -215,7 +225,7 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
             if ws.numel() < need:     # a given workspace that is too small
                 ws = _workspace(need, dev)
                 continue
-        _check(st, "fsparse_assemble")
+        _check(st, name)
         break
     nnz = int(info.nnz)
     p = None
@@ -226,6 +236,59 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
 
 
 assemble = sparse
+
+
+def sparse_expand(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
+                  n: Optional[int] = None, nzmax: Optional[int] = None, *,
+                  atomic: bool = False, keep_slot: bool = False,
+                  plan: bool = False, cap: Optional[int] = None,
+                  ws: Optional[torch.Tensor] = None,
+                  out: Optional[tuple] = None) -> Assembled:
+    """Assembly with index expansion: ``ii``, ``jj``, ``ss`` broadcast.
+
+    The three arrays (at most 3-D) broadcast to one grid of shape
+    (P, C, R) by the usual right-aligned rules; the triplets are the grid's
+    elements in row-major order (triplet k = r + R*(c + C*p)), each taking
+    the broadcast ii, jj and ss there.  No expanded index array is formed.
+    For finite elements with connectivity ``conn`` (elements x nv) and
+    element matrices ``K`` (elements x nv x nv, K[e, a, b] for row node
+    conn[e, a] and column node conn[e, b]):
+    ``sparse_expand(conn[:, :, None], conn[:, None, :], K)``.
+    Slots, plans and re-assembly count all P*C*R triplets.  Other arguments
+    as for ``sparse``.
+    """
+    dev = _device(ss, ii, jj)
+    ss = ss.contiguous()
+    ii = _dev_i32(ii, dev)
+    jj = _dev_i32(jj, dev)
+    if max(ii.dim(), jj.dim(), ss.dim()) > 3:
+        raise ValueError("operands of at most 3 dimensions")
+    grid = torch.broadcast_shapes(ii.shape, jj.shape, ss.shape)
+    grid = (1,) * (3 - len(grid)) + tuple(grid)
+    x = L.FsparseExpand()
+    for d in range(3):
+        x.shape[d] = grid[2 - d]
+    for name, t in (("ii_shape", ii), ("jj_shape", jj), ("ss_shape", ss)):
+        s = (1,) * (3 - t.dim()) + tuple(t.shape)
+        dst = getattr(x, name)
+        for d in range(3):
+            dst[d] = s[2 - d]
+    Ln = grid[0] * grid[1] * grid[2]
+    if m is None or n is None:
+        if Ln == 0:
+            dm = dn = 0
+        else:
+            # every operand entry is used: its largest index is the default
+            dm = dims(ii.reshape(-1), ii.reshape(-1))[0]
+            dn = dims(jj.reshape(-1), jj.reshape(-1))[1]
+        m = dm if m is None else m
+        n = dn if n is None else n
+
+    def call(*a):
+        return L.fsparse_assemble_expand(_ptr(ii), _ptr(jj), _ptr(ss),
+                                         _dt(ss.dtype), ctypes.byref(x), *a)
+    return _fresh(call, Ln, int(m), int(n), ss, dev, nzmax, atomic, keep_slot,
+                  plan, cap, ws, out, "fsparse_assemble_expand")
 
 
 def reassemble(res: Assembled, ss: torch.Tensor,

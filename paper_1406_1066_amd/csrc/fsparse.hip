@@ -222,14 +222,8 @@ struct Geom {
 
 // Bin width for an average fill of `fill` percent of the capacity, and the
 // multiply-shift that divides by it.
-void set_width(Geom& g, int64_t L, int64_t N, int cap, int fill) {
-  int64_t w = 1;
-  if (L > 0) {
-    const double target =
-        std::max(1.0, (double)cap * fill / 100.0) * (double)N / (double)L;
-    w = (int64_t)std::min<double>(target, (double)cap);
-    w = std::max<int64_t>(1, w);
-  }
+// x / w for x < 2^31 as a multiply-high and a shift (the device's bin_of)
+void set_divisor(Geom& g, int64_t w) {
   g.w = w;
   g.s = 0;
   while ((int64_t(1) << g.s) < w) ++g.s;
@@ -240,6 +234,17 @@ void set_width(Geom& g, int64_t L, int64_t N, int cap, int fill) {
     g.sh = 31 + g.s;
     g.mul = (uint32_t)(((uint64_t(1) << g.sh) + (uint64_t)w - 1) / (uint64_t)w);
   }
+}
+
+void set_width(Geom& g, int64_t L, int64_t N, int cap, int fill) {
+  int64_t w = 1;
+  if (L > 0) {
+    const double target =
+        std::max(1.0, (double)cap * fill / 100.0) * (double)N / (double)L;
+    w = (int64_t)std::min<double>(target, (double)cap);
+    w = std::max<int64_t>(1, w);
+  }
+  set_divisor(g, w);
   g.B = std::max<int64_t>(1, (N + w - 1) / w);
 }
 
@@ -480,13 +485,15 @@ hipError_t launch_atomic_values(const int32_t* slot, const void* ss, int64_t L,
 }
 
 // The shared pipeline of fresh and batched assembly.
-template <typename VT, bool BATCHED>
+// With EXP, triplet e reads ii, jj and ss through the expansion map `ex`.
+template <typename VT, bool BATCHED, bool EXP = false>
 hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
                         int64_t L, int32_t m, int32_t n, BatchDesc bd,
                         int64_t N, const Layout& lo, const Tuning& tu,
                         void* ws, int32_t* jcS_target, int32_t* irS, VT* prS,
                         int64_t cap, int32_t* slot, bool keep_plan,
-                        int mode, hipStream_t stream, Ctrl* hostctrl = nullptr) {
+                        int mode, hipStream_t stream, Ctrl* hostctrl = nullptr,
+                        fsp::Expand ex = fsp::Expand{}) {
   const Geom& g = lo.g;
   Ctrl* ctrl = at<Ctrl>(ws, lo.ctrl);
   hipError_t e;
@@ -518,15 +525,15 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   // 1. bin counts (the slot mode has none)
   if (mode != kSlot) e = launch(kHist, stream, [&] {
     if (mode == kDense)
-      hipLaunchKernelGGL(fsp::k_count_dense<BATCHED>, dim3((unsigned)(8 * ((g.T + 7) / 8))), dim3(blk),
+      hipLaunchKernelGGL((fsp::k_count_dense<BATCHED, EXP>), dim3((unsigned)(8 * ((g.T + 7) / 8))), dim3(blk),
                          (size_t)B * 4, stream, jj, L, n, bd, G, B, (int32_t)g.TS,
                          cntmat, at<uint32_t>(ws, 0), zwords,
-                         at<uint32_t>(ws, lo.tilebad));
+                         at<uint32_t>(ws, lo.tilebad), ex);
     else
-      hipLaunchKernelGGL((fsp::k_count_claim<BATCHED, kClaimNT, kClaimIPT>),
+      hipLaunchKernelGGL((fsp::k_count_claim<BATCHED, EXP, kClaimNT, kClaimIPT>),
                          dim3((unsigned)g.T), dim3(kClaimNT),
                          (size_t)kClaimWindow * 4, stream, jj, L, n, bd, G,
-                         kClaimWindow, bincnt, ctrl);
+                         kClaimWindow, bincnt, ctrl, ex);
   });
   if (e != hipSuccess) return e;
   // 2. bin pointers (dense mode: with the column scan of the count matrix)
@@ -552,29 +559,29 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   e = launch(kBucket, stream, [&] {
     if (mode == kDense) {
       if (packed)
-        hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED, true>), dim3((unsigned)(8 * ((g.T + 7) / 8))),
+        hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED, true, EXP>), dim3((unsigned)(8 * ((g.T + 7) / 8))),
                            dim3(blk), (size_t)B * 4, stream, ii, jj, ss, L, m, n, bd,
                            G, B, (int32_t)g.TS, cntmat, binstart, bucket, bcol,
-                           (uint32_t)std::max<int64_t>(L, g.nslot), ctrl);
+                           (uint32_t)std::max<int64_t>(L, g.nslot), ctrl, ex);
       else
-        hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED, false>), dim3((unsigned)(8 * ((g.T + 7) / 8))),
+        hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED, false, EXP>), dim3((unsigned)(8 * ((g.T + 7) / 8))),
                            dim3(blk), (size_t)B * 4, stream, ii, jj, ss, L, m, n, bd,
                            G, B, (int32_t)g.TS, cntmat, binstart, bucket, bcol,
-                           (uint32_t)std::max<int64_t>(L, g.nslot), ctrl);
+                           (uint32_t)std::max<int64_t>(L, g.nslot), ctrl, ex);
     } else {
       const uint32_t trash = (uint32_t)std::max<int64_t>(L, g.nslot);
       if (packed)
-        hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, true, kClaimNT, kClaimIPT>),
+        hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, true, EXP, kClaimNT, kClaimIPT>),
                            dim3((unsigned)g.T), dim3(kClaimNT),
                            (size_t)kClaimWindow * 4, stream, ii, jj, ss, L, m, n, bd,
                            G, kClaimWindow, binstart, slotcap, binfill, bucket, bcol,
-                           trash, ctrl);
+                           trash, ctrl, ex);
       else
-        hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, false, kClaimNT, kClaimIPT>),
+        hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, false, EXP, kClaimNT, kClaimIPT>),
                            dim3((unsigned)g.T), dim3(kClaimNT),
                            (size_t)kClaimWindow * 4, stream, ii, jj, ss, L, m, n, bd,
                            G, kClaimWindow, binstart, slotcap, binfill, bucket, bcol,
-                           trash, ctrl);
+                           trash, ctrl, ex);
     }
   });
   if (e != hipSuccess) return e;
@@ -770,27 +777,16 @@ fsparse_status fsparse_dims(const int32_t* ii, const int32_t* jj, int64_t len,
   return FSPARSE_OK;
 }
 
-fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
-                                const void* ss, fsparse_dtype dt, int64_t len,
-                                int64_t m, int64_t n, int64_t nzmax,
-                                unsigned flags, int32_t* jcS, int64_t jcS_cap,
-                                int32_t* irS, void* prS, int64_t cap,
-                                int32_t* slot, void* ws, size_t ws_bytes,
-                                fsparse_plan** plan, fsparse_info* info,
-                                hipStream_t stream) {
-  if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
-  if (len < 0 || len > kMaxI32 || m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
-  if (flags & ~(unsigned)FSPARSE_ATOMIC) return FSPARSE_E_ARG;
-  if (len > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
-  if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS))) return FSPARSE_E_ARG;
-  if (plan) *plan = nullptr;
-  if (m < 0 || n < 0) {
-    int64_t dm = 0, dn = 0;
-    fsparse_status st = fsparse_dims(ii, jj, len, &dm, &dn, ws, ws_bytes, stream);
-    if (st != FSPARSE_OK) return st;
-    if (m < 0) m = dm;
-    if (n < 0) n = dn;
-  }
+// Fresh assembly once the dimensions are known; with `ex`, triplet e reads
+// ii, jj and ss through the expansion map.
+static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
+                             const void* ss, fsparse_dtype dt, int64_t len,
+                             int64_t m, int64_t n, int64_t nzmax,
+                             unsigned flags, int32_t* jcS, int64_t jcS_cap,
+                             int32_t* irS, void* prS, int64_t cap,
+                             int32_t* slot, void* ws, size_t ws_bytes,
+                             fsparse_plan** plan, fsparse_info* info,
+                             hipStream_t stream, const fsp::Expand* ex) {
   if (info) {
     info->m = m;
     info->n = n;
@@ -818,11 +814,21 @@ fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
     int mode = lo.g.mode;
     for (;;) {
       hipError_t e;
-      if (dt == FSPARSE_F64)
+      if (dt == FSPARSE_F64 && ex)
+        e = run_pipeline<double, false, true>(ii, jj, (const double*)ss, len, (int32_t)m,
+                                              (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
+                                              (double*)prS, cap, slot_used, keep, mode,
+                                              stream, h, *ex);
+      else if (dt == FSPARSE_F64)
         e = run_pipeline<double, false>(ii, jj, (const double*)ss, len, (int32_t)m,
                                         (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
                                         (double*)prS, cap, slot_used, keep, mode,
                                         stream, h);
+      else if (ex)
+        e = run_pipeline<float, false, true>(ii, jj, (const float*)ss, len, (int32_t)m,
+                                             (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
+                                             (float*)prS, cap, slot_used, keep, mode,
+                                             stream, h, *ex);
       else
         e = run_pipeline<float, false>(ii, jj, (const float*)ss, len, (int32_t)m,
                                        (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
@@ -883,6 +889,104 @@ fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
     *plan = pl;
   }
   return FSPARSE_OK;
+}
+
+fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
+                                const void* ss, fsparse_dtype dt, int64_t len,
+                                int64_t m, int64_t n, int64_t nzmax,
+                                unsigned flags, int32_t* jcS, int64_t jcS_cap,
+                                int32_t* irS, void* prS, int64_t cap,
+                                int32_t* slot, void* ws, size_t ws_bytes,
+                                fsparse_plan** plan, fsparse_info* info,
+                                hipStream_t stream) {
+  if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
+  if (len < 0 || len > kMaxI32 || m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
+  if (flags & ~(unsigned)FSPARSE_ATOMIC) return FSPARSE_E_ARG;
+  if (len > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
+  if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS))) return FSPARSE_E_ARG;
+  if (plan) *plan = nullptr;
+  if (m < 0 || n < 0) {
+    int64_t dm = 0, dn = 0;
+    fsparse_status st = fsparse_dims(ii, jj, len, &dm, &dn, ws, ws_bytes, stream);
+    if (st != FSPARSE_OK) return st;
+    if (m < 0) m = dm;
+    if (n < 0) n = dn;
+  }
+  return assemble_impl(ii, jj, ss, dt, len, m, n, nzmax, flags, jcS, jcS_cap, irS,
+                       prS, cap, slot, ws, ws_bytes, plan, info, stream, nullptr);
+}
+
+// Exact division by d on [0, 2^31) in the bins' multiply-high form.
+static fsp::BinGeo divisor(int64_t d) {
+  Geom g{};
+  set_divisor(g, d);
+  return fsp::BinGeo{g.mul, g.sh, (int32_t)g.w, g.s};
+}
+
+fsparse_status fsparse_assemble_expand(const int32_t* ii, const int32_t* jj,
+                                       const void* ss, fsparse_dtype dt,
+                                       const fsparse_expand* x, int64_t m,
+                                       int64_t n, int64_t nzmax, unsigned flags,
+                                       int32_t* jcS, int64_t jcS_cap, int32_t* irS,
+                                       void* prS, int64_t cap, int32_t* slot,
+                                       void* ws, size_t ws_bytes,
+                                       fsparse_plan** plan, fsparse_info* info,
+                                       hipStream_t stream) {
+  if (check_dt(dt) != FSPARSE_OK || !x) return FSPARSE_E_ARG;
+  if (m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
+  if (flags & ~(unsigned)FSPARSE_ATOMIC) return FSPARSE_E_ARG;
+  int64_t len = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (x->shape[d] < 0 || x->shape[d] > kMaxI32) return FSPARSE_E_ARG;
+    len *= x->shape[d];
+    if (len > kMaxI32) return FSPARSE_E_ARG;
+  }
+  // every operand dimension is 1 or the grid's; strides of a dense array
+  const int64_t* shp[3] = {x->ii_shape, x->jj_shape, x->ss_shape};
+  int64_t size[3];
+  uint32_t stride[3][3];
+  bool full_ss = true;
+  for (int a = 0; a < 3; ++a) {
+    int64_t st = 1;
+    for (int d = 0; d < 3; ++d) {
+      const int64_t k = shp[a][d];
+      if (k != 1 && k != x->shape[d]) return FSPARSE_E_ARG;
+      stride[a][d] = (k == 1) ? 0u : (uint32_t)st;
+      st *= k;
+      if (a == 2 && k != x->shape[d]) full_ss = false;
+    }
+    size[a] = st;
+  }
+  // the order-free sum reads ss by triplet number
+  if ((flags & FSPARSE_ATOMIC) && !full_ss) return FSPARSE_E_ARG;
+  if (len > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
+  if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS))) return FSPARSE_E_ARG;
+  if (plan) *plan = nullptr;
+  if (m < 0 || n < 0) {
+    // with at least one triplet every operand element is used, so the
+    // largest index of an operand is the largest over the triplets
+    int64_t dm = 0, dn = 0, dummy = 0;
+    if (len > 0) {
+      fsparse_status st = fsparse_dims(ii, ii, size[0], &dm, &dummy, ws, ws_bytes, stream);
+      if (st != FSPARSE_OK) return st;
+      st = fsparse_dims(jj, jj, size[1], &dummy, &dn, ws, ws_bytes, stream);
+      if (st != FSPARSE_OK) return st;
+    }
+    if (m < 0) m = dm;
+    if (n < 0) n = dn;
+  }
+  fsp::Expand ex{};
+  ex.dR = divisor(std::max<int64_t>(1, x->shape[0]));
+  ex.dC = divisor(std::max<int64_t>(1, x->shape[1]));
+  ex.R = (uint32_t)x->shape[0];
+  ex.C = (uint32_t)x->shape[1];
+  for (int d = 0; d < 3; ++d) {
+    ex.si[d] = stride[0][d];
+    ex.sj[d] = stride[1][d];
+    ex.sv[d] = stride[2][d];
+  }
+  return assemble_impl(ii, jj, ss, dt, len, m, n, nzmax, flags, jcS, jcS_cap, irS,
+                       prS, cap, slot, ws, ws_bytes, plan, info, stream, &ex);
 }
 
 fsparse_status fsparse_assemble_reuse(fsparse_plan* plan, const void* ss,

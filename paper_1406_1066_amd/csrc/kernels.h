@@ -472,6 +472,35 @@ __device__ __forceinline__ uint32_t bin_col(const BinGeo& G, int64_t g, uint32_t
   return (uint32_t)g - q * (uint32_t)G.w;
 }
 
+// Expanded input (the index-expansion extension of the input syntax,
+// Section 2.1): the triplets form an R x C x P grid, triplet
+// e = r + R * (c + C * p), and each of ii, jj, ss is a dense array over the
+// same grid in which any dimension may be 1, read with stride 0 along it.
+// The two quotients e / R and (e / R) / C use the bins' exact
+// multiply-high division (e < 2^31).
+struct Expand {
+  BinGeo dR, dC;
+  uint32_t R, C;
+  uint32_t si[3], sj[3], sv[3];  // element strides of ii, jj, ss along r, c, p
+};
+
+struct ExpPos {
+  uint32_t r, c, p;
+};
+
+__device__ __forceinline__ ExpPos exp_pos(const Expand& x, int64_t e) {
+  ExpPos o;
+  const uint32_t q = bin_of(x.dR, e);
+  o.r = (uint32_t)e - q * x.R;
+  o.p = bin_of(x.dC, q);
+  o.c = q - o.p * x.C;
+  return o;
+}
+
+__device__ __forceinline__ uint32_t exp_at(const uint32_t (&s)[3], const ExpPos& o) {
+  return o.r * s[0] + o.c * s[1] + o.p * s[2];
+}
+
 // The matrix of the triplets a thread visits, in increasing order: its index,
 // triplet end, column offset and dimensions, kept in registers.
 struct MatCur {
@@ -584,12 +613,12 @@ constexpr int kScatterU = 4;
 // look-back words (zero[0..zwords)), which no later kernel of the call uses
 // before it is done; so it reports a bad column not in the control block
 // but in its own word tilebad[tile], which the column scan reads.
-template <bool BATCHED>
+template <bool BATCHED, bool EXP>
 __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
                               int32_t n, BatchDesc bd, BinGeo G, int32_t B,
                               int32_t TS, uint32_t* __restrict__ cnt,
                               uint32_t* __restrict__ zero, int64_t zwords,
-                              uint32_t* __restrict__ tilebad) {
+                              uint32_t* __restrict__ tilebad, Expand ex) {
   extern __shared__ uint32_t hist[];
   __shared__ int sB;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < zwords;
@@ -610,7 +639,13 @@ __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
   for (int64_t eb = t0 + threadIdx.x; eb < t1; eb += kDenseU * nt) {
     int32_t cj[kDenseU];
 #pragma unroll
-    for (int u = 0; u < kDenseU; ++u) cj[u] = jj[min(eb + u * nt, t1 - 1)];  // no branch
+    for (int u = 0; u < kDenseU; ++u) {
+      const int64_t e = min(eb + u * nt, t1 - 1);  // no branch
+      if constexpr (EXP)
+        cj[u] = jj[exp_at(ex.sj, exp_pos(ex, e))];
+      else
+        cj[u] = jj[e];
+    }
 #pragma unroll
     for (int u = 0; u < kDenseU; ++u) {
       const int64_t e = eb + u * nt;
@@ -711,7 +746,7 @@ k_colscan_bins(uint32_t* __restrict__ cnt, int32_t T, int32_t B,
 
 // dense mode, pass 3: scatter (row, k, value) and the in-bin column into
 // the bins; the position inside the bin is an LDS atomic rank
-template <typename VT, bool BATCHED, bool PACKED>
+template <typename VT, bool BATCHED, bool PACKED, bool EXP>
 __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
                                 const int32_t* __restrict__ jj,
                                 const VT* __restrict__ ss, int64_t L, int32_t m,
@@ -720,7 +755,7 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
                                 const int32_t* __restrict__ binstart,
                                 Entry<VT>* __restrict__ bucket,
                                 uint32_t* __restrict__ bcol, uint32_t trash,
-                                Ctrl* ctrl) {
+                                Ctrl* ctrl, Expand ex) {
   extern __shared__ uint32_t ctr[];
   __shared__ int sB;
   const int64_t tile = xcd_tile(L, TS);
@@ -752,10 +787,17 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
     for (int u = 0; u < kDenseSU; ++u) {
       const int64_t e = eb + u * nt;
       if (e < t1) {
-        const uint32_t x = (uint32_t)(e - t0);
-        cj[u] = ld_off32(jt, x);
-        ri[u] = ld_off32(it, x);
-        sv[u] = ld_off32(st, x);
+        if constexpr (EXP) {
+          const ExpPos o = exp_pos(ex, e);
+          cj[u] = jj[exp_at(ex.sj, o)];
+          ri[u] = ii[exp_at(ex.si, o)];
+          sv[u] = ss[exp_at(ex.sv, o)];
+        } else {
+          const uint32_t x = (uint32_t)(e - t0);
+          cj[u] = ld_off32(jt, x);
+          ri[u] = ld_off32(it, x);
+          sv[u] = ld_off32(st, x);
+        }
       }
     }
     uint32_t pos[kDenseSU], key[kDenseSU], bc[kDenseSU];
@@ -787,12 +829,13 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
 }
 
 // claim mode: tiles of NT*IPT triplets; bins of the tile live in registers
-template <bool BATCHED, int NT, int IPT>
+template <bool BATCHED, bool EXP, int NT, int IPT>
 __device__ __forceinline__ void tile_bins(const int32_t* __restrict__ jj,
                                           int64_t L, int32_t n, const BatchDesc& bd,
                                           const BinGeo& G, int64_t t0, int* sB,
                                           int32_t (&bn)[IPT], int32_t (&cj)[IPT],
-                                          int32_t& lo, int32_t& hi, bool& bad) {
+                                          int32_t& lo, int32_t& hi, bool& bad,
+                                          const Expand& ex) {
   MatCur b;
   mat_cur<BATCHED>(bd, b, tile_first_mat<BATCHED>(bd, t0, L, sB));
   lo = INT32_MAX;
@@ -800,8 +843,13 @@ __device__ __forceinline__ void tile_bins(const int32_t* __restrict__ jj,
   int32_t mb;
   // all column loads in flight at once (clamped index: no branch)
 #pragma unroll
-  for (int j = 0; j < IPT; ++j)
-    cj[j] = jj[min(t0 + (int64_t)j * NT + threadIdx.x, L - 1)];
+  for (int j = 0; j < IPT; ++j) {
+    const int64_t e = min(t0 + (int64_t)j * NT + threadIdx.x, L - 1);
+    if constexpr (EXP)
+      cj[j] = jj[exp_at(ex.sj, exp_pos(ex, e))];
+    else
+      cj[j] = jj[e];
+  }
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const int64_t e = t0 + (int64_t)j * NT + threadIdx.x;
@@ -841,18 +889,18 @@ __device__ __forceinline__ void block_minmax(int32_t& lo, int32_t& hi,
   hi = *sHi;
 }
 
-template <bool BATCHED, int NT, int IPT>
+template <bool BATCHED, bool EXP, int NT, int IPT>
 __global__ void __launch_bounds__(NT)
 k_count_claim(const int32_t* __restrict__ jj, int64_t L, int32_t n,
               BatchDesc bd, BinGeo G, int32_t WMAX,
-              uint32_t* __restrict__ bincnt, Ctrl* ctrl) {
+              uint32_t* __restrict__ bincnt, Ctrl* ctrl, Expand ex) {
   extern __shared__ uint32_t hist[];
   __shared__ int sB;
   __shared__ int32_t sLo, sHi;
   const int64_t t0 = (int64_t)blockIdx.x * NT * IPT;
   int32_t bn[IPT], cj[IPT], lo, hi;
   bool bad = false;
-  tile_bins<BATCHED, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, cj, lo, hi, bad);
+  tile_bins<BATCHED, EXP, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, cj, lo, hi, bad, ex);
   block_minmax<NT>(lo, hi, &sLo, &sHi);
   if (bad) atomicOr(&ctrl->err, kErrCol);
   if (hi < lo) return;
@@ -873,21 +921,22 @@ k_count_claim(const int32_t* __restrict__ jj, int64_t L, int32_t n,
   }
 }
 
-template <typename VT, bool BATCHED, bool PACKED, int NT, int IPT>
+template <typename VT, bool BATCHED, bool PACKED, bool EXP, int NT, int IPT>
 __global__ void __launch_bounds__(NT)
 k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
                 const VT* __restrict__ ss, int64_t L, int32_t m, int32_t n,
                 BatchDesc bd, BinGeo G, int32_t WMAX,
                 const int32_t* __restrict__ binstart, int32_t slotcap,
                 uint32_t* __restrict__ binfill, Entry<VT>* __restrict__ bucket,
-                uint32_t* __restrict__ bcol, uint32_t trash, Ctrl* ctrl) {
+                uint32_t* __restrict__ bcol, uint32_t trash, Ctrl* ctrl,
+                Expand ex) {
   extern __shared__ uint32_t hist[];
   __shared__ int sB;
   __shared__ int32_t sLo, sHi;
   const int64_t t0 = (int64_t)blockIdx.x * NT * IPT;
   int32_t bn[IPT], cj[IPT], lo, hi;
   bool bad = false;
-  tile_bins<BATCHED, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, cj, lo, hi, bad);
+  tile_bins<BATCHED, EXP, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, cj, lo, hi, bad, ex);
   block_minmax<NT>(lo, hi, &sLo, &sHi);
   if (hi < lo) return;
   const int width = hi - lo + 1;
@@ -923,8 +972,14 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
 #pragma unroll
     for (int u = 0; u < kScatterU; ++u) {
       const int64_t e = min(t0 + (int64_t)(j0 + u) * NT + threadIdx.x, L - 1);
-      ri[u] = ii[e];
-      sv[u] = ss[e];
+      if constexpr (EXP) {
+        const ExpPos o = exp_pos(ex, e);
+        ri[u] = ii[exp_at(ex.si, o)];
+        sv[u] = ss[exp_at(ex.sv, o)];
+      } else {
+        ri[u] = ii[e];
+        sv[u] = ss[e];
+      }
     }
     uint32_t pos[kScatterU], key[kScatterU], bc[kScatterU];
 #pragma unroll
