@@ -235,6 +235,8 @@ def main():
     }
     if not args.no_modes:
         line["modes"] = modes(args, fs, torch, ii, jj, ss, m, n, L, vb, eb)
+        if "conn" in t.meta:
+            line["modes"]["expand"] = expanded(args, fs, torch, t, ss, vb, eb)
         line["copy_gbps"] = copy_bw(fs, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(t, args.cpu_seconds)
@@ -280,6 +282,41 @@ def modes(args, fs, torch, ii, jj, ss, m, n, L, vb, eb):
         d[name] = rec
         log(name, "%.4f ms" % ms)
     return d
+
+
+def expanded(args, fs, torch, t, ss, vb, eb):
+    """Fresh assembly from the element connectivity and element matrices
+    (index expansion), with the launch shapes of the plain call."""
+    conn = torch.from_numpy(t.meta["conn"]).to(ss.device)
+    ne, nv = conn.shape
+    ci, cj = conn[:, :, None], conn[:, None, :]
+    K = ss.view(ne, nv, nv)
+    L, n = ss.numel(), t.n
+    ws = torch.empty(fs.workspace_bytes(L, n, 1, ss.dtype), dtype=torch.uint8,
+                     device=ss.device)
+    out = (torch.empty(n + 1, dtype=torch.int32, device=ss.device),
+           torch.empty(L, dtype=torch.int32, device=ss.device),
+           torch.empty(L, dtype=ss.dtype, device=ss.device))
+
+    def fn():
+        return fs.sparse_expand(ci, cj, K, t.m, n, ws=ws, out=out)
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    stages, _ = stage_profile(fs, torch, fn, args.steps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    log("expand", "%.4f ms" % ms)
+    # the index bytes of the whole path: the connectivity once
+    ib = 4 * ne * nv
+    return {"value": L / (ms * 1e-3) / 1e9, "unit": "Gtriplets/s", "ms": ms,
+            "index_bytes": ib, "stages_ms": stages}
 
 
 def copy_bw(fs, torch):

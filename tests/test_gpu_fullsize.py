@@ -184,3 +184,19 @@ def test_fem3d_50_full_and_backward(fs, dtype):
         fd = (lp - lm) / (hp + hm)
         worst = max(worst, abs(fd - float(g[k])) / max(1.0, abs(float(g[k]))))
     assert worst <= tol, worst
+
+
+def test_fem3d_100_expanded(fs):
+    # index expansion at full size: connectivity and element matrices only
+    # (the 93M-triplet index arrays are never formed); sampled columns
+    # against the oracle, the whole output through the invariants
+    t = W.config("fem3d_100")
+    conn = t.meta["conn"]
+    ne, nv = conn.shape
+    c = to_dev(conn)
+    K = to_dev(t.ss).view(ne, nv, nv)
+    res = fs.sparse_expand(c[:, :, None], c[:, None, :], K, t.m, t.n,
+                           keep_slot=True)
+    assert res.nnz == W.fem3d_counts(100)[1]
+    check_invariants(res, to_dev(t.ii), to_dev(t.jj), t.m, t.n)
+    check_sampled(res, t, sample_cols(t.n, 200, 21))
