@@ -174,6 +174,24 @@ def assemble_columns(ii, jj, ss, m: int, n: int, cols: Sequence[int],
     return out, kidx, gslot
 
 
+def indices_from_double(v) -> np.ndarray:
+    """Unit-offset indices held in doubles, checked and converted.
+
+    The pre-processing of Section 2.2 (and its appendix listings) rejects a
+    value below 1 or one that differs from its ceiling, then converts; NaN
+    fails the second test.  Values beyond int32, which the conversion cannot
+    hold, are rejected as well (the reading taken for them and for
+    infinities).  Raises OracleIndexError.
+    """
+    v = np.asarray(v, dtype=np.float64)
+    with np.errstate(invalid="ignore"):
+        bad = (v < 1.0) | (v != np.ceil(v)) | (v > 2147483647.0)
+    if bad.any():
+        raise OracleIndexError("index %r at %d is not a whole number >= 1"
+                               % (float(v[bad][0]), int(np.argmax(bad))))
+    return v.astype(np.int32)
+
+
 def expand(ii, jj, ss):
     """The triplets of an index-expanded input, written out.
 

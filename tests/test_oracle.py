@@ -407,3 +407,36 @@ def test_expand_shape_errors():
     with pytest.raises(ValueError):
         oracle.expand(np.ones((1, 1, 1, 2), np.int32), np.ones(2, np.int32),
                       np.ones(2))
+
+
+# ---------------------------------------------------------------------------
+# double-valued indices (the pre-processing check of Section 2.2)
+# ---------------------------------------------------------------------------
+def test_indices_from_double_accepts_whole_numbers():
+    v = [1.0, 2.0, 7.0, 2147483647.0, 3.0]
+    got = oracle.indices_from_double(v)
+    assert got.dtype == np.int32
+    assert got.tolist() == [1, 2, 7, 2147483647, 3]
+    # a float32 array holds the same whole numbers exactly
+    f = np.array([1, 5, 16777216], dtype=np.float32)
+    assert oracle.indices_from_double(f).tolist() == [1, 5, 16777216]
+
+
+@pytest.mark.parametrize("bad", [0.0, -0.0, -3.0, 0.999, 1.5, 2.0000000000000004,
+                                 float("nan"), float("inf"), float("-inf"),
+                                 2147483648.0, 1e300])
+def test_indices_from_double_rejects(bad):
+    with pytest.raises(oracle.OracleIndexError):
+        oracle.indices_from_double([1.0, 2.0, bad, 3.0])
+
+
+def test_double_indices_assemble_like_integers():
+    rng = np.random.default_rng(17)
+    ii = rng.integers(1, 50, 3000)
+    jj = rng.integers(1, 40, 3000)
+    ss = rng.standard_normal(3000)
+    a = oracle.assemble(oracle.indices_from_double(ii.astype(np.float64)),
+                        oracle.indices_from_double(jj.astype(np.float64)), ss)
+    b = oracle.assemble(ii.astype(np.int32), jj.astype(np.int32), ss)
+    assert np.array_equal(a.jcS, b.jcS) and np.array_equal(a.irS, b.irS)
+    assert a.prS.tobytes() == b.prS.tobytes()
