@@ -237,6 +237,8 @@ def main():
         line["modes"] = modes(args, fs, torch, ii, jj, ss, m, n, L, vb, eb)
         if "conn" in t.meta:
             line["modes"]["expand"] = expanded(args, fs, torch, t, ss, vb, eb)
+        line["modes"]["f64_index"] = double_indices(args, fs, torch, ii, jj,
+                                                    ss, m, n)
         line["copy_gbps"] = copy_bw(fs, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(t, args.cpu_seconds)
@@ -317,6 +319,37 @@ def expanded(args, fs, torch, t, ss, vb, eb):
     ib = 4 * ne * nv
     return {"value": L / (ms * 1e-3) / 1e9, "unit": "Gtriplets/s", "ms": ms,
             "index_bytes": ib, "stages_ms": stages}
+
+
+def double_indices(args, fs, torch, ii, jj, ss, m, n):
+    """Fresh assembly from double-valued index arrays (checked and
+    converted by the passes that read them), same launch shapes."""
+    di, dj = ii.to(torch.float64), jj.to(torch.float64)
+    L = ss.numel()
+    ws = torch.empty(fs.workspace_bytes(L, n, 1, ss.dtype), dtype=torch.uint8,
+                     device=ss.device)
+    out = (torch.empty(n + 1, dtype=torch.int32, device=ss.device),
+           torch.empty(L, dtype=torch.int32, device=ss.device),
+           torch.empty(L, dtype=ss.dtype, device=ss.device))
+
+    def fn():
+        return fs.sparse(di, dj, ss, m, n, ws=ws, out=out)
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    stages, _ = stage_profile(fs, torch, fn, args.steps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    log("f64_index", "%.4f ms" % ms)
+    del di, dj, ws, out
+    return {"value": L / (ms * 1e-3) / 1e9, "unit": "Gtriplets/s", "ms": ms,
+            "stages_ms": stages}
 
 
 def copy_bw(fs, torch):

@@ -131,6 +131,30 @@ fsparse_status fsparse_assemble(const int32_t *ii, const int32_t *jj,
                                 hipStream_t stream);
 
 /*
+ * Double-valued indices (Matlab's default array type; the pre-processing of
+ * Section 2.2 and its appendix listings, which check and convert them).
+ * The same as fsparse_assemble / fsparse_dims with ii and jj given as
+ * [len] doubles holding unit-offset indices.  An index must be a whole
+ * number in [1, 2^31 - 1] (and within [1,m] / [1,n] when those are given):
+ * a fraction, NaN, an infinity or a value below 1 gives FSPARSE_E_INDEX,
+ * like an index out of range.  The conversion happens as the passes read
+ * the indices; no int32 copy is made.
+ */
+fsparse_status fsparse_dims_f64idx(const double *ii, const double *jj,
+                                   int64_t len, int64_t *m /* host out */,
+                                   int64_t *n /* host out */, void *ws,
+                                   size_t ws_bytes, hipStream_t stream);
+fsparse_status fsparse_assemble_f64idx(const double *ii, const double *jj,
+                                       const void *ss, fsparse_dtype dt,
+                                       int64_t len, int64_t m, int64_t n,
+                                       int64_t nzmax, unsigned flags,
+                                       int32_t *jcS, int64_t jcS_cap,
+                                       int32_t *irS, void *prS, int64_t cap,
+                                       int32_t *slot, void *ws, size_t ws_bytes,
+                                       fsparse_plan **plan, fsparse_info *info,
+                                       hipStream_t stream);
+
+/*
  * Index expansion (Section 2.1 mentions an extension of the input syntax in
  * which row and column indices are used several times as the shapes of the
  * inputs dictate; the paper gives no detail, so this library defines it as

@@ -69,6 +69,14 @@ fsparse_assemble = _sig(
     [_vp, _vp, _vp, _st, _i64, _i64, _i64, _i64, _u, _vp, _i64, _vp, _vp,
      _i64, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp),
      ctypes.POINTER(FsparseInfo), _vp])
+fsparse_dims_f64idx = _sig("fsparse_dims_f64idx", _st,
+                           [_vp, _vp, _i64, ctypes.POINTER(_i64),
+                            ctypes.POINTER(_i64), _vp, ctypes.c_size_t, _vp])
+fsparse_assemble_f64idx = _sig(
+    "fsparse_assemble_f64idx", _st,
+    [_vp, _vp, _vp, _st, _i64, _i64, _i64, _i64, _u, _vp, _i64, _vp, _vp,
+     _i64, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp),
+     ctypes.POINTER(FsparseInfo), _vp])
 fsparse_assemble_expand = _sig(
     "fsparse_assemble_expand", _st,
     [_vp, _vp, _vp, _st, ctypes.POINTER(FsparseExpand), _i64, _i64, _i64, _u,
@@ -108,6 +116,7 @@ fsparse_stream_copy = _sig("fsparse_stream_copy", _st,
 EXPORTS = [
     "fsparse_version", "fsparse_status_string", "fsparse_workspace_bytes",
     "fsparse_dims", "fsparse_assemble", "fsparse_assemble_expand",
+    "fsparse_dims_f64idx", "fsparse_assemble_f64idx",
     "fsparse_assemble_reuse",
     "fsparse_backward", "fsparse_assemble_batched", "fsparse_dims_batched",
     "fsparse_plan_destroy",

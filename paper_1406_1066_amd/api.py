@@ -10,6 +10,7 @@ import ctypes
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -68,14 +69,39 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else None
 
 
+def _as_tensor(x) -> torch.Tensor:
+    return x if isinstance(x, torch.Tensor) else torch.as_tensor(np.asarray(x))
+
+
+def _is_float_index(x) -> bool:
+    return _as_tensor(x).dtype.is_floating_point
+
+
 def _dev_i32(x, device) -> torch.Tensor:
+    """Integer indices as contiguous int32 on the device.  A value that int32
+    cannot hold becomes 0, which the library rejects as an index below 1
+    (instead of wrapping into range)."""
     if (isinstance(x, torch.Tensor) and x.dtype == torch.int32 and
             x.device == device and x.is_contiguous()):
         return x
-    t = torch.as_tensor(x)
+    t = _as_tensor(x)
+    if t.dtype.is_floating_point or t.dtype.is_complex:
+        raise TypeError("integer index arrays expected here, got %s" % t.dtype)
+    t = t.to(device)
     if t.dtype != torch.int32:
+        if t.dtype in (torch.int64, torch.uint32, torch.uint64):
+            t = torch.where((t < 1) | (t > 2**31 - 1), torch.zeros_like(t), t)
         t = t.to(torch.int32)
-    return t.to(device).contiguous()
+    return t.contiguous()
+
+
+def _dev_f64(x, device) -> torch.Tensor:
+    """Floating-point indices as contiguous float64 on the device (exact
+    for float32 and float16)."""
+    t = _as_tensor(x).to(device)
+    if t.dtype != torch.float64:
+        t = t.to(torch.float64)
+    return t.contiguous()
 
 
 def _device(*ts):
@@ -96,14 +122,21 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def dims(ii: torch.Tensor, jj: torch.Tensor):
-    """Default (m, n): the largest row / column index (Section 2.2)."""
+    """Default (m, n): the largest row / column index (Section 2.2).
+    Floating-point index arrays are checked as the paper's pre-processing
+    does (whole numbers >= 1)."""
     dev = _device(ii, jj)
-    ii = _dev_i32(ii, dev)
-    jj = _dev_i32(jj, dev)
+    fn = L.fsparse_dims
+    if _is_float_index(ii) or _is_float_index(jj):
+        ii, jj, fn = _dev_f64(ii, dev), _dev_f64(jj, dev), L.fsparse_dims_f64idx
+    else:
+        ii, jj = _dev_i32(ii, dev), _dev_i32(jj, dev)
+    if ii.numel() != jj.numel():
+        raise ValueError("ii and jj must have the same length")
     ws = _workspace(256, dev)
     m, n = ctypes.c_int64(), ctypes.c_int64()
-    _check(L.fsparse_dims(_ptr(ii), _ptr(jj), ii.numel(), ctypes.byref(m),
-                          ctypes.byref(n), _ptr(ws), ws.numel(), _stream()),
+    _check(fn(_ptr(ii), _ptr(jj), ii.numel(), ctypes.byref(m),
+              ctypes.byref(n), _ptr(ws), ws.numel(), _stream()),
            "fsparse_dims")
     return int(m.value), int(n.value)
 
@@ -157,8 +190,10 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
            out: Optional[tuple] = None) -> Assembled:
     """S = sparse(ii, jj, ss, m, n, nzmax) on the GPU.
 
-    ``ii``/``jj`` unit-offset indices (any integer tensor, converted to
-    int32 on the device of ``ss``), ``ss`` float64/float32 on the GPU.
+    ``ii``/``jj`` unit-offset indices: integer arrays (converted to int32 on
+    the device of ``ss``) or floating-point arrays as Matlab passes them
+    (read as doubles by the kernels, which reject any index that is not a
+    whole number >= 1), ``ss`` float64/float32 on the GPU.
     ``m``/``n`` default to the largest index.  ``cap`` is the capacity of
     irS/prS (default len, always enough).  With ``plan=True`` the result
     carries a re-use plan (see ``reassemble``); ``keep_slot`` returns the
@@ -167,8 +202,12 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
     """
     dev = _device(ss, ii, jj)
     ss = ss.contiguous()
-    ii = _dev_i32(ii, dev)
-    jj = _dev_i32(jj, dev)
+    fn = L.fsparse_assemble
+    if _is_float_index(ii) or _is_float_index(jj):
+        ii, jj = _dev_f64(ii, dev), _dev_f64(jj, dev)
+        fn = L.fsparse_assemble_f64idx
+    else:
+        ii, jj = _dev_i32(ii, dev), _dev_i32(jj, dev)
     Ln = ss.numel()
     if ii.numel() != Ln or jj.numel() != Ln:
         raise ValueError("ii, jj and ss must have the same length")
@@ -178,8 +217,7 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
         n = dn if n is None else n
 
     def call(*a):
-        return L.fsparse_assemble(_ptr(ii), _ptr(jj), _ptr(ss), _dt(ss.dtype),
-                                  Ln, *a)
+        return fn(_ptr(ii), _ptr(jj), _ptr(ss), _dt(ss.dtype), Ln, *a)
     return _fresh(call, Ln, int(m), int(n), ss, dev, nzmax, atomic, keep_slot,
                   plan, cap, ws, out, "fsparse_assemble")
 

@@ -485,8 +485,9 @@ hipError_t launch_atomic_values(const int32_t* slot, const void* ss, int64_t L,
 }
 
 // The shared pipeline of fresh and batched assembly.
-// With EXP, triplet e reads ii, jj and ss through the expansion map `ex`.
-template <typename VT, bool BATCHED, bool EXP = false>
+// SRC: where triplet e's indices come from (int32 arrays, the expansion map
+// `ex`, or double arrays).
+template <typename VT, bool BATCHED, int SRC = fsp::kIdxI32>
 hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
                         int64_t L, int32_t m, int32_t n, BatchDesc bd,
                         int64_t N, const Layout& lo, const Tuning& tu,
@@ -525,12 +526,12 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   // 1. bin counts (the slot mode has none)
   if (mode != kSlot) e = launch(kHist, stream, [&] {
     if (mode == kDense)
-      hipLaunchKernelGGL((fsp::k_count_dense<BATCHED, EXP>), dim3((unsigned)(8 * ((g.T + 7) / 8))), dim3(blk),
+      hipLaunchKernelGGL((fsp::k_count_dense<BATCHED, SRC>), dim3((unsigned)(8 * ((g.T + 7) / 8))), dim3(blk),
                          (size_t)B * 4, stream, jj, L, n, bd, G, B, (int32_t)g.TS,
                          cntmat, at<uint32_t>(ws, 0), zwords,
                          at<uint32_t>(ws, lo.tilebad), ex);
     else
-      hipLaunchKernelGGL((fsp::k_count_claim<BATCHED, EXP, kClaimNT, kClaimIPT>),
+      hipLaunchKernelGGL((fsp::k_count_claim<BATCHED, SRC, kClaimNT, kClaimIPT>),
                          dim3((unsigned)g.T), dim3(kClaimNT),
                          (size_t)kClaimWindow * 4, stream, jj, L, n, bd, G,
                          kClaimWindow, bincnt, ctrl, ex);
@@ -559,25 +560,25 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   e = launch(kBucket, stream, [&] {
     if (mode == kDense) {
       if (packed)
-        hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED, true, EXP>), dim3((unsigned)(8 * ((g.T + 7) / 8))),
+        hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED, true, SRC>), dim3((unsigned)(8 * ((g.T + 7) / 8))),
                            dim3(blk), (size_t)B * 4, stream, ii, jj, ss, L, m, n, bd,
                            G, B, (int32_t)g.TS, cntmat, binstart, bucket, bcol,
                            (uint32_t)std::max<int64_t>(L, g.nslot), ctrl, ex);
       else
-        hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED, false, EXP>), dim3((unsigned)(8 * ((g.T + 7) / 8))),
+        hipLaunchKernelGGL((fsp::k_scatter_dense<VT, BATCHED, false, SRC>), dim3((unsigned)(8 * ((g.T + 7) / 8))),
                            dim3(blk), (size_t)B * 4, stream, ii, jj, ss, L, m, n, bd,
                            G, B, (int32_t)g.TS, cntmat, binstart, bucket, bcol,
                            (uint32_t)std::max<int64_t>(L, g.nslot), ctrl, ex);
     } else {
       const uint32_t trash = (uint32_t)std::max<int64_t>(L, g.nslot);
       if (packed)
-        hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, true, EXP, kClaimNT, kClaimIPT>),
+        hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, true, SRC, kClaimNT, kClaimIPT>),
                            dim3((unsigned)g.T), dim3(kClaimNT),
                            (size_t)kClaimWindow * 4, stream, ii, jj, ss, L, m, n, bd,
                            G, kClaimWindow, binstart, slotcap, binfill, bucket, bcol,
                            trash, ctrl, ex);
       else
-        hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, false, EXP, kClaimNT, kClaimIPT>),
+        hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, false, SRC, kClaimNT, kClaimIPT>),
                            dim3((unsigned)g.T), dim3(kClaimNT),
                            (size_t)kClaimWindow * 4, stream, ii, jj, ss, L, m, n, bd,
                            G, kClaimWindow, binstart, slotcap, binfill, bucket, bcol,
@@ -746,9 +747,11 @@ size_t fsparse_workspace_bytes(int64_t len, int64_t ncols, int32_t nb,
   return make_layout(len, ncols, nb, esize_of(dt), tuning()).total;
 }
 
-fsparse_status fsparse_dims(const int32_t* ii, const int32_t* jj, int64_t len,
-                            int64_t* m, int64_t* n, void* ws, size_t ws_bytes,
-                            hipStream_t stream) {
+// Default dimensions; with f64, ii and jj point to doubles (an index that is
+// not a whole number in [1, 2^31 - 1] reads as 0: E_INDEX).
+static fsparse_status dims_impl(const int32_t* ii, const int32_t* jj, int64_t len,
+                                int64_t* m, int64_t* n, void* ws, size_t ws_bytes,
+                                hipStream_t stream, bool f64) {
   if (!m || !n || len < 0 || len > kMaxI32 || !ws || ws_bytes < 256)
     return FSPARSE_E_ARG;
   if (len > 0 && (!ii || !jj)) return FSPARSE_E_ARG;
@@ -765,8 +768,13 @@ fsparse_status fsparse_dims(const int32_t* ii, const int32_t* jj, int64_t len,
   HIPCHK(hipMemcpyAsync(ws, h, sizeof(Ctrl), hipMemcpyHostToDevice, stream));
   BatchDesc bd{};
   hipError_t e = launch(kDims, stream, [&] {
-    hipLaunchKernelGGL(fsp::k_dims<false>, dim3(grid_for(len, 256, 8)), dim3(256),
-                       0, stream, ii, jj, len, bd, (Ctrl*)ws, (int32_t*)nullptr);
+    if (f64)
+      hipLaunchKernelGGL((fsp::k_dims<false, fsp::kIdxF64>), dim3(grid_for(len, 256, 8)),
+                         dim3(256), 0, stream, ii, jj, len, bd, (Ctrl*)ws,
+                         (int32_t*)nullptr);
+    else
+      hipLaunchKernelGGL(fsp::k_dims<false>, dim3(grid_for(len, 256, 8)), dim3(256),
+                         0, stream, ii, jj, len, bd, (Ctrl*)ws, (int32_t*)nullptr);
   });
   if (e != hipSuccess) return FSPARSE_E_HIP;
   HIPCHK(hipMemcpyAsync(h, ws, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
@@ -777,8 +785,23 @@ fsparse_status fsparse_dims(const int32_t* ii, const int32_t* jj, int64_t len,
   return FSPARSE_OK;
 }
 
-// Fresh assembly once the dimensions are known; with `ex`, triplet e reads
-// ii, jj and ss through the expansion map.
+fsparse_status fsparse_dims(const int32_t* ii, const int32_t* jj, int64_t len,
+                            int64_t* m, int64_t* n, void* ws, size_t ws_bytes,
+                            hipStream_t stream) {
+  return dims_impl(ii, jj, len, m, n, ws, ws_bytes, stream, false);
+}
+
+fsparse_status fsparse_dims_f64idx(const double* ii, const double* jj, int64_t len,
+                                   int64_t* m, int64_t* n, void* ws,
+                                   size_t ws_bytes, hipStream_t stream) {
+  return dims_impl(reinterpret_cast<const int32_t*>(ii),
+                   reinterpret_cast<const int32_t*>(jj), len, m, n, ws, ws_bytes,
+                   stream, true);
+}
+
+// Fresh assembly once the dimensions are known; `src` says where the
+// indices come from (with kIdxExpand, ii, jj and ss are read through `ex`;
+// with kIdxF64, ii and jj point to doubles).
 static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
                              const void* ss, fsparse_dtype dt, int64_t len,
                              int64_t m, int64_t n, int64_t nzmax,
@@ -786,7 +809,8 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
                              int32_t* irS, void* prS, int64_t cap,
                              int32_t* slot, void* ws, size_t ws_bytes,
                              fsparse_plan** plan, fsparse_info* info,
-                             hipStream_t stream, const fsp::Expand* ex) {
+                             hipStream_t stream, int src,
+                             const fsp::Expand* ex) {
   if (info) {
     info->m = m;
     info->n = n;
@@ -813,27 +837,21 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
     if (!h) return FSPARSE_E_HIP;
     int mode = lo.g.mode;
     for (;;) {
+      const fsp::Expand x = ex ? *ex : fsp::Expand{};
       hipError_t e;
-      if (dt == FSPARSE_F64 && ex)
-        e = run_pipeline<double, false, true>(ii, jj, (const double*)ss, len, (int32_t)m,
-                                              (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
-                                              (double*)prS, cap, slot_used, keep, mode,
-                                              stream, h, *ex);
-      else if (dt == FSPARSE_F64)
-        e = run_pipeline<double, false>(ii, jj, (const double*)ss, len, (int32_t)m,
-                                        (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
-                                        (double*)prS, cap, slot_used, keep, mode,
-                                        stream, h);
-      else if (ex)
-        e = run_pipeline<float, false, true>(ii, jj, (const float*)ss, len, (int32_t)m,
-                                             (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
-                                             (float*)prS, cap, slot_used, keep, mode,
-                                             stream, h, *ex);
+#define FSP_RUN(VT, S)                                                          \
+  run_pipeline<VT, false, S>(ii, jj, (const VT*)ss, len, (int32_t)m, (int32_t)n, bd, n, \
+                             lo, tu, ws, jcS, irS, (VT*)prS, cap, slot_used, keep, \
+                             mode, stream, h, x)
+      if (dt == FSPARSE_F64)
+        e = src == fsp::kIdxExpand ? FSP_RUN(double, fsp::kIdxExpand)
+          : src == fsp::kIdxF64    ? FSP_RUN(double, fsp::kIdxF64)
+                                   : FSP_RUN(double, fsp::kIdxI32);
       else
-        e = run_pipeline<float, false>(ii, jj, (const float*)ss, len, (int32_t)m,
-                                       (int32_t)n, bd, n, lo, tu, ws, jcS, irS,
-                                       (float*)prS, cap, slot_used, keep, mode,
-                                       stream, h);
+        e = src == fsp::kIdxExpand ? FSP_RUN(float, fsp::kIdxExpand)
+          : src == fsp::kIdxF64    ? FSP_RUN(float, fsp::kIdxF64)
+                                   : FSP_RUN(float, fsp::kIdxI32);
+#undef FSP_RUN
       if (e != hipSuccess) return FSPARSE_E_HIP;
       if (keep && launch_reuse_tiles(ws, lo, len, stream) != hipSuccess) return FSPARSE_E_HIP;
       // the bin kernel's last block has written err and nnz into h
@@ -913,7 +931,36 @@ fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
     if (n < 0) n = dn;
   }
   return assemble_impl(ii, jj, ss, dt, len, m, n, nzmax, flags, jcS, jcS_cap, irS,
-                       prS, cap, slot, ws, ws_bytes, plan, info, stream, nullptr);
+                       prS, cap, slot, ws, ws_bytes, plan, info, stream,
+                       fsp::kIdxI32, nullptr);
+}
+
+fsparse_status fsparse_assemble_f64idx(const double* ii, const double* jj,
+                                       const void* ss, fsparse_dtype dt,
+                                       int64_t len, int64_t m, int64_t n,
+                                       int64_t nzmax, unsigned flags,
+                                       int32_t* jcS, int64_t jcS_cap,
+                                       int32_t* irS, void* prS, int64_t cap,
+                                       int32_t* slot, void* ws, size_t ws_bytes,
+                                       fsparse_plan** plan, fsparse_info* info,
+                                       hipStream_t stream) {
+  if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
+  if (len < 0 || len > kMaxI32 || m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
+  if (flags & ~(unsigned)FSPARSE_ATOMIC) return FSPARSE_E_ARG;
+  if (len > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
+  if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS))) return FSPARSE_E_ARG;
+  if (plan) *plan = nullptr;
+  if (m < 0 || n < 0) {
+    int64_t dm = 0, dn = 0;
+    fsparse_status st = fsparse_dims_f64idx(ii, jj, len, &dm, &dn, ws, ws_bytes, stream);
+    if (st != FSPARSE_OK) return st;
+    if (m < 0) m = dm;
+    if (n < 0) n = dn;
+  }
+  return assemble_impl(reinterpret_cast<const int32_t*>(ii),
+                       reinterpret_cast<const int32_t*>(jj), ss, dt, len, m, n,
+                       nzmax, flags, jcS, jcS_cap, irS, prS, cap, slot, ws,
+                       ws_bytes, plan, info, stream, fsp::kIdxF64, nullptr);
 }
 
 // Exact division by d on [0, 2^31) in the bins' multiply-high form.
@@ -986,7 +1033,8 @@ fsparse_status fsparse_assemble_expand(const int32_t* ii, const int32_t* jj,
     ex.sv[d] = stride[2][d];
   }
   return assemble_impl(ii, jj, ss, dt, len, m, n, nzmax, flags, jcS, jcS_cap, irS,
-                       prS, cap, slot, ws, ws_bytes, plan, info, stream, &ex);
+                       prS, cap, slot, ws, ws_bytes, plan, info, stream,
+                       fsp::kIdxExpand, &ex);
 }
 
 fsparse_status fsparse_assemble_reuse(fsparse_plan* plan, const void* ss,

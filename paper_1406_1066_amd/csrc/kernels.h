@@ -361,10 +361,31 @@ __global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst,
   for (; i < n16; i += stride) dst[i] = src[i];
 }
 
+// Where the streaming passes take a triplet's indices from: int32 arrays,
+// the expansion map, or double arrays (Matlab's default array type).
+enum IdxSrc { kIdxI32 = 0, kIdxExpand = 1, kIdxF64 = 2 };
+
+// A unit-offset index held in a double (the pre-processing check of
+// Section 2.2): a whole number in [1, 2^31 - 1] converts exactly; anything
+// else (a fraction, NaN, an infinity, a value below 1 or beyond int32)
+// becomes 0, which every pass rejects like any other index below 1.
+__device__ __forceinline__ int32_t f64_index(double v) {
+  return (v >= 1.0 && v <= 2147483647.0 && v == ceil(v)) ? (int32_t)v : 0;
+}
+
+// Index x of an index array of the given source (not the expansion map).
+template <int SRC>
+__device__ __forceinline__ int32_t ld_index(const int32_t* __restrict__ p, int64_t x) {
+  if constexpr (SRC == kIdxF64)
+    return f64_index(reinterpret_cast<const double*>(p)[x]);
+  else
+    return p[x];
+}
+
 // ---------------------------------------------------------------------------
 // dims: largest / smallest index (the pre-processing pass, Section 2.2)
 // ---------------------------------------------------------------------------
-template <bool BATCHED>
+template <bool BATCHED, int SRC = kIdxI32>
 __global__ void k_dims(const int32_t* __restrict__ ii,
                        const int32_t* __restrict__ jj, int64_t L,
                        BatchDesc bd, Ctrl* ctrl, int32_t* __restrict__ bmax) {
@@ -372,7 +393,7 @@ __global__ void k_dims(const int32_t* __restrict__ ii,
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; e < L; e += stride) {
-    const int32_t r = ii[e], c = jj[e];
+    const int32_t r = ld_index<SRC>(ii, e), c = ld_index<SRC>(jj, e);
     rmin = min(rmin, r);
     cmin = min(cmin, c);
     if (BATCHED) {
@@ -613,7 +634,7 @@ constexpr int kScatterU = 4;
 // look-back words (zero[0..zwords)), which no later kernel of the call uses
 // before it is done; so it reports a bad column not in the control block
 // but in its own word tilebad[tile], which the column scan reads.
-template <bool BATCHED, bool EXP>
+template <bool BATCHED, int SRC>
 __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
                               int32_t n, BatchDesc bd, BinGeo G, int32_t B,
                               int32_t TS, uint32_t* __restrict__ cnt,
@@ -641,10 +662,10 @@ __global__ void k_count_dense(const int32_t* __restrict__ jj, int64_t L,
 #pragma unroll
     for (int u = 0; u < kDenseU; ++u) {
       const int64_t e = min(eb + u * nt, t1 - 1);  // no branch
-      if constexpr (EXP)
+      if constexpr (SRC == kIdxExpand)
         cj[u] = jj[exp_at(ex.sj, exp_pos(ex, e))];
       else
-        cj[u] = jj[e];
+        cj[u] = ld_index<SRC>(jj, e);
     }
 #pragma unroll
     for (int u = 0; u < kDenseU; ++u) {
@@ -746,7 +767,7 @@ k_colscan_bins(uint32_t* __restrict__ cnt, int32_t T, int32_t B,
 
 // dense mode, pass 3: scatter (row, k, value) and the in-bin column into
 // the bins; the position inside the bin is an LDS atomic rank
-template <typename VT, bool BATCHED, bool PACKED, bool EXP>
+template <typename VT, bool BATCHED, bool PACKED, int SRC>
 __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
                                 const int32_t* __restrict__ jj,
                                 const VT* __restrict__ ss, int64_t L, int32_t m,
@@ -787,11 +808,16 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
     for (int u = 0; u < kDenseSU; ++u) {
       const int64_t e = eb + u * nt;
       if (e < t1) {
-        if constexpr (EXP) {
+        if constexpr (SRC == kIdxExpand) {
           const ExpPos o = exp_pos(ex, e);
           cj[u] = jj[exp_at(ex.sj, o)];
           ri[u] = ii[exp_at(ex.si, o)];
           sv[u] = ss[exp_at(ex.sv, o)];
+        } else if constexpr (SRC == kIdxF64) {
+          const uint32_t x = (uint32_t)(e - t0);
+          cj[u] = f64_index(ld_off32(reinterpret_cast<const double*>(jj) + t0, x));
+          ri[u] = f64_index(ld_off32(reinterpret_cast<const double*>(ii) + t0, x));
+          sv[u] = ld_off32(st, x);
         } else {
           const uint32_t x = (uint32_t)(e - t0);
           cj[u] = ld_off32(jt, x);
@@ -829,7 +855,7 @@ __global__ void k_scatter_dense(const int32_t* __restrict__ ii,
 }
 
 // claim mode: tiles of NT*IPT triplets; bins of the tile live in registers
-template <bool BATCHED, bool EXP, int NT, int IPT>
+template <bool BATCHED, int SRC, int NT, int IPT>
 __device__ __forceinline__ void tile_bins(const int32_t* __restrict__ jj,
                                           int64_t L, int32_t n, const BatchDesc& bd,
                                           const BinGeo& G, int64_t t0, int* sB,
@@ -845,10 +871,10 @@ __device__ __forceinline__ void tile_bins(const int32_t* __restrict__ jj,
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
     const int64_t e = min(t0 + (int64_t)j * NT + threadIdx.x, L - 1);
-    if constexpr (EXP)
+    if constexpr (SRC == kIdxExpand)
       cj[j] = jj[exp_at(ex.sj, exp_pos(ex, e))];
     else
-      cj[j] = jj[e];
+      cj[j] = ld_index<SRC>(jj, e);
   }
 #pragma unroll
   for (int j = 0; j < IPT; ++j) {
@@ -889,7 +915,7 @@ __device__ __forceinline__ void block_minmax(int32_t& lo, int32_t& hi,
   hi = *sHi;
 }
 
-template <bool BATCHED, bool EXP, int NT, int IPT>
+template <bool BATCHED, int SRC, int NT, int IPT>
 __global__ void __launch_bounds__(NT)
 k_count_claim(const int32_t* __restrict__ jj, int64_t L, int32_t n,
               BatchDesc bd, BinGeo G, int32_t WMAX,
@@ -900,7 +926,7 @@ k_count_claim(const int32_t* __restrict__ jj, int64_t L, int32_t n,
   const int64_t t0 = (int64_t)blockIdx.x * NT * IPT;
   int32_t bn[IPT], cj[IPT], lo, hi;
   bool bad = false;
-  tile_bins<BATCHED, EXP, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, cj, lo, hi, bad, ex);
+  tile_bins<BATCHED, SRC, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, cj, lo, hi, bad, ex);
   block_minmax<NT>(lo, hi, &sLo, &sHi);
   if (bad) atomicOr(&ctrl->err, kErrCol);
   if (hi < lo) return;
@@ -921,7 +947,7 @@ k_count_claim(const int32_t* __restrict__ jj, int64_t L, int32_t n,
   }
 }
 
-template <typename VT, bool BATCHED, bool PACKED, bool EXP, int NT, int IPT>
+template <typename VT, bool BATCHED, bool PACKED, int SRC, int NT, int IPT>
 __global__ void __launch_bounds__(NT)
 k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
                 const VT* __restrict__ ss, int64_t L, int32_t m, int32_t n,
@@ -936,7 +962,7 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
   const int64_t t0 = (int64_t)blockIdx.x * NT * IPT;
   int32_t bn[IPT], cj[IPT], lo, hi;
   bool bad = false;
-  tile_bins<BATCHED, EXP, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, cj, lo, hi, bad, ex);
+  tile_bins<BATCHED, SRC, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, cj, lo, hi, bad, ex);
   block_minmax<NT>(lo, hi, &sLo, &sHi);
   if (hi < lo) return;
   const int width = hi - lo + 1;
@@ -972,12 +998,12 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
 #pragma unroll
     for (int u = 0; u < kScatterU; ++u) {
       const int64_t e = min(t0 + (int64_t)(j0 + u) * NT + threadIdx.x, L - 1);
-      if constexpr (EXP) {
+      if constexpr (SRC == kIdxExpand) {
         const ExpPos o = exp_pos(ex, e);
         ri[u] = ii[exp_at(ex.si, o)];
         sv[u] = ss[exp_at(ex.sv, o)];
       } else {
-        ri[u] = ii[e];
+        ri[u] = ld_index<SRC>(ii, e);
         sv[u] = ss[e];
       }
     }
