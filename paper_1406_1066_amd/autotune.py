@@ -57,7 +57,11 @@ def _store(d: dict):
 
 
 def config_class(L: int, N: int, dtype, nb: int = 1) -> str:
-    dev = torch.cuda.get_device_name(torch.cuda.current_device())
+    # the architecture and compute-unit count (the marketing name is not
+    # available in every environment, e.g. under a profiler)
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    dev = "%s/%dcu" % (getattr(p, "gcnArchName", "") or p.name,
+                       p.multi_processor_count)
     lg = lambda x: int(math.log2(max(1, x)))
     return "%s|%s|L2^%d|N2^%d|LN2^%d|nb%d" % (
         dev, str(dtype).replace("torch.", ""), lg(L), lg(N),
