@@ -174,6 +174,23 @@ def assemble_columns(ii, jj, ss, m: int, n: int, cols: Sequence[int],
     return out, kidx, gslot
 
 
+def drop_zeros(res: Result) -> Result:
+    """Matlab's convention on an assembled result: a sparse matrix stores no
+    zeros, so the pairs whose sum is +0 or -0 are removed.  The paper keeps
+    them (its nnz counts distinct pairs); this is the option that gives
+    Matlab's output.  Kept pairs keep their order; jcS counts the kept pairs
+    before each column; a triplet of a removed pair gets slot -1.
+    """
+    keep = res.prS != 0
+    before = np.concatenate([[0], np.cumsum(keep)]).astype(np.int64)
+    jcS = before[res.jcS.astype(np.int64)].astype(np.int32)
+    newpos = (before[:-1]).astype(np.int32)
+    slot = np.where(keep[res.slot], newpos[res.slot], -1).astype(np.int32) \
+        if res.slot.size else res.slot.copy()
+    return Result(jcS, res.irS[keep].copy(), res.prS[keep].copy(), slot,
+                  res.m, res.n)
+
+
 def indices_from_double(v) -> np.ndarray:
     """Unit-offset indices held in doubles, checked and converted.
 

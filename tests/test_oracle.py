@@ -440,3 +440,51 @@ def test_double_indices_assemble_like_integers():
     b = oracle.assemble(ii.astype(np.int32), jj.astype(np.int32), ss)
     assert np.array_equal(a.jcS, b.jcS) and np.array_equal(a.irS, b.irS)
     assert a.prS.tobytes() == b.prS.tobytes()
+
+
+# ---------------------------------------------------------------------------
+# dropping zero sums (Matlab stores no zeros)
+# ---------------------------------------------------------------------------
+def test_drop_zeros_hand_example():
+    # (1,1): 1 + -1 = 0 -> dropped; (2,1): -0.0 alone -> dropped;
+    # (3,1): 0 + 5 -> kept; (1,2): 2 -> kept; column 3 empty
+    ii = i32([1, 2, 3, 1, 1, 3])
+    jj = i32([1, 1, 1, 2, 1, 1])
+    ss = np.array([1.0, -0.0, 0.0, 2.0, -1.0, 5.0])
+    r = oracle.drop_zeros(oracle.assemble(ii, jj, ss, 3, 3))
+    assert r.jcS.tolist() == [0, 1, 2, 2]
+    assert r.irS.tolist() == [2, 0] and r.prS.tolist() == [5.0, 2.0]
+    assert r.slot.tolist() == [-1, -1, 0, 1, -1, 0]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_drop_zeros_against_dense_accumulation(seed):
+    # small integers cancel often; the dense matrix summed in k order (the
+    # brute force) has exactly the kept pairs as its nonzeros, column-major
+    rng = np.random.default_rng(400 + seed)
+    m, n, L = 6, 5, 120
+    ii = rng.integers(1, m + 1, L).astype(np.int32)
+    jj = rng.integers(1, n + 1, L).astype(np.int32)
+    ss = rng.integers(-2, 3, L).astype(np.float64)
+    r = oracle.drop_zeros(oracle.assemble(ii, jj, ss, m, n))
+    D = np.zeros((m, n))
+    for k in range(L):
+        D[ii[k] - 1, jj[k] - 1] += ss[k]
+    rows, cols = np.nonzero(D.T)            # column-major order of nonzeros
+    assert r.nnz == rows.size
+    assert np.array_equal(r.irS, cols) and np.array_equal(r.prS, D.T[rows, cols])
+    assert np.array_equal(np.diff(r.jcS), np.count_nonzero(D, axis=0))
+    for k in range(L):
+        s = r.slot[k]
+        if D[ii[k] - 1, jj[k] - 1] == 0:
+            assert s == -1
+        else:
+            assert r.irS[s] == ii[k] - 1 and r.jcS[jj[k] - 1] <= s < r.jcS[jj[k]]
+
+
+def test_drop_zeros_keeps_everything_without_zero_sums():
+    t = W.uniform(5000, 300, 200, seed=3)
+    a = oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
+    b = oracle.drop_zeros(a)
+    assert np.array_equal(a.jcS, b.jcS) and np.array_equal(a.slot, b.slot)
+    assert a.prS.tobytes() == b.prS.tobytes()
