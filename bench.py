@@ -239,6 +239,7 @@ def main():
             line["modes"]["expand"] = expanded(args, fs, torch, t, ss, vb, eb)
         line["modes"]["f64_index"] = double_indices(args, fs, torch, ii, jj,
                                                     ss, m, n)
+        line["modes"]["drop_zeros"] = dropped(args, fs, torch, ii, jj, ss, m, n)
         line["copy_gbps"] = copy_bw(fs, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(t, args.cpu_seconds)
@@ -350,6 +351,32 @@ def double_indices(args, fs, torch, ii, jj, ss, m, n):
     del di, dj, ws, out
     return {"value": L / (ms * 1e-3) / 1e9, "unit": "Gtriplets/s", "ms": ms,
             "stages_ms": stages}
+
+
+def dropped(args, fs, torch, ii, jj, ss, m, n):
+    """Fresh assembly with the zero sums removed (Matlab's convention): the
+    compaction over the pairs and the second wait, on top of the plain call."""
+    L = ss.numel()
+    ws = torch.empty(fs.workspace_bytes(L, n, 1, ss.dtype), dtype=torch.uint8,
+                     device=ss.device)
+    out = (torch.empty(n + 1, dtype=torch.int32, device=ss.device),
+           torch.empty(L, dtype=torch.int32, device=ss.device),
+           torch.empty(L, dtype=ss.dtype, device=ss.device))
+
+    def fn():
+        return fs.sparse(ii, jj, ss, m, n, ws=ws, out=out, drop_zeros=True)
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    stages, _ = stage_profile(fs, torch, fn, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = fn()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    log("drop_zeros", "%.4f ms" % ms)
+    return {"value": L / (ms * 1e-3) / 1e9, "unit": "Gtriplets/s", "ms": ms,
+            "nnz_kept": r.nnz, "stages_ms": stages}
 
 
 def copy_bw(fs, torch):

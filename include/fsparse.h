@@ -28,7 +28,8 @@
  *    bit-identical from run to run.  FSPARSE_ATOMIC adds them with device
  *    atomics in an unspecified order instead.
  *  - Entries whose sum is zero are kept (nnz counts distinct index pairs,
- *    Section 2.2: nnz = 1 + max irank).
+ *    Section 2.2: nnz = 1 + max irank), unless FSPARSE_DROP_ZEROS asks for
+ *    Matlab's convention of storing no zeros.
  *  - Functions return a status and never abort.  After an error the output
  *    arrays hold unspecified data.
  *  - len, m, n and nnz must stay below 2^31.
@@ -49,8 +50,9 @@ typedef enum { FSPARSE_F64 = 0, FSPARSE_F32 = 1 } fsparse_dtype;
 
 /* flags */
 enum {
-  FSPARSE_ORDERED = 0u, /* increasing-k fold, bit-exact (default)          */
-  FSPARSE_ATOMIC = 1u   /* device atomics, order unspecified               */
+  FSPARSE_ORDERED = 0u,    /* increasing-k fold, bit-exact (default)       */
+  FSPARSE_ATOMIC = 1u,     /* device atomics, order unspecified            */
+  FSPARSE_DROP_ZEROS = 2u  /* fresh calls: remove pairs whose sum is zero  */
 };
 
 typedef enum {
@@ -106,7 +108,14 @@ fsparse_status fsparse_dims(const int32_t *ii, const int32_t *jj, int64_t len,
  *           index, computed with one extra pass and one extra wait).  With
  *           given dimensions every index must lie in [1,m] x [1,n].
  *  nzmax    Matlab capacity request; only reported back in info->nzmax.
- *  flags    FSPARSE_ORDERED or FSPARSE_ATOMIC (how prS is summed).
+ *  flags    FSPARSE_ORDERED or FSPARSE_ATOMIC (how prS is summed), optionally
+ *           | FSPARSE_DROP_ZEROS: a Matlab sparse matrix stores no zeros, so
+ *           the pairs whose sum is +0 or -0 are removed after the fold (the
+ *           paper keeps them; this option gives Matlab's result).  Then
+ *           info->nnz, jcS, irS, prS describe the kept pairs, slot[k] is the
+ *           kept position or -1, cap must still hold every distinct pair
+ *           (E_CAPACITY reports that count), the call waits twice, and a
+ *           plan cannot be made (E_ARG: the pattern depends on the values).
  *  jcS      [jcS_cap >= n+1] out, column pointers
  *  irS,prS  [cap] out; cap >= nnz is required.  cap = len always suffices.
  *           When cap < nnz the call returns FSPARSE_E_CAPACITY with the

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FSPARSE_LIBRARY") or os.path.join(HERE, "libfsparse.so")
 
 F64, F32 = 0, 1
-ORDERED, ATOMIC = 0, 1
+ORDERED, ATOMIC, DROP_ZEROS = 0, 1, 2
 OK, E_INDEX, E_ARG, E_CAPACITY, E_PLAN, E_HIP = range(6)
 
 

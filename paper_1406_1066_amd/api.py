@@ -187,7 +187,8 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
            atomic: bool = False, keep_slot: bool = False, plan: bool = False,
            cap: Optional[int] = None,
            ws: Optional[torch.Tensor] = None,
-           out: Optional[tuple] = None) -> Assembled:
+           out: Optional[tuple] = None,
+           drop_zeros: bool = False) -> Assembled:
     """S = sparse(ii, jj, ss, m, n, nzmax) on the GPU.
 
     ``ii``/``jj`` unit-offset indices: integer arrays (converted to int32 on
@@ -199,6 +200,8 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
     carries a re-use plan (see ``reassemble``); ``keep_slot`` returns the
     inverse rank slot[k].  ``out = (jcS, irS, prS[, slot])`` supplies
     preallocated output buffers (irS/prS capacity = their length).
+    ``drop_zeros`` removes the pairs whose sum is zero, as Matlab stores no
+    zeros (the slot of a dropped pair's triplets is -1; no plan then).
     """
     dev = _device(ss, ii, jj)
     ss = ss.contiguous()
@@ -219,14 +222,19 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
     def call(*a):
         return fn(_ptr(ii), _ptr(jj), _ptr(ss), _dt(ss.dtype), Ln, *a)
     return _fresh(call, Ln, int(m), int(n), ss, dev, nzmax, atomic, keep_slot,
-                  plan, cap, ws, out, "fsparse_assemble")
+                  plan, cap, ws, out, "fsparse_assemble", drop_zeros)
 
 
 def _fresh(call, Ln, m, n, ss, dev, nzmax, atomic, keep_slot, plan, cap, ws,
-           out, name) -> Assembled:
+           out, name, drop_zeros=False) -> Assembled:
     """Output buffers and the capacity / workspace retry around one fresh
     assembly call ``call(m, n, nzmax, flags, jcS, jcS_cap, irS, prS, cap,
     slot, ws, ws_bytes, plan_out, info, stream)``."""
+    if drop_zeros and plan:
+        raise ValueError("drop_zeros: the pattern depends on the values, "
+                         "so no re-use plan can be made")
+    flags = (L.ATOMIC if atomic else L.ORDERED) | (
+        L.DROP_ZEROS if drop_zeros else 0)
     if ws is None:
         ws = _workspace(workspace_bytes(Ln, n, 1, ss.dtype), dev)
     slot = None
@@ -252,7 +260,7 @@ def _fresh(call, Ln, m, n, ss, dev, nzmax, atomic, keep_slot, plan, cap, ws,
         ph = ctypes.c_void_p()
         st = call(
             m, n, int(nzmax) if nzmax is not None else 0,
-            L.ATOMIC if atomic else L.ORDERED, _ptr(jcS), jcS.numel(),
+            flags, _ptr(jcS), jcS.numel(),
             _ptr(irS), _ptr(prS), cap, _ptr(slot), _ptr(ws), ws.numel(),
             ctypes.byref(ph) if plan else None, ctypes.byref(info), _stream())
         if st == L.E_CAPACITY and info.nnz > cap and irS0 is None:
@@ -281,7 +289,8 @@ def sparse_expand(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
                   atomic: bool = False, keep_slot: bool = False,
                   plan: bool = False, cap: Optional[int] = None,
                   ws: Optional[torch.Tensor] = None,
-                  out: Optional[tuple] = None) -> Assembled:
+                  out: Optional[tuple] = None,
+                  drop_zeros: bool = False) -> Assembled:
     """Assembly with index expansion: ``ii``, ``jj``, ``ss`` broadcast.
 
     The three arrays (at most 3-D) broadcast to one grid of shape
@@ -326,7 +335,7 @@ def sparse_expand(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
         return L.fsparse_assemble_expand(_ptr(ii), _ptr(jj), _ptr(ss),
                                          _dt(ss.dtype), ctypes.byref(x), *a)
     return _fresh(call, Ln, int(m), int(n), ss, dev, nzmax, atomic, keep_slot,
-                  plan, cap, ws, out, "fsparse_assemble_expand")
+                  plan, cap, ws, out, "fsparse_assemble_expand", drop_zeros)
 
 
 def reassemble(res: Assembled, ss: torch.Tensor,

@@ -53,11 +53,11 @@ int kernel_cap(int cap) { return cap <= 1024 ? 1024 : (cap <= 2048 ? 2048 : 4096
 // ---------------------------------------------------------------------------
 enum Stage {
   kDims, kInit, kHist, kScan, kBucket, kChunk, kBatchedJcs, kAtomic,
-  kReuse, kBackward, kCopy, kFill, kColScan, kNumStages
+  kReuse, kBackward, kCopy, kFill, kColScan, kDrop, kNumStages
 };
 const char* kStageNames[kNumStages] = {
     "dims", "init", "count", "binscan", "scatter", "bin", "batched_jcs",
-    "atomic", "reuse", "backward", "copy", "fill", "colscan"};
+    "atomic", "reuse", "backward", "copy", "fill", "colscan", "drop_zeros"};
 
 struct Rec {
   int stage;
@@ -300,7 +300,7 @@ struct Layout {
   int64_t mmax;  // largest m over the matrices (batched)
   size_t ctrl, scan_st, bin_st, bincnt, binfill, bmax, zero_end;
   size_t binstart, cntmat, tilebad, bcol, colptr, bucket, tmp, perm, seg, islot, rtile;
-  size_t slowlist, slowd, slowb;
+  size_t slowlist, slowd, slowb, dropst;
   size_t b_trip, b_col, b_m, b_n, jcg, nnzoff;
   size_t total;
   int64_t nscan;
@@ -337,6 +337,8 @@ Layout make_layout(int64_t L, int64_t N, int nb, int esize, const Tuning& tu) {
   o.slowlist = p;    p = al(p + 4 * (size_t)B);
   o.slowd = p;       p = al(p + 4 * (size_t)B);
   o.slowb = p;       p = al(p + 8 * (size_t)B);
+  // drop zeros: look-back words of the scan over the pairs, and its ticket
+  o.dropst = p;      p = al(p + 64 + 8 * (size_t)((L + 1 + kScanTile - 1) / kScanTile));
   o.b_trip = p;      p = al(p + 8 * (size_t)(nb + 1));
   o.b_col = p;       p = al(p + 8 * (size_t)(nb + 1));
   o.b_m = p;         p = al(p + 4 * (size_t)nb);
@@ -467,6 +469,44 @@ fsparse_status plan_reuse_atomic(fsparse_plan* pl, const void* ss, void* prS,
   }
   hipError_t e = launch(kReuse, stream, [&] { (void)hipGraphLaunch(pl->x_at, stream); });
   return e == hipSuccess ? FSPARSE_OK : FSPARSE_E_HIP;
+}
+
+// Removes the zero sums from the nnz pairs in place (irS, prS, jcS, and
+// slot when given); the kept count lands in h->kept once the stream is done.
+template <typename VT>
+hipError_t drop_zeros(void* ws, const Layout& lo, int64_t nnz, int64_t n, int64_t L,
+                      int32_t* jcS, int32_t* irS, VT* prS, int32_t* slot,
+                      Ctrl* h, hipStream_t stream) {
+  uint32_t* keep = at<uint32_t>(ws, lo.perm);          // nnz words
+  int32_t* excl = at<int32_t>(ws, lo.seg);             // nnz + 1 words
+  int32_t* ir2 = at<int32_t>(ws, lo.tmp);              // scratch: nnz rows,
+  // then the values, 8-byte aligned: 4 (nnz + 1) + sizeof(VT) nnz bytes fit
+  // the region's (8 + sizeof(VT)) L
+  VT* pr2 = reinterpret_cast<VT*>(ir2 + ((nnz + 1) & ~int64_t(1)));
+  uint32_t* ticket = at<uint32_t>(ws, lo.dropst);
+  uint64_t* status = at<uint64_t>(ws, lo.dropst + 64);
+  const int64_t tiles = (nnz + 1 + kScanTile - 1) / kScanTile;
+  const int64_t zw = (64 + 8 * tiles) / 4;
+  hipError_t e = launch(kDrop, stream, [&] {
+    hipLaunchKernelGGL(fsp::k_zero, dim3(grid_for(zw, 256, 4)), dim3(256), 0, stream,
+                       ticket, zw);
+    hipLaunchKernelGGL(fsp::k_drop_flags<VT>, dim3(grid_for(nnz, 256, 4)), dim3(256), 0,
+                       stream, (const VT*)prS, nnz, keep);
+    hipLaunchKernelGGL((fsp::k_scan_excl<kScanNT, kScanIPT>), dim3((unsigned)tiles),
+                       dim3(kScanNT), 0, stream, (const uint32_t*)keep, (int32_t)nnz,
+                       excl, status, ticket, UINT32_MAX, (uint32_t*)nullptr,
+                       (int32_t*)nullptr);
+    hipLaunchKernelGGL(fsp::k_drop_compact<VT>, dim3(grid_for(nnz, 256, 4)), dim3(256), 0,
+                       stream, (const int32_t*)excl, nnz, (const int32_t*)irS,
+                       (const VT*)prS, ir2, pr2);
+    hipLaunchKernelGGL(fsp::k_drop_finish<VT>,
+                       dim3(grid_for(std::max<int64_t>(std::max(nnz, L), n + 1), 256, 4)),
+                       dim3(256), 0, stream, (const int32_t*)excl, nnz,
+                       (const int32_t*)ir2, (const VT*)pr2, irS, prS, jcS, n, slot, L);
+  });
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(&h->kept, excl + nnz, sizeof(int32_t), hipMemcpyDeviceToHost,
+                        stream);
 }
 
 template <typename VT>
@@ -881,6 +921,14 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
           : launch_atomic_values<float>(slot_used, ss, len, prS, nnz, tu.rblock, stream);
       if (ea != hipSuccess) return FSPARSE_E_HIP;
     }
+    if (flags & FSPARSE_DROP_ZEROS) {
+      hipError_t ed = dt == FSPARSE_F64
+          ? drop_zeros<double>(ws, lo, nnz, n, len, jcS, irS, (double*)prS, slot, h, stream)
+          : drop_zeros<float>(ws, lo, nnz, n, len, jcS, irS, (float*)prS, slot, h, stream);
+      if (ed != hipSuccess) return FSPARSE_E_HIP;
+      HIPCHK(hipStreamSynchronize(stream));
+      if (info) info->nnz = h->kept;
+    }
     if (keep) {
       fsparse_plan* pl = new (std::nothrow) fsparse_plan();
       if (!pl) return FSPARSE_E_ARG;
@@ -919,7 +967,9 @@ fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
                                 hipStream_t stream) {
   if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
   if (len < 0 || len > kMaxI32 || m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
-  if (flags & ~(unsigned)FSPARSE_ATOMIC) return FSPARSE_E_ARG;
+  if (flags & ~(unsigned)(FSPARSE_ATOMIC | FSPARSE_DROP_ZEROS)) return FSPARSE_E_ARG;
+  // the pattern of a call that drops zeros depends on the values: no plan
+  if ((flags & FSPARSE_DROP_ZEROS) && plan) return FSPARSE_E_ARG;
   if (len > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
   if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS))) return FSPARSE_E_ARG;
   if (plan) *plan = nullptr;
@@ -946,7 +996,9 @@ fsparse_status fsparse_assemble_f64idx(const double* ii, const double* jj,
                                        hipStream_t stream) {
   if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
   if (len < 0 || len > kMaxI32 || m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
-  if (flags & ~(unsigned)FSPARSE_ATOMIC) return FSPARSE_E_ARG;
+  if (flags & ~(unsigned)(FSPARSE_ATOMIC | FSPARSE_DROP_ZEROS)) return FSPARSE_E_ARG;
+  // the pattern of a call that drops zeros depends on the values: no plan
+  if ((flags & FSPARSE_DROP_ZEROS) && plan) return FSPARSE_E_ARG;
   if (len > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
   if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS))) return FSPARSE_E_ARG;
   if (plan) *plan = nullptr;
@@ -981,7 +1033,9 @@ fsparse_status fsparse_assemble_expand(const int32_t* ii, const int32_t* jj,
                                        hipStream_t stream) {
   if (check_dt(dt) != FSPARSE_OK || !x) return FSPARSE_E_ARG;
   if (m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
-  if (flags & ~(unsigned)FSPARSE_ATOMIC) return FSPARSE_E_ARG;
+  if (flags & ~(unsigned)(FSPARSE_ATOMIC | FSPARSE_DROP_ZEROS)) return FSPARSE_E_ARG;
+  // the pattern of a call that drops zeros depends on the values: no plan
+  if ((flags & FSPARSE_DROP_ZEROS) && plan) return FSPARSE_E_ARG;
   int64_t len = 1;
   for (int d = 0; d < 3; ++d) {
     if (x->shape[d] < 0 || x->shape[d] > kMaxI32) return FSPARSE_E_ARG;

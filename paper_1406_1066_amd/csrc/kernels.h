@@ -54,7 +54,8 @@ struct Ctrl {
   int64_t nnz;
   int64_t ltot;
   int32_t rmin, rmax, cmin, cmax;  // dims pass
-  uint32_t pad1[20];
+  int32_t kept;                    // pairs left after dropping zero sums
+  uint32_t pad1[19];
 };
 static_assert(sizeof(Ctrl) <= 256, "control block");
 
@@ -2316,6 +2317,59 @@ __global__ void k_backward(const int32_t* __restrict__ slot,
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; k < L; k += stride) gs[k] = g[slot[k]];
+}
+
+// ---------------------------------------------------------------------------
+// drop zeros: remove the pairs whose sum is zero (+0 or -0), as a Matlab
+// sparse matrix stores no zeros.  keep[j] = prS[j] != 0, its exclusive scan
+// gives every kept entry its new place, the kept entries go out of place to
+// scratch and back, and jcS and the slots are renumbered.
+// ---------------------------------------------------------------------------
+template <typename VT>
+__global__ void k_drop_flags(const VT* __restrict__ prS, int64_t nnz,
+                             uint32_t* __restrict__ keep) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; j < nnz; j += stride) keep[j] = prS[j] != (VT)0 ? 1u : 0u;
+}
+
+template <typename VT>
+__global__ void k_drop_compact(const int32_t* __restrict__ excl, int64_t nnz,
+                               const int32_t* __restrict__ irS,
+                               const VT* __restrict__ prS,
+                               int32_t* __restrict__ ir2, VT* __restrict__ pr2) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; j < nnz; j += stride) {
+    const int32_t p = excl[j];
+    if (excl[j + 1] > p) {
+      ir2[p] = irS[j];
+      pr2[p] = prS[j];
+    }
+  }
+}
+
+// back into the caller's arrays (excl[nnz] entries), jcS[c] = kept entries
+// before the column's old start, slot[k] = the new place or -1
+template <typename VT>
+__global__ void k_drop_finish(const int32_t* __restrict__ excl, int64_t nnz,
+                              const int32_t* __restrict__ ir2,
+                              const VT* __restrict__ pr2, int32_t* __restrict__ irS,
+                              VT* __restrict__ prS, int32_t* __restrict__ jcS,
+                              int64_t n, int32_t* __restrict__ slot, int64_t L) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t kept = excl[nnz];
+  for (int64_t j = t; j < kept; j += stride) {
+    irS[j] = ir2[j];
+    prS[j] = pr2[j];
+  }
+  for (int64_t c = t; c <= n; c += stride) jcS[c] = excl[jcS[c]];
+  if (slot)
+    for (int64_t k = t; k < L; k += stride) {
+      const int32_t s = slot[k];
+      slot[k] = excl[s + 1] > excl[s] ? excl[s] : -1;
+    }
 }
 
 }  // namespace fsp
