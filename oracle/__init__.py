@@ -174,6 +174,27 @@ def assemble_columns(ii, jj, ss, m: int, n: int, cols: Sequence[int],
     return out, kidx, gslot
 
 
+def append(res: Result, ii, jj, ss, m: Optional[int] = None,
+           n: Optional[int] = None) -> Result:
+    """Delayed assembly (Section 2.1: input not all available at the first
+    call), written out: the stored pairs of ``res`` as triplets in storage
+    order, then the new triplets, assembled in one call.  m and n default to
+    those of ``res`` grown to the largest new index.
+    """
+    cols = np.repeat(np.arange(res.n, dtype=np.int64),
+                     np.diff(res.jcS.astype(np.int64)))
+    ii = np.asarray(ii)
+    jj = np.asarray(jj)
+    if m is None:
+        m = max(res.m, int(ii.max()) if ii.size else 0)
+    if n is None:
+        n = max(res.n, int(jj.max()) if jj.size else 0)
+    return assemble(np.concatenate([res.irS.astype(np.int64) + 1, ii]),
+                    np.concatenate([cols + 1, jj]),
+                    np.concatenate([res.prS, np.asarray(ss, res.prS.dtype)]),
+                    m, n)
+
+
 def drop_zeros(res: Result) -> Result:
     """Matlab's convention on an assembled result: a sparse matrix stores no
     zeros, so the pairs whose sum is +0 or -0 are removed.  The paper keeps

@@ -488,3 +488,40 @@ def test_drop_zeros_keeps_everything_without_zero_sums():
     b = oracle.drop_zeros(a)
     assert np.array_equal(a.jcS, b.jcS) and np.array_equal(a.slot, b.slot)
     assert a.prS.tobytes() == b.prS.tobytes()
+
+
+# ---------------------------------------------------------------------------
+# delayed assembly: continuing from stored sums = one fold over everything
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("seed", range(4))
+def test_append_equals_one_assembly(dtype, seed):
+    rng = np.random.default_rng(500 + seed)
+    L, m, n = 4000, 30, 20
+    ii = rng.integers(1, m + 1, L).astype(np.int32)
+    jj = rng.integers(1, n + 1, L).astype(np.int32)
+    # magnitudes far apart make the fold order visible; -0.0 and exact
+    # cancellation check the sign of zero sums
+    ss = (rng.standard_normal(L) * 10.0 ** rng.integers(-8, 9, L)).astype(dtype)
+    ss[rng.random(L) < 0.05] = -0.0
+    ss[:50] = 1e8
+    ss[50:100] = -1e8
+    cuts = sorted(rng.choice(np.arange(1, L), size=3, replace=False))
+    parts = np.split(np.arange(L), cuts)
+    r = oracle.assemble(ii[parts[0]], jj[parts[0]], ss[parts[0]], m, n)
+    for p in parts[1:]:
+        r = oracle.append(r, ii[p], jj[p], ss[p], m, n)
+    want = oracle.assemble(ii, jj, ss, m, n)
+    assert np.array_equal(r.jcS, want.jcS) and np.array_equal(r.irS, want.irS)
+    assert r.prS.tobytes() == want.prS.tobytes()
+    # a fold from +0.0 never ends at -0.0
+    assert not np.any(np.signbit(want.prS) & (want.prS == 0))
+
+
+def test_append_grows_dimensions_and_maps_old_pairs():
+    a = oracle.assemble(i32([1, 2]), i32([1, 2]), np.array([1.0, 2.0]), 2, 2)
+    r = oracle.append(a, i32([5, 1]), i32([1, 3]), np.array([3.0, 4.0]))
+    assert (r.m, r.n) == (5, 3)
+    assert r.jcS.tolist() == [0, 2, 3, 4]
+    assert r.irS.tolist() == [0, 4, 1, 0] and r.prS.tolist() == [1, 3, 2, 4]
+    assert r.slot.tolist() == [0, 2, 1, 3]     # old pairs, then new triplets
