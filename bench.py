@@ -240,6 +240,7 @@ def main():
         line["modes"]["f64_index"] = double_indices(args, fs, torch, ii, jj,
                                                     ss, m, n)
         line["modes"]["drop_zeros"] = dropped(args, fs, torch, ii, jj, ss, m, n)
+        line["modes"]["append"] = appended(args, fs, torch, ii, jj, ss, m, n)
         line["copy_gbps"] = copy_bw(fs, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(t, args.cpu_seconds)
@@ -377,6 +378,33 @@ def dropped(args, fs, torch, ii, jj, ss, m, n):
     log("drop_zeros", "%.4f ms" % ms)
     return {"value": L / (ms * 1e-3) / 1e9, "unit": "Gtriplets/s", "ms": ms,
             "nnz_kept": r.nnz, "stages_ms": stages}
+
+
+def appended(args, fs, torch, ii, jj, ss, m, n):
+    """Delayed assembly: the second half of the triplets added to the
+    assembled first half (the same matrix as the fresh call)."""
+    L = ss.numel()
+    h = L // 2
+    A = fs.sparse(ii[:h], jj[:h], ss[:h], m, n)
+    ws = torch.empty(fs.append_workspace_bytes(A.nnz, L - h, n, ss.dtype),
+                     dtype=torch.uint8, device=ss.device)
+    i2, j2, s2 = ii[h:].contiguous(), jj[h:].contiguous(), ss[h:].contiguous()
+
+    def fn():
+        return fs.sparse_append(A, i2, j2, s2, m, n, ws=ws)
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    stages, _ = stage_profile(fs, torch, fn, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fn()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    log("append", "%.4f ms" % ms)
+    return {"value": (L - h) / (ms * 1e-3) / 1e9, "unit": "Gtriplets/s (new)",
+            "ms": ms, "old_pairs": A.nnz, "new_triplets": L - h,
+            "stages_ms": stages}
 
 
 def copy_bw(fs, torch):

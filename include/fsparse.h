@@ -209,6 +209,45 @@ fsparse_status fsparse_assemble_expand(const int32_t *ii, const int32_t *jj,
                                        hipStream_t stream);
 
 /*
+ * Delayed assembly (Section 2.1 names the case of input that is not all
+ * available at the first call): new triplets added to an assembled matrix.
+ * The result is bit-identical to one fresh assembly of all the triplets,
+ * old ones first: every pair's fold continues from its stored sum, and a
+ * fold that starts from +0.0 never ends at -0.0, so continuing from the
+ * stored sum equals folding all of the pair's contributions in order.
+ *
+ *  jcA, irA, prA  the existing matrix: [nA+1], [nnzA], [nnzA] of type dt, in
+ *                 the format fsparse_assemble writes (rows strictly
+ *                 increasing per column)
+ *  ii, jj, ss     [len] new triplets, as for fsparse_assemble
+ *  m, n           dimensions of the result (at least those of the existing
+ *                 matrix); negative: the largest row index over old and new,
+ *                 and max(nA, largest new column)
+ *  flags, jcS, irS, prS, cap, plan, info: as for fsparse_assemble over the
+ *                 nnzA + len triplets (the outputs may be the input arrays
+ *                 when they are large enough: the old pairs are copied
+ *                 first)
+ *  slot           [nnzA + len] or NULL: the first nnzA entries give where
+ *                 each old pair went, the rest the new triplets' positions
+ *  ws             fsparse_append_workspace_bytes(nnzA, len, n, dt) bytes;
+ *                 a plan covers nnzA + len values (the old sums, then the new
+ *                 values)
+ */
+size_t fsparse_append_workspace_bytes(int64_t nnzA, int64_t len, int64_t n,
+                                      fsparse_dtype dt);
+fsparse_status fsparse_assemble_append(const int32_t *jcA, const int32_t *irA,
+                                       const void *prA, int64_t nnzA,
+                                       int64_t nA, const int32_t *ii,
+                                       const int32_t *jj, const void *ss,
+                                       int64_t len, fsparse_dtype dt,
+                                       int64_t m, int64_t n, unsigned flags,
+                                       int32_t *jcS, int64_t jcS_cap,
+                                       int32_t *irS, void *prS, int64_t cap,
+                                       int32_t *slot, void *ws, size_t ws_bytes,
+                                       fsparse_plan **plan, fsparse_info *info,
+                                       hipStream_t stream);
+
+/*
  * Pattern re-use: the values prS[0..nnz) of the matrix the plan was made
  * for, from new values ss[0..len) on the same (ii, jj) -- the repeated
  * assembly of Section 2.1 ("saving various types of information between

@@ -9,7 +9,9 @@ marshals torch tensors (device memory and the current stream) into it.
 from ._lib import LIB_PATH  # noqa: F401  (raises if the library is not built)
 from .api import (  # noqa: F401
     Assembled, Assembler, Batched, FsparseError, FsparseIndexError,
+    append_workspace_bytes,
     SparseAssemble, assemble, assemble_batched, backward, dims, get_tuning,
-    reassemble, set_tuning, sparse, sparse_expand, stream_copy, timing,
+    reassemble, set_tuning, sparse, sparse_append, sparse_expand, stream_copy,
+    timing,
     to_torch_csc, version, workspace_bytes,
 )

@@ -117,6 +117,13 @@ def workspace_bytes(L_: int, ncols: int, nb: int = 1,
                                          _dt(dtype)))
 
 
+def append_workspace_bytes(nnzA: int, L_: int, ncols: int,
+                           dtype=torch.float64) -> int:
+    """Workspace of ``sparse_append``: nnzA stored pairs, L_ new triplets."""
+    return int(L.fsparse_append_workspace_bytes(int(nnzA), int(L_),
+                                                int(ncols), _dt(dtype)))
+
+
 def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
 
@@ -226,7 +233,7 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
 
 
 def _fresh(call, Ln, m, n, ss, dev, nzmax, atomic, keep_slot, plan, cap, ws,
-           out, name, drop_zeros=False) -> Assembled:
+           out, name, drop_zeros=False, ws_need=None) -> Assembled:
     """Output buffers and the capacity / workspace retry around one fresh
     assembly call ``call(m, n, nzmax, flags, jcS, jcS_cap, irS, prS, cap,
     slot, ws, ws_bytes, plan_out, info, stream)``."""
@@ -235,8 +242,10 @@ def _fresh(call, Ln, m, n, ss, dev, nzmax, atomic, keep_slot, plan, cap, ws,
                          "so no re-use plan can be made")
     flags = (L.ATOMIC if atomic else L.ORDERED) | (
         L.DROP_ZEROS if drop_zeros else 0)
+    if ws_need is None:
+        ws_need = lambda: workspace_bytes(Ln, n, 1, ss.dtype)  # noqa: E731
     if ws is None:
-        ws = _workspace(workspace_bytes(Ln, n, 1, ss.dtype), dev)
+        ws = _workspace(ws_need(), dev)
     slot = None
     if out is not None:
         jcS, irS0, prS0 = out[0], out[1], out[2]
@@ -267,7 +276,7 @@ def _fresh(call, Ln, m, n, ss, dev, nzmax, atomic, keep_slot, plan, cap, ws,
             cap = int(info.nnz)       # retry with the reported size
             continue
         if st == L.E_CAPACITY:
-            need = workspace_bytes(Ln, n, 1, ss.dtype)
+            need = ws_need()
             if ws.numel() < need:     # a given workspace that is too small
                 ws = _workspace(need, dev)
                 continue
@@ -282,6 +291,49 @@ def _fresh(call, Ln, m, n, ss, dev, nzmax, atomic, keep_slot, plan, cap, ws,
 
 
 assemble = sparse
+
+
+def sparse_append(A: "Assembled", ii, jj, ss: torch.Tensor,
+                  m: Optional[int] = None, n: Optional[int] = None, *,
+                  atomic: bool = False, keep_slot: bool = False,
+                  plan: bool = False, cap: Optional[int] = None,
+                  ws: Optional[torch.Tensor] = None,
+                  drop_zeros: bool = False) -> Assembled:
+    """Delayed assembly: ``A`` with the triplets (ii, jj, ss) added.
+
+    Bit-identical to one ``sparse`` call on A's triplets followed by the new
+    ones (Section 2.1's input that arrives over time).  ``m``/``n`` default to
+    A's dimensions grown to the largest new index.  With ``keep_slot`` the
+    slot array has A.nnz + len entries: where each of A's pairs went, then
+    the new triplets' positions.
+    """
+    dev = _device(ss, ii, jj)
+    ss = ss.contiguous()
+    if A.prS.dtype != ss.dtype:
+        raise TypeError("values must have the matrix's type %s" % A.prS.dtype)
+    ii, jj = _dev_i32(ii, dev), _dev_i32(jj, dev)
+    Ln = ss.numel()
+    if ii.numel() != Ln or jj.numel() != Ln:
+        raise ValueError("ii, jj and ss must have the same length")
+    nnzA = int(A.nnz)
+    if m is None or n is None:
+        dm, dn = dims(ii, jj)
+        m = max(A.m, dm) if m is None else m
+        n = max(A.n, dn) if n is None else n
+    jcA = A.jcS.contiguous()
+    irA = A.irS.contiguous()
+    prA = A.prS.contiguous()
+
+    def call(m_, n_, nzmax_, *rest):
+        return L.fsparse_assemble_append(
+            _ptr(jcA), _ptr(irA), _ptr(prA), nnzA, A.n, _ptr(ii), _ptr(jj),
+            _ptr(ss), Ln, _dt(ss.dtype), m_, n_, *rest)
+
+    def need():
+        return append_workspace_bytes(nnzA, Ln, n, ss.dtype)
+    return _fresh(call, nnzA + Ln, int(m), int(n), ss, dev, None, atomic,
+                  keep_slot, plan, cap, ws, None, "fsparse_assemble_append",
+                  drop_zeros, need)
 
 
 def sparse_expand(ii, jj, ss: torch.Tensor, m: Optional[int] = None,

@@ -53,11 +53,11 @@ int kernel_cap(int cap) { return cap <= 1024 ? 1024 : (cap <= 2048 ? 2048 : 4096
 // ---------------------------------------------------------------------------
 enum Stage {
   kDims, kInit, kHist, kScan, kBucket, kChunk, kBatchedJcs, kAtomic,
-  kReuse, kBackward, kCopy, kFill, kColScan, kDrop, kNumStages
+  kReuse, kBackward, kCopy, kFill, kColScan, kDrop, kAppend, kNumStages
 };
 const char* kStageNames[kNumStages] = {
     "dims", "init", "count", "binscan", "scatter", "bin", "batched_jcs",
-    "atomic", "reuse", "backward", "copy", "fill", "colscan", "drop_zeros"};
+    "atomic", "reuse", "backward", "copy", "fill", "colscan", "drop_zeros", "append"};
 
 struct Rec {
   int stage;
@@ -1089,6 +1089,82 @@ fsparse_status fsparse_assemble_expand(const int32_t* ii, const int32_t* jj,
   return assemble_impl(ii, jj, ss, dt, len, m, n, nzmax, flags, jcS, jcS_cap, irS,
                        prS, cap, slot, ws, ws_bytes, plan, info, stream,
                        fsp::kIdxExpand, &ex);
+}
+
+// Delayed assembly: the stored pairs of the existing matrix, then the new
+// triplets, as one triplet list at the head of the workspace.
+static size_t append_head(int64_t Lc, fsparse_dtype dt) {
+  const size_t vb = dt == FSPARSE_F64 ? 8 : 4;
+  return al(4 * (size_t)Lc) * 2 + al(vb * (size_t)Lc);
+}
+
+size_t fsparse_append_workspace_bytes(int64_t nnzA, int64_t len, int64_t n,
+                                      fsparse_dtype dt) {
+  if (nnzA < 0 || len < 0 || n < 0 || check_dt(dt) != FSPARSE_OK) return 0;
+  const size_t w = fsparse_workspace_bytes(nnzA + len, n, 1, dt);
+  return w ? append_head(nnzA + len, dt) + w : 0;
+}
+
+fsparse_status fsparse_assemble_append(const int32_t* jcA, const int32_t* irA,
+                                       const void* prA, int64_t nnzA, int64_t nA,
+                                       const int32_t* ii, const int32_t* jj,
+                                       const void* ss, int64_t len, fsparse_dtype dt,
+                                       int64_t m, int64_t n, unsigned flags,
+                                       int32_t* jcS, int64_t jcS_cap, int32_t* irS,
+                                       void* prS, int64_t cap, int32_t* slot,
+                                       void* ws, size_t ws_bytes,
+                                       fsparse_plan** plan, fsparse_info* info,
+                                       hipStream_t stream) {
+  if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
+  if (nnzA < 0 || len < 0 || nA < 0 || nnzA + len > kMaxI32 || m > kMaxI32 ||
+      n > kMaxI32 || nA > kMaxI32)
+    return FSPARSE_E_ARG;
+  if (flags & ~(unsigned)(FSPARSE_ATOMIC | FSPARSE_DROP_ZEROS)) return FSPARSE_E_ARG;
+  if ((flags & FSPARSE_DROP_ZEROS) && plan) return FSPARSE_E_ARG;
+  if (!jcA || (nnzA > 0 && (!irA || !prA))) return FSPARSE_E_ARG;
+  if (len > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
+  if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS))) return FSPARSE_E_ARG;
+  if (plan) *plan = nullptr;
+  const int64_t Lc = nnzA + len;
+  const size_t head = append_head(Lc, dt);
+  if (ws_bytes < head + 256) return FSPARSE_E_CAPACITY;
+  const size_t vb = dt == FSPARSE_F64 ? 8 : 4;
+  int32_t* ic = static_cast<int32_t*>(ws);
+  int32_t* jc = at<int32_t>(ws, al(4 * (size_t)Lc));
+  void* sc = at<char>(ws, 2 * al(4 * (size_t)Lc));
+  void* ws2 = at<char>(ws, head);
+  const size_t ws2_bytes = ws_bytes - head;
+  // the stored pairs first (their own order), then the new triplets: every
+  // pair's fold continues from its stored sum, which equals folding all of
+  // its contributions in order (a fold from +0.0 never ends at -0.0)
+  if (nnzA > 0) {
+    hipError_t e = launch(kAppend, stream, [&] {
+      if (dt == FSPARSE_F64)
+        hipLaunchKernelGGL(fsp::k_ccs_triplets<double>, dim3(grid_for(nnzA, 256, 4)),
+                           dim3(256), 0, stream, jcA, irA, (const double*)prA, nA,
+                           nnzA, ic, jc, (double*)sc);
+      else
+        hipLaunchKernelGGL(fsp::k_ccs_triplets<float>, dim3(grid_for(nnzA, 256, 4)),
+                           dim3(256), 0, stream, jcA, irA, (const float*)prA, nA,
+                           nnzA, ic, jc, (float*)sc);
+    });
+    if (e != hipSuccess) return FSPARSE_E_HIP;
+  }
+  if (len > 0) {
+    HIPCHK(hipMemcpyAsync(ic + nnzA, ii, 4 * (size_t)len, hipMemcpyDeviceToDevice, stream));
+    HIPCHK(hipMemcpyAsync(jc + nnzA, jj, 4 * (size_t)len, hipMemcpyDeviceToDevice, stream));
+    HIPCHK(hipMemcpyAsync(static_cast<char*>(sc) + vb * nnzA, ss, vb * (size_t)len,
+                          hipMemcpyDeviceToDevice, stream));
+  }
+  if (m < 0 || n < 0) {
+    int64_t dm = 0, dn = 0;
+    fsparse_status st = dims_impl(ic, jc, Lc, &dm, &dn, ws2, ws2_bytes, stream, false);
+    if (st != FSPARSE_OK) return st;
+    if (m < 0) m = dm;
+    if (n < 0) n = std::max(dn, nA);
+  }
+  return assemble_impl(ic, jc, sc, dt, Lc, m, n, 0, flags, jcS, jcS_cap, irS, prS, cap,
+                       slot, ws2, ws2_bytes, plan, info, stream, fsp::kIdxI32, nullptr);
 }
 
 fsparse_status fsparse_assemble_reuse(fsparse_plan* plan, const void* ss,

@@ -2320,6 +2320,31 @@ __global__ void k_backward(const int32_t* __restrict__ slot,
 }
 
 // ---------------------------------------------------------------------------
+// delayed assembly: an assembled matrix (jcA, irA, prA) as its own triplets,
+// one per stored pair in storage order, ahead of the new triplets.  Column
+// of entry e: the last c with jcA[c] <= e (binary search over jcA[0..n]).
+// ---------------------------------------------------------------------------
+template <typename VT>
+__global__ void k_ccs_triplets(const int32_t* __restrict__ jcA,
+                               const int32_t* __restrict__ irA,
+                               const VT* __restrict__ prA, int64_t n, int64_t nnzA,
+                               int32_t* __restrict__ ii, int32_t* __restrict__ jj,
+                               VT* __restrict__ ss) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; e < nnzA; e += stride) {
+    int64_t lo = 0, hi = n;  // jcA[lo] <= e < jcA[hi]
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (jcA[mid] <= e) lo = mid; else hi = mid;
+    }
+    ii[e] = irA[e] + 1;
+    jj[e] = (int32_t)lo + 1;
+    ss[e] = prA[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // drop zeros: remove the pairs whose sum is zero (+0 or -0), as a Matlab
 // sparse matrix stores no zeros.  keep[j] = prS[j] != 0, its exclusive scan
 // gives every kept entry its new place, the kept entries go out of place to

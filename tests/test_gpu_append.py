@@ -1,0 +1,106 @@
+"""Delayed assembly on the GPU: chained appends against the oracle.
+
+Appending triplets to an assembled matrix must give, bit for bit, the
+oracle's assembly of all the triplets at once (and the oracle's own chained
+append, slots included), in every bin mode and value type, with growing
+dimensions, empty parts and re-assembly from a plan.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from gpu_util import assert_same, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1406_1066_amd as fs
+    fs.set_tuning(reset=True)
+    yield fs
+    fs.set_tuning(reset=True)
+
+
+def chain(fs, ii, jj, ss, cuts, m=None, n=None):
+    parts = np.split(np.arange(ii.size), cuts)
+    p = parts[0]
+    ref = oracle.assemble(ii[p], jj[p], ss[p], m, n)
+    res = fs.sparse(to_dev(ii[p]), to_dev(jj[p]), to_dev(ss[p]), m, n,
+                    keep_slot=True)
+    assert_same(res, ref)
+    for p in parts[1:]:
+        ref = oracle.append(ref, ii[p], jj[p], ss[p], m, n)
+        res = fs.sparse_append(res, to_dev(ii[p]), to_dev(jj[p]),
+                               to_dev(ss[p]), m, n, keep_slot=True)
+        assert (res.m, res.n) == (ref.m, ref.n)
+        assert_same(res, ref)
+    return res, ref
+
+
+@pytest.mark.parametrize("mode", ["auto", "dense", "slot", "claim"])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_chained_appends_equal_one_assembly(fs, mode, dtype):
+    fs.set_tuning(bin_mode=mode)
+    try:
+        rng = np.random.default_rng(70)
+        L, m, n = 400_000, 3000, 2000
+        ii = rng.integers(1, m + 1, L).astype(np.int32)
+        jj = rng.integers(1, n + 1, L).astype(np.int32)
+        ss = (rng.standard_normal(L) * 10.0 ** rng.integers(-6, 7, L)).astype(dtype)
+        ss[rng.random(L) < 0.03] = -0.0
+        res, _ = chain(fs, ii, jj, ss, [50_000, 51_000, 300_000], m, n)
+        one = oracle.assemble(ii, jj, ss, m, n)
+        assert res.prS.cpu().numpy().tobytes() == one.prS.tobytes()
+        np.testing.assert_array_equal(res.irS.cpu().numpy(), one.irS)
+    finally:
+        fs.set_tuning(reset=True)
+
+
+def test_mesh_in_element_chunks_and_growing_dims(fs):
+    t = W.fem3d(12, 0.15, seed=71)
+    per = t.per_elem
+    ne = t.L // per
+    cuts = [per * (ne // 5), per * (ne // 2), per * (ne - 7)]
+    res, _ = chain(fs, t.ii, t.jj, t.ss, cuts)        # default dims grow
+    one = oracle.assemble(t.ii, t.jj, t.ss)
+    assert (res.m, res.n) == (one.m, one.n)
+    assert res.prS.cpu().numpy().tobytes() == one.prS.tobytes()
+
+
+def test_empty_parts_and_small_capacity(fs):
+    fs.set_tuning(chunk_cap=16)
+    try:
+        rng = np.random.default_rng(72)
+        ii = rng.integers(1, 60, 5000).astype(np.int32)
+        jj = rng.integers(1, 8, 5000).astype(np.int32)
+        ss = rng.integers(-3, 4, 5000).astype(np.float64)
+        chain(fs, ii, jj, ss, [0, 0, 2500, 5000, 5000], 60, 8)
+    finally:
+        fs.set_tuning(reset=True)
+
+
+def test_plan_from_append_and_drop_zeros(fs):
+    rng = np.random.default_rng(73)
+    ii = rng.integers(1, 200, 60_000).astype(np.int32)
+    jj = rng.integers(1, 100, 60_000).astype(np.int32)
+    ss = rng.integers(-2, 3, 60_000).astype(np.float64)
+    a = fs.sparse(to_dev(ii[:20_000]), to_dev(jj[:20_000]),
+                  to_dev(ss[:20_000]), 200, 100)
+    ra = oracle.assemble(ii[:20_000], jj[:20_000], ss[:20_000], 200, 100)
+    res = fs.sparse_append(a, to_dev(ii[20_000:]), to_dev(jj[20_000:]),
+                           to_dev(ss[20_000:]), plan=True, keep_slot=True)
+    ref = oracle.append(ra, ii[20_000:], jj[20_000:], ss[20_000:])
+    assert_same(res, ref)
+    # the plan covers the old sums, then the new values
+    v = np.concatenate([ra.prS * 2.0, ss[20_000:] * 2.0])
+    pr2 = fs.reassemble(res, to_dev(v)).cpu().numpy()[:ref.nnz]
+    assert pr2.tobytes() == (ref.prS * 2.0).tobytes()
+    # Matlab's convention on the appended result
+    d = fs.sparse_append(a, to_dev(ii[20_000:]), to_dev(jj[20_000:]),
+                         to_dev(ss[20_000:]), keep_slot=True, drop_zeros=True)
+    assert_same(d, oracle.drop_zeros(ref))
