@@ -248,12 +248,17 @@ void set_width(Geom& g, int64_t L, int64_t N, int cap, int fill) {
   g.B = std::max<int64_t>(1, (N + w - 1) / w);
 }
 
-Geom make_geom(int64_t L, int64_t N, int cap, int force_mode, int blk) {
+// `refit`: the geometry after fixed-capacity places overflowed.  That points
+// to columns of uneven density, so the counted placement then uses bins of
+// half the average fill, which keeps more of the dense bins within the LDS.
+Geom make_geom(int64_t L, int64_t N, int cap, int force_mode, int blk,
+               bool refit = false) {
   Geom g{};
   // an average bin fills kBinFill percent of the LDS capacity: a bin's cost
   // is mostly latency, so fuller bins mean fewer of them; a bin that still
   // overflows takes the slow path
-  set_width(g, L, N, cap, kBinFill);
+  set_width(g, L, N, cap, refit ? kBinFill / 2 : kBinFill);
+  if (refit) force_mode = 1 + kClaim;
   // few bins: a tiles x bins count matrix gives the tile offsets (dense);
   // many bins: every bin gets a fixed place of `cap` triplets so one pass
   // (claims per tile and bin) places the triplets, and an overflowing bin
@@ -306,9 +311,10 @@ struct Layout {
   int64_t nscan;
 };
 
-Layout make_layout(int64_t L, int64_t N, int nb, int esize, const Tuning& tu) {
+Layout make_layout(int64_t L, int64_t N, int nb, int esize, const Tuning& tu,
+                   bool refit = false) {
   Layout o{};
-  o.g = make_geom(L, N, tu.cap, tu.bmode, tu.sblock);
+  o.g = make_geom(L, N, tu.cap, tu.bmode, tu.sblock, refit);
   const int64_t B = o.g.B;
   // look-back words: scan tiles of the bin scan, or 64-bin groups of the
   // dense column scan
@@ -325,10 +331,13 @@ Layout make_layout(int64_t L, int64_t N, int nb, int esize, const Tuning& tu) {
   o.cntmat = p;      p = al(p + (o.g.dense ? 4 * (size_t)o.g.T * B : 0));
   o.tilebad = p;     p = al(p + (o.g.dense ? 4 * (size_t)o.g.T : 0));
   const int64_t nb_places = std::max(L, o.g.nslot);
-  // one spare place past the end of the bucket (and of bcol)
-  o.bcol = p;        p = al(p + 4 * (size_t)(nb_places + 1));
+  // spare places past the end of the bucket (and of bcol) for the stores of
+  // unplaced triplets: one for the dense scatter, kSpare (one per lane of a
+  // wave) for the claim scatter, where a full fixed-capacity bin can send
+  // many triplets there
+  o.bcol = p;        p = al(p + 4 * (size_t)(nb_places + fsp::kSpare));
   o.colptr = p;      p = al(p + 4 * (size_t)(N + 1));
-  o.bucket = p;      p = al(p + (size_t)esize * (nb_places + 1));
+  o.bucket = p;      p = al(p + (size_t)esize * (nb_places + fsp::kSpare));
   o.tmp = p;         p = al(p + (size_t)esize * L);
   o.perm = p;        p = al(p + 4 * (size_t)L);
   o.seg = p;         p = al(p + 4 * (size_t)(L + 1));
@@ -784,7 +793,10 @@ const char* fsparse_status_string(int s) {
 size_t fsparse_workspace_bytes(int64_t len, int64_t ncols, int32_t nb,
                                fsparse_dtype dt) {
   if (len < 0 || ncols < 0 || nb < 1 || check_dt(dt) != FSPARSE_OK) return 0;
-  return make_layout(len, ncols, nb, esize_of(dt), tuning()).total;
+  // room for the geometry of a refit after fixed-capacity places overflow
+  const Tuning tu = tuning();
+  return std::max(make_layout(len, ncols, nb, esize_of(dt), tu).total,
+                  make_layout(len, ncols, nb, esize_of(dt), tu, true).total);
 }
 
 // Default dimensions; with f64, ii and jj point to doubles (an index that is
@@ -859,7 +871,7 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
   }
   if (jcS_cap < n + 1) return FSPARSE_E_CAPACITY;
   const Tuning tu = tuning();
-  const Layout lo = make_layout(len, n, 1, esize_of(dt), tu);
+  Layout lo = make_layout(len, n, 1, esize_of(dt), tu);
   if (ws_bytes < lo.total) return FSPARSE_E_CAPACITY;
   Ctrl* ctrl = at<Ctrl>(ws, lo.ctrl);
   const bool keep = plan != nullptr;
@@ -896,9 +908,12 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
       if (keep && launch_reuse_tiles(ws, lo, len, stream) != hipSuccess) return FSPARSE_E_HIP;
       // the bin kernel's last block has written err and nnz into h
       HIPCHK(hipStreamSynchronize(stream));
-      // a full fixed-capacity bin: count first and redo
+      // a full fixed-capacity bin: count first, in narrower bins, and redo
       if ((h->err & fsp::kErrSlot) && mode == kSlot) {
-        mode = kClaim;
+        lo = make_layout(len, n, 1, esize_of(dt), tu, true);
+        if (ws_bytes < lo.total) return FSPARSE_E_CAPACITY;
+        slot_used = slot ? slot : (keep ? at<int32_t>(ws, lo.islot) : nullptr);
+        mode = lo.g.mode;
         continue;
       }
       break;
@@ -1323,7 +1338,29 @@ fsparse_status fsparse_assemble_batched(
                             hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     if ((reinterpret_cast<const Ctrl*>(h)->err & fsp::kErrSlot) && mode == kSlot) {
-      mode = kClaim;  // a full fixed-capacity bin: count first and redo
+      // a full fixed-capacity bin: count first, in narrower bins, and redo
+      const int64_t mmax = lo.mmax;
+      Layout l2 = make_layout(L, N, nb, esize_of(dt), tu, true);
+      if (ws_bytes < l2.total) return FSPARSE_E_CAPACITY;
+      // the batch tables sit at the same offsets only if the bin regions
+      // kept their size: copy them again
+      l2.mmax = mmax;
+      lo = l2;
+      HIPCHK(hipMemcpyAsync(at<int64_t>(ws, lo.b_trip), trip_off, 8 * (size_t)(nb + 1),
+                            hipMemcpyHostToDevice, stream));
+      HIPCHK(hipMemcpyAsync(at<int64_t>(ws, lo.b_col), col.data(), 8 * (size_t)(nb + 1),
+                            hipMemcpyHostToDevice, stream));
+      HIPCHK(hipMemcpyAsync(at<int32_t>(ws, lo.b_m), m32.data(), 4 * (size_t)nb,
+                            hipMemcpyHostToDevice, stream));
+      HIPCHK(hipMemcpyAsync(at<int32_t>(ws, lo.b_n), n32.data(), 4 * (size_t)nb,
+                            hipMemcpyHostToDevice, stream));
+      bd = BatchDesc{at<int64_t>(ws, lo.b_trip), at<int64_t>(ws, lo.b_col),
+                     at<int32_t>(ws, lo.b_m), at<int32_t>(ws, lo.b_n), nb};
+      slot_used = slot ? slot : (keep ? at<int32_t>(ws, lo.islot) : nullptr);
+      jcg = nb > 1 ? at<int32_t>(ws, lo.jcg) : jcS;
+      dnnz = at<int64_t>(ws, lo.nnzoff);
+      ctrl = at<Ctrl>(ws, lo.ctrl);
+      mode = lo.g.mode;
       continue;
     }
     break;
@@ -1383,7 +1420,9 @@ fsparse_status fsparse_dims_batched(int32_t nb, const int64_t* trip_off,
     n[b] = -1;
   }
   if (L > 0) {
-    fsparse_status st = batched_dims(nb, trip_off, ii, jj, L, FSPARSE_F64,
+    // no values here: the fp32 layout, the smaller one, fits any workspace
+    // sized for nb matrices
+    fsparse_status st = batched_dims(nb, trip_off, ii, jj, L, FSPARSE_F32,
                                      tuning(), ws, ws_bytes, m, n, stream);
     if (st != FSPARSE_OK) return st;
   }

@@ -627,6 +627,9 @@ __device__ __forceinline__ T ld_off32(const T* __restrict__ p, uint32_t x) {
 // triplets whose loads one thread keeps in flight: dense count, dense
 // scatter, claim scatter
 constexpr int kDenseU = 8;
+// spare bucket places past the last one: the claim scatter's unplaced
+// triplets go to place trash + (lane % kSpare)
+constexpr int kSpare = 64;
 constexpr int kDenseSU = 8;
 constexpr int kScatterU = 4;
 
@@ -960,12 +963,19 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
   extern __shared__ uint32_t hist[];
   __shared__ int sB;
   __shared__ int32_t sLo, sHi;
+  __shared__ bool sStop;
   const int64_t t0 = (int64_t)blockIdx.x * NT * IPT;
   int32_t bn[IPT], cj[IPT], lo, hi;
   bool bad = false;
   tile_bins<BATCHED, SRC, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, cj, lo, hi, bad, ex);
+  // (block_minmax ends with a barrier after thread 0's reads below)
+  if (slotcap > 0 && threadIdx.x == 0)
+    sStop = (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+             kErrSlot) != 0;
   block_minmax<NT>(lo, hi, &sLo, &sHi);
-  if (hi < lo) return;
+  // a fixed-capacity bin is full: the call is redone with counts, so the
+  // tiles that start later have nothing to place
+  if (hi < lo || (slotcap > 0 && sStop)) return;
   const int width = hi - lo + 1;
   const bool narrow = width <= WMAX;
   uint32_t rk[IPT];
@@ -1013,7 +1023,7 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
     for (int u = 0; u < kScatterU; ++u) {
       const int j = j0 + u;
       const int64_t e = t0 + (int64_t)j * NT + threadIdx.x;
-      pos[u] = trash;
+      pos[u] = trash + (threadIdx.x & (kSpare - 1));
       if (bn[j] >= 0) {
         bool ok;
         int32_t mb;

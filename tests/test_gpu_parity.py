@@ -256,3 +256,20 @@ def test_forced_modes_on_dense_geometry(fs, mode):
         check(fs, t.ii, t.jj, t.ss, t.m, t.n)
     finally:
         fs.set_tuning(reset=True)
+
+
+def test_uneven_column_density_refit(fs, cap):
+    # the second half of the columns is ten times denser than the first:
+    # fixed-capacity bins sized for the average density overflow in the
+    # dense half, and the call redoes the placement counted, in bins of half
+    # the average fill
+    cap(64)
+    rng = np.random.default_rng(20)
+    n, m = 100_000, 5000
+    jj = np.concatenate([rng.integers(1, n // 2 + 1, 100_000),
+                         rng.integers(n // 2 + 1, n + 1, 1_000_000)])
+    p = rng.permutation(jj.size)
+    jj = jj[p].astype(np.int32)
+    ii = rng.integers(1, m + 1, jj.size).astype(np.int32)
+    ss = rng.standard_normal(jj.size)
+    check(fs, ii, jj, ss, m, n)
