@@ -9,7 +9,8 @@ one thread); ``brute`` holds an independent pure-Python dense accumulation
 used to pin the C oracle on tiny inputs.  ``backward`` and ``reassemble``
 are the definitions of the derivative of the assembled values with respect
 to the triplet values and of re-assembly with new values; ``expand`` writes
-out the triplets of an index-expanded input.
+out the triplets of an index-expanded input; ``assemble_complex`` sums
+complex values (split real and imaginary arrays) on the same pattern.
 """
 from __future__ import annotations
 
@@ -210,6 +211,64 @@ def drop_zeros(res: Result) -> Result:
         if res.slot.size else res.slot.copy()
     return Result(jcS, res.irS[keep].copy(), res.prS[keep].copy(), slot,
                   res.m, res.n)
+
+
+@dataclass
+class ComplexResult:
+    jcS: np.ndarray      # int32 [n+1]
+    irS: np.ndarray      # int32 [nnz]
+    prS: np.ndarray      # real parts [nnz]
+    piS: np.ndarray      # imaginary parts [nnz]
+    slot: np.ndarray     # int32 [len]
+    m: int
+    n: int
+
+    @property
+    def nnz(self) -> int:
+        return int(self.jcS[-1])
+
+
+def assemble_complex(ii, jj, sr, si, m: Optional[int] = None,
+                     n: Optional[int] = None) -> ComplexResult:
+    """S = sparse(ii, jj, sr + i*si, m, n) for complex values.
+
+    Matlab's compatibility (Section 1) covers complex matrices, which its
+    classic external interface stores as two arrays of real and imaginary
+    parts beside one pattern (the paper's sr and prS are the real array).
+    The pattern and slot do not depend on the values, so they are those of
+    the real assembly; every pair's value is its complex triplets summed in
+    increasing k from +0 (Section 2.2, eq. (2.3), with complex addition,
+    which rounds the real and imaginary sums separately).
+    """
+    sr = np.ascontiguousarray(sr)
+    if sr.dtype not in (np.float64, np.float32):
+        sr = sr.astype(np.float64)
+    si = np.ascontiguousarray(si, dtype=sr.dtype)
+    assert si.shape == sr.shape
+    base = assemble(ii, jj, sr, m, n)
+    ct = np.complex128 if sr.dtype == np.float64 else np.complex64
+    z = np.empty(sr.shape[0], dtype=ct)
+    z.real = sr
+    z.imag = si
+    acc = np.zeros(base.nnz, dtype=ct)
+    # unbuffered: repeated slots are added one after another in k order
+    np.add.at(acc, base.slot, z)
+    return ComplexResult(base.jcS, base.irS, acc.real.copy(), acc.imag.copy(),
+                         base.slot, base.m, base.n)
+
+
+def drop_zeros_complex(res: ComplexResult) -> ComplexResult:
+    """Matlab's no-stored-zeros convention for complex values: a pair is
+    removed when both its real and its imaginary sum are zero (either
+    sign); otherwise as for real values."""
+    keep = (res.prS != 0) | (res.piS != 0)
+    before = np.concatenate([[0], np.cumsum(keep)]).astype(np.int64)
+    jcS = before[res.jcS.astype(np.int64)].astype(np.int32)
+    newpos = (before[:-1]).astype(np.int32)
+    slot = np.where(keep[res.slot], newpos[res.slot], -1).astype(np.int32) \
+        if res.slot.size else res.slot.copy()
+    return ComplexResult(jcS, res.irS[keep].copy(), res.prS[keep].copy(),
+                         res.piS[keep].copy(), slot, res.m, res.n)
 
 
 def indices_from_double(v) -> np.ndarray:

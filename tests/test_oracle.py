@@ -525,3 +525,81 @@ def test_append_grows_dimensions_and_maps_old_pairs():
     assert r.jcS.tolist() == [0, 2, 3, 4]
     assert r.irS.tolist() == [0, 4, 1, 0] and r.prS.tolist() == [1, 3, 2, 4]
     assert r.slot.tolist() == [0, 2, 1, 3]     # old pairs, then new triplets
+
+
+# ---------------------------------------------------------------------------
+# complex values: split real and imaginary arrays on one pattern
+# ---------------------------------------------------------------------------
+def _dense_complex(ii, jj, sr, si, m, n, f32):
+    # Python complex (two doubles) or numpy complex64 scalars, added into a
+    # dense table in k order: no slot map, no sorting, no numpy ufunc.at
+    ct = np.complex64 if f32 else complex
+    D = [[ct(0) for _ in range(n)] for _ in range(m)]
+    hit = [[False] * n for _ in range(m)]
+    for k in range(len(ii)):
+        r, c = int(ii[k]) - 1, int(jj[k]) - 1
+        z = ct(complex(float(sr[k]), float(si[k])))
+        D[r][c] = ct(D[r][c] + z)
+        hit[r][c] = True
+    cells = [(r, c) for c in range(n) for r in range(m) if hit[r][c]]
+    return cells, [D[r][c] for r, c in cells]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("seed", range(4))
+def test_complex_against_dense_brute_force(dtype, seed):
+    rng = np.random.default_rng(600 + seed)
+    m, n, L = 7, 6, 150
+    ii = rng.integers(1, m + 1, L).astype(np.int32)
+    jj = rng.integers(1, n + 1, L).astype(np.int32)
+    sr = (rng.standard_normal(L) * 10.0 ** rng.integers(-6, 7, L)).astype(dtype)
+    si = (rng.standard_normal(L) * 10.0 ** rng.integers(-6, 7, L)).astype(dtype)
+    si[rng.random(L) < 0.1] = -0.0
+    r = oracle.assemble_complex(ii, jj, sr, si, m, n)
+    cells, vals = _dense_complex(ii, jj, sr, si, m, n, dtype == np.float32)
+    assert r.nnz == len(cells)
+    assert r.irS.tolist() == [c[0] for c in cells]
+    assert np.diff(r.jcS).tolist() == [sum(1 for c in cells if c[1] == q)
+                                       for q in range(n)]
+    assert r.prS.dtype == dtype and r.piS.dtype == dtype
+    assert r.prS.tobytes() == np.array([v.real for v in vals], dtype).tobytes()
+    assert r.piS.tobytes() == np.array([v.imag for v in vals], dtype).tobytes()
+
+
+def test_complex_reduces_to_real_parts():
+    # with zero imaginary parts the real parts are the real assembly and the
+    # imaginary sums are +0; swapping the parts swaps the outputs
+    t = W.fem2d(9, 0.2, seed=5)
+    z = np.zeros_like(t.ss)
+    a = oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
+    c = oracle.assemble_complex(t.ii, t.jj, t.ss, z, t.m, t.n)
+    assert np.array_equal(c.jcS, a.jcS) and np.array_equal(c.irS, a.irS)
+    assert np.array_equal(c.slot, a.slot)
+    assert c.prS.tobytes() == a.prS.tobytes()
+    assert c.piS.tobytes() == np.zeros(a.nnz).tobytes()
+    d = oracle.assemble_complex(t.ii, t.jj, z, t.ss, t.m, t.n)
+    assert d.piS.tobytes() == a.prS.tobytes()
+    assert d.prS.tobytes() == np.zeros(a.nnz).tobytes()
+
+
+def test_complex_times_i():
+    # i*(x + iy) = -y + ix: negation is exact, so the sums rotate exactly
+    t = W.uniform(3000, 40, 30, seed=8)
+    y = np.random.default_rng(9).standard_normal(t.L)
+    a = oracle.assemble_complex(t.ii, t.jj, t.ss, y, t.m, t.n)
+    b = oracle.assemble_complex(t.ii, t.jj, -y, t.ss, t.m, t.n)
+    assert np.array_equal(b.prS, -a.piS) and np.array_equal(b.piS, a.prS)
+
+
+def test_complex_drop_zeros_hand_example():
+    # (1,1): (1+2i) + (-1+0i) = 0+2i -> kept; (2,1): (0-0i) alone -> dropped;
+    # (1,2): (3+1i) + (0-1i) = 3+0i -> kept; (2,2): (1+1i) + (-1-1i) -> dropped
+    ii = i32([1, 2, 1, 1, 1, 2, 2])
+    jj = i32([1, 1, 2, 1, 2, 2, 2])
+    sr = np.array([1.0, 0.0, 3.0, -1.0, 0.0, 1.0, -1.0])
+    si = np.array([2.0, -0.0, 1.0, 0.0, -1.0, 1.0, -1.0])
+    r = oracle.drop_zeros_complex(oracle.assemble_complex(ii, jj, sr, si, 2, 2))
+    assert r.jcS.tolist() == [0, 1, 2]
+    assert r.irS.tolist() == [0, 0]
+    assert r.prS.tolist() == [0.0, 3.0] and r.piS.tolist() == [2.0, 0.0]
+    assert r.slot.tolist() == [0, -1, 1, 0, 1, -1, -1]
