@@ -241,6 +241,7 @@ def main():
                                                     ss, m, n)
         line["modes"]["drop_zeros"] = dropped(args, fs, torch, ii, jj, ss, m, n)
         line["modes"]["append"] = appended(args, fs, torch, ii, jj, ss, m, n)
+        line["modes"]["complex"] = complexed(args, fs, torch, ii, jj, ss, m, n)
         line["copy_gbps"] = copy_bw(fs, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(t, args.cpu_seconds)
@@ -378,6 +379,33 @@ def dropped(args, fs, torch, ii, jj, ss, m, n):
     log("drop_zeros", "%.4f ms" % ms)
     return {"value": L / (ms * 1e-3) / 1e9, "unit": "Gtriplets/s", "ms": ms,
             "nnz_kept": r.nnz, "stages_ms": stages}
+
+
+def complexed(args, fs, torch, ii, jj, ss, m, n):
+    """Complex values, split real and imaginary arrays: the fresh pass on the
+    real parts with the sorted order kept, then the ordered fold of the
+    imaginary parts along it."""
+    L = ss.numel()
+    g = torch.Generator(device=ss.device)
+    g.manual_seed(1406)
+    si = torch.randn(L, dtype=ss.dtype, device=ss.device, generator=g)
+    ws = torch.empty(fs.workspace_bytes(L, n, 1, ss.dtype), dtype=torch.uint8,
+                     device=ss.device)
+
+    def fn():
+        return fs.sparse_complex(ii, jj, ss, si, m, n, ws=ws)
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    stages, _ = stage_profile(fs, torch, fn, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = fn()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    log("complex", "%.4f ms" % ms)
+    return {"value": L / (ms * 1e-3) / 1e9, "unit": "Gtriplets/s (complex)",
+            "ms": ms, "nnz": r.nnz, "stages_ms": stages}
 
 
 def appended(args, fs, torch, ii, jj, ss, m, n):

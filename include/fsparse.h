@@ -140,6 +140,34 @@ fsparse_status fsparse_assemble(const int32_t *ii, const int32_t *jj,
                                 hipStream_t stream);
 
 /*
+ * Complex values (Matlab compatibility, Section 1).  Matlab's classic
+ * external interface holds a complex sparse matrix as one pattern and two
+ * value arrays, real and imaginary parts; the paper's sr and prS are the
+ * real one.  Complex addition rounds the real and imaginary sums
+ * separately, so both parts follow eq. (2.3) on the same pattern: every
+ * pair's parts are summed from +0 in increasing k.
+ *  sr, si   [len] device, real and imaginary parts, both of dtype dt.
+ *  prS, piS [cap] device out, the real and imaginary sums.
+ * Every other argument as for fsparse_assemble.  The imaginary parts are
+ * folded along the sorted order the real pass leaves in ws (so ws must be
+ * fsparse_workspace_bytes(len, n, 1, dt), as always).  FSPARSE_ATOMIC sums
+ * both parts with atomics through the slot map.  FSPARSE_DROP_ZEROS removes
+ * a pair only when both sums are zero, and compacts piS with prS (no plan).
+ * A plan, when asked for, re-assembles one part per fsparse_assemble_reuse
+ * call.  Outputs are ordered on the stream; the call waits once, for nnz.
+ */
+fsparse_status fsparse_assemble_complex(const int32_t *ii, const int32_t *jj,
+                                        const void *sr, const void *si,
+                                        fsparse_dtype dt, int64_t len,
+                                        int64_t m, int64_t n, int64_t nzmax,
+                                        unsigned flags, int32_t *jcS,
+                                        int64_t jcS_cap, int32_t *irS,
+                                        void *prS, void *piS, int64_t cap,
+                                        int32_t *slot, void *ws, size_t ws_bytes,
+                                        fsparse_plan **plan, fsparse_info *info,
+                                        hipStream_t stream);
+
+/*
  * Double-valued indices (Matlab's default array type; the pre-processing of
  * Section 2.2 and its appendix listings, which check and convert them).
  * The same as fsparse_assemble / fsparse_dims with ii and jj given as

@@ -11,7 +11,8 @@ from .api import (  # noqa: F401
     Assembled, Assembler, Batched, FsparseError, FsparseIndexError,
     append_workspace_bytes,
     SparseAssemble, assemble, assemble_batched, backward, dims, get_tuning,
-    reassemble, set_tuning, sparse, sparse_append, sparse_expand, stream_copy,
+    reassemble, set_tuning, sparse, sparse_append, sparse_complex, sparse_expand,
+    stream_copy,
     timing,
     to_torch_csc, version, workspace_bytes,
 )

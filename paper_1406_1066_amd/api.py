@@ -161,6 +161,7 @@ class Assembled:
     slot: Optional[torch.Tensor] = None
     plan: Optional["_Plan"] = None
     ws: Optional[torch.Tensor] = field(default=None, repr=False)
+    piS: Optional[torch.Tensor] = None     # imaginary sums (complex values)
 
     def to_dense(self) -> torch.Tensor:
         return to_torch_csc(self).to_dense()
@@ -291,6 +292,52 @@ def _fresh(call, Ln, m, n, ss, dev, nzmax, atomic, keep_slot, plan, cap, ws,
 
 
 assemble = sparse
+
+
+def sparse_complex(ii, jj, sr: torch.Tensor, si: torch.Tensor,
+                   m: Optional[int] = None, n: Optional[int] = None,
+                   nzmax: Optional[int] = None, *, atomic: bool = False,
+                   keep_slot: bool = False, plan: bool = False,
+                   cap: Optional[int] = None,
+                   ws: Optional[torch.Tensor] = None,
+                   drop_zeros: bool = False) -> Assembled:
+    """S = sparse(ii, jj, sr + 1i*si, m, n, nzmax) for complex values.
+
+    Real and imaginary parts come as two float64 (or two float32) arrays,
+    the split storage of Matlab's external interface; the result carries
+    ``prS`` and ``piS`` on one pattern.  Both parts are summed in increasing
+    k from +0.  ``drop_zeros`` removes a pair only when both sums are zero.
+    A plan re-assembles one part per ``reassemble`` call.  Integer indices.
+    """
+    dev = _device(sr, ii, jj)
+    sr = sr.contiguous()
+    si = si.contiguous()
+    if si.dtype != sr.dtype or si.shape != sr.shape or si.device != sr.device:
+        raise ValueError("sr and si must match in dtype, shape and device")
+    if _is_float_index(ii) or _is_float_index(jj):
+        raise TypeError("complex values take integer index arrays")
+    ii, jj = _dev_i32(ii, dev), _dev_i32(jj, dev)
+    Ln = sr.numel()
+    if ii.numel() != Ln or jj.numel() != Ln:
+        raise ValueError("ii, jj, sr and si must have the same length")
+    if m is None or n is None:
+        dm, dn = dims(ii, jj)
+        m = dm if m is None else m
+        n = dn if n is None else n
+    held = {}
+
+    def call(m_, n_, nzmax_, flags, jcS, jcS_cap, irS, prS, cap_, *rest):
+        pi = held.get("piS")
+        if pi is None or pi.numel() < max(cap_, 1):
+            pi = held["piS"] = torch.empty(max(cap_, 1), dtype=sr.dtype,
+                                           device=dev)
+        return L.fsparse_assemble_complex(
+            _ptr(ii), _ptr(jj), _ptr(sr), _ptr(si), _dt(sr.dtype), Ln, m_, n_,
+            nzmax_, flags, jcS, jcS_cap, irS, prS, _ptr(pi), cap_, *rest)
+    res = _fresh(call, Ln, int(m), int(n), sr, dev, nzmax, atomic, keep_slot,
+                 plan, cap, ws, None, "fsparse_assemble_complex", drop_zeros)
+    res.piS = held["piS"][:res.nnz]
+    return res
 
 
 def sparse_append(A: "Assembled", ii, jj, ss: torch.Tensor,

@@ -481,11 +481,12 @@ fsparse_status plan_reuse_atomic(fsparse_plan* pl, const void* ss, void* prS,
 }
 
 // Removes the zero sums from the nnz pairs in place (irS, prS, jcS, and
-// slot when given); the kept count lands in h->kept once the stream is done.
+// slot when given; with piS, complex sums zero in both parts, and piS is
+// compacted too); the kept count lands in h->kept once the stream is done.
 template <typename VT>
 hipError_t drop_zeros(void* ws, const Layout& lo, int64_t nnz, int64_t n, int64_t L,
                       int32_t* jcS, int32_t* irS, VT* prS, int32_t* slot,
-                      Ctrl* h, hipStream_t stream) {
+                      Ctrl* h, hipStream_t stream, VT* piS = nullptr) {
   uint32_t* keep = at<uint32_t>(ws, lo.perm);          // nnz words
   int32_t* excl = at<int32_t>(ws, lo.seg);             // nnz + 1 words
   int32_t* ir2 = at<int32_t>(ws, lo.tmp);              // scratch: nnz rows,
@@ -500,7 +501,7 @@ hipError_t drop_zeros(void* ws, const Layout& lo, int64_t nnz, int64_t n, int64_
     hipLaunchKernelGGL(fsp::k_zero, dim3(grid_for(zw, 256, 4)), dim3(256), 0, stream,
                        ticket, zw);
     hipLaunchKernelGGL(fsp::k_drop_flags<VT>, dim3(grid_for(nnz, 256, 4)), dim3(256), 0,
-                       stream, (const VT*)prS, nnz, keep);
+                       stream, (const VT*)prS, (const VT*)piS, nnz, keep);
     hipLaunchKernelGGL((fsp::k_scan_excl<kScanNT, kScanIPT>), dim3((unsigned)tiles),
                        dim3(kScanNT), 0, stream, (const uint32_t*)keep, (int32_t)nnz,
                        excl, status, ticket, UINT32_MAX, (uint32_t*)nullptr,
@@ -512,6 +513,12 @@ hipError_t drop_zeros(void* ws, const Layout& lo, int64_t nnz, int64_t n, int64_
                        dim3(grid_for(std::max<int64_t>(std::max(nnz, L), n + 1), 256, 4)),
                        dim3(256), 0, stream, (const int32_t*)excl, nnz,
                        (const int32_t*)ir2, (const VT*)pr2, irS, prS, jcS, n, slot, L);
+    if (piS) {  // pr2 is free again once the finish has read it
+      hipLaunchKernelGGL(fsp::k_drop_move<VT>, dim3(grid_for(nnz, 256, 4)), dim3(256), 0,
+                         stream, (const int32_t*)excl, nnz, (const VT*)piS, pr2);
+      hipLaunchKernelGGL(fsp::k_drop_back<VT>, dim3(grid_for(nnz, 256, 4)), dim3(256), 0,
+                         stream, (const int32_t*)excl, nnz, (const VT*)pr2, piS);
+    }
   });
   if (e != hipSuccess) return e;
   return hipMemcpyAsync(&h->kept, excl + nnz, sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -723,6 +730,23 @@ hipError_t launch_reuse_tiles(void* ws, const Layout& lo, int64_t L,
   });
 }
 
+// The ordered fold of a second value array along the sorted order and runs
+// (perm, seg, rtile) a fresh pass with a kept plan leaves in the workspace.
+hipError_t launch_reuse_direct(void* ws, const Layout& lo, int64_t L, fsparse_dtype dt,
+                               int rblock, const void* ss, void* prS,
+                               hipStream_t stream) {
+  const int blk = rblock <= 256 ? 256 : (rblock <= 512 ? 512 : 1024);
+  const int64_t T = (L + kReuseTP - 1) / kReuseTP;
+  const int32_t* perm = at<int32_t>(ws, lo.perm);
+  const int32_t* seg = at<int32_t>(ws, lo.seg);
+  const int32_t* rtile = at<int32_t>(ws, lo.rtile);
+  void* args[] = {(void*)&perm, (void*)&seg, (void*)&rtile, (void*)&ss, (void*)&prS};
+  const void* fn = dt == FSPARSE_F64 ? reuse_fn<double>(blk) : reuse_fn<float>(blk);
+  return launch(kReuse, stream, [&] {
+    (void)hipLaunchKernel(fn, dim3((unsigned)T), dim3(blk), args, 0, stream);
+  });
+}
+
 fsparse_status check_dt(fsparse_dtype dt) {
   return (dt == FSPARSE_F64 || dt == FSPARSE_F32) ? FSPARSE_OK : FSPARSE_E_ARG;
 }
@@ -862,7 +886,8 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
                              int32_t* slot, void* ws, size_t ws_bytes,
                              fsparse_plan** plan, fsparse_info* info,
                              hipStream_t stream, int src,
-                             const fsp::Expand* ex) {
+                             const fsp::Expand* ex,
+                             const void* si = nullptr, void* piS = nullptr) {
   if (info) {
     info->m = m;
     info->n = n;
@@ -874,7 +899,9 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
   Layout lo = make_layout(len, n, 1, esize_of(dt), tu);
   if (ws_bytes < lo.total) return FSPARSE_E_CAPACITY;
   Ctrl* ctrl = at<Ctrl>(ws, lo.ctrl);
-  const bool keep = plan != nullptr;
+  // complex values: the imaginary parts are folded along the sorted order
+  // that the real parts' pass leaves in the workspace
+  const bool keep = plan != nullptr || si != nullptr;
   int32_t* slot_used = slot ? slot : (keep ? at<int32_t>(ws, lo.islot) : nullptr);
   if (len == 0) {
     hipError_t e = launch(kInit, stream, [&] {
@@ -936,15 +963,27 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
           : launch_atomic_values<float>(slot_used, ss, len, prS, nnz, tu.rblock, stream);
       if (ea != hipSuccess) return FSPARSE_E_HIP;
     }
+    if (si) {
+      hipError_t ei;
+      if (flags & FSPARSE_ATOMIC)
+        ei = dt == FSPARSE_F64
+            ? launch_atomic_values<double>(slot_used, si, len, piS, nnz, tu.rblock, stream)
+            : launch_atomic_values<float>(slot_used, si, len, piS, nnz, tu.rblock, stream);
+      else
+        ei = launch_reuse_direct(ws, lo, len, dt, tu.rblock, si, piS, stream);
+      if (ei != hipSuccess) return FSPARSE_E_HIP;
+    }
     if (flags & FSPARSE_DROP_ZEROS) {
       hipError_t ed = dt == FSPARSE_F64
-          ? drop_zeros<double>(ws, lo, nnz, n, len, jcS, irS, (double*)prS, slot, h, stream)
-          : drop_zeros<float>(ws, lo, nnz, n, len, jcS, irS, (float*)prS, slot, h, stream);
+          ? drop_zeros<double>(ws, lo, nnz, n, len, jcS, irS, (double*)prS, slot, h, stream,
+                               (double*)piS)
+          : drop_zeros<float>(ws, lo, nnz, n, len, jcS, irS, (float*)prS, slot, h, stream,
+                              (float*)piS);
       if (ed != hipSuccess) return FSPARSE_E_HIP;
       HIPCHK(hipStreamSynchronize(stream));
       if (info) info->nnz = h->kept;
     }
-    if (keep) {
+    if (plan) {
       fsparse_plan* pl = new (std::nothrow) fsparse_plan();
       if (!pl) return FSPARSE_E_ARG;
       pl->len = len;
@@ -961,7 +1000,7 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
     }
     return FSPARSE_OK;
   }
-  if (keep) {
+  if (plan) {
     fsparse_plan* pl = new (std::nothrow) fsparse_plan();
     if (!pl) return FSPARSE_E_ARG;
     pl->dt = dt;
@@ -1028,6 +1067,34 @@ fsparse_status fsparse_assemble_f64idx(const double* ii, const double* jj,
                        reinterpret_cast<const int32_t*>(jj), ss, dt, len, m, n,
                        nzmax, flags, jcS, jcS_cap, irS, prS, cap, slot, ws,
                        ws_bytes, plan, info, stream, fsp::kIdxF64, nullptr);
+}
+
+fsparse_status fsparse_assemble_complex(const int32_t* ii, const int32_t* jj,
+                                        const void* sr, const void* si,
+                                        fsparse_dtype dt, int64_t len, int64_t m,
+                                        int64_t n, int64_t nzmax, unsigned flags,
+                                        int32_t* jcS, int64_t jcS_cap, int32_t* irS,
+                                        void* prS, void* piS, int64_t cap,
+                                        int32_t* slot, void* ws, size_t ws_bytes,
+                                        fsparse_plan** plan, fsparse_info* info,
+                                        hipStream_t stream) {
+  if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
+  if (len < 0 || len > kMaxI32 || m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
+  if (flags & ~(unsigned)(FSPARSE_ATOMIC | FSPARSE_DROP_ZEROS)) return FSPARSE_E_ARG;
+  if ((flags & FSPARSE_DROP_ZEROS) && plan) return FSPARSE_E_ARG;
+  if (len > 0 && (!ii || !jj || !sr || !si)) return FSPARSE_E_ARG;
+  if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS || !piS))) return FSPARSE_E_ARG;
+  if (plan) *plan = nullptr;
+  if (m < 0 || n < 0) {
+    int64_t dm = 0, dn = 0;
+    fsparse_status st = fsparse_dims(ii, jj, len, &dm, &dn, ws, ws_bytes, stream);
+    if (st != FSPARSE_OK) return st;
+    if (m < 0) m = dm;
+    if (n < 0) n = dn;
+  }
+  return assemble_impl(ii, jj, sr, dt, len, m, n, nzmax, flags, jcS, jcS_cap, irS,
+                       prS, cap, slot, ws, ws_bytes, plan, info, stream, fsp::kIdxI32,
+                       nullptr, si, piS);
 }
 
 // Exact division by d on [0, 2^31) in the bins' multiply-high form.

@@ -2360,12 +2360,17 @@ __global__ void k_ccs_triplets(const int32_t* __restrict__ jcA,
 // gives every kept entry its new place, the kept entries go out of place to
 // scratch and back, and jcS and the slots are renumbered.
 // ---------------------------------------------------------------------------
+// With complex values (piS given) a pair is zero when both parts are.
 template <typename VT>
-__global__ void k_drop_flags(const VT* __restrict__ prS, int64_t nnz,
-                             uint32_t* __restrict__ keep) {
+__global__ void k_drop_flags(const VT* __restrict__ prS, const VT* __restrict__ piS,
+                             int64_t nnz, uint32_t* __restrict__ keep) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; j < nnz; j += stride) keep[j] = prS[j] != (VT)0 ? 1u : 0u;
+  if (piS)
+    for (; j < nnz; j += stride)
+      keep[j] = (prS[j] != (VT)0 || piS[j] != (VT)0) ? 1u : 0u;
+  else
+    for (; j < nnz; j += stride) keep[j] = prS[j] != (VT)0 ? 1u : 0u;
 }
 
 template <typename VT>
@@ -2382,6 +2387,27 @@ __global__ void k_drop_compact(const int32_t* __restrict__ excl, int64_t nnz,
       pr2[p] = prS[j];
     }
   }
+}
+
+// a second value array (imaginary parts): kept entries to scratch, then back
+template <typename VT>
+__global__ void k_drop_move(const int32_t* __restrict__ excl, int64_t nnz,
+                            const VT* __restrict__ src, VT* __restrict__ dst) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; j < nnz; j += stride) {
+    const int32_t p = excl[j];
+    if (excl[j + 1] > p) dst[p] = src[j];
+  }
+}
+
+template <typename VT>
+__global__ void k_drop_back(const int32_t* __restrict__ excl, int64_t nnz,
+                            const VT* __restrict__ src, VT* __restrict__ dst) {
+  const int64_t kept = excl[nnz];
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; j < kept; j += stride) dst[j] = src[j];
 }
 
 // back into the caller's arrays (excl[nnz] entries), jcS[c] = kept entries
