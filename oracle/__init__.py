@@ -10,7 +10,8 @@ used to pin the C oracle on tiny inputs.  ``backward`` and ``reassemble``
 are the definitions of the derivative of the assembled values with respect
 to the triplet values and of re-assembly with new values; ``expand`` writes
 out the triplets of an index-expanded input; ``assemble_complex`` sums
-complex values (split real and imaginary arrays) on the same pattern.
+complex values (split real and imaginary arrays) on the same pattern;
+``assemble_logical`` stores the pairs that have a true triplet.
 """
 from __future__ import annotations
 
@@ -269,6 +270,23 @@ def drop_zeros_complex(res: ComplexResult) -> ComplexResult:
         if res.slot.size else res.slot.copy()
     return ComplexResult(jcS, res.irS[keep].copy(), res.prS[keep].copy(),
                          res.piS[keep].copy(), slot, res.m, res.n)
+
+
+def assemble_logical(ii, jj, sl, m: Optional[int] = None,
+                     n: Optional[int] = None) -> Result:
+    """S = sparse(ii, jj, sl, m, n) for logical values.
+
+    A Matlab logical matrix holds only true entries, and adding logical
+    values gives true when any of them is true.  So a pair is stored when at
+    least one of its triplets is true, and its value is true (1, uint8);
+    the dimensions come from the indices as for real values.  Written out:
+    the real assembly of the 0/1 indicators (exact counts), then the pairs
+    with a zero count removed; every triplet of a removed pair gets slot -1.
+    """
+    sl = np.asarray(sl).astype(bool)
+    r = drop_zeros(assemble(ii, jj, sl.astype(np.float64), m, n))
+    return Result(r.jcS, r.irS, np.ones(r.irS.size, dtype=np.uint8), r.slot,
+                  r.m, r.n)
 
 
 def indices_from_double(v) -> np.ndarray:

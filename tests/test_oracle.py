@@ -603,3 +603,53 @@ def test_complex_drop_zeros_hand_example():
     assert r.irS.tolist() == [0, 0]
     assert r.prS.tolist() == [0.0, 3.0] and r.piS.tolist() == [2.0, 0.0]
     assert r.slot.tolist() == [0, -1, 1, 0, 1, -1, -1]
+
+
+# ---------------------------------------------------------------------------
+# logical values: a pair is stored when any of its triplets is true
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(6))
+def test_logical_against_dense_or(seed):
+    # a dense boolean table OR-ed in k order, read out column-major; the
+    # slots of every triplet of a stored pair point to it, others are -1
+    rng = np.random.default_rng(700 + seed)
+    m, n, L = 8, 6, 90
+    ii = rng.integers(1, m + 1, L).astype(np.int32)
+    jj = rng.integers(1, n + 1, L).astype(np.int32)
+    sl = rng.random(L) < (0.1 + 0.15 * seed)
+    r = oracle.assemble_logical(ii, jj, sl, m, n)
+    T = [[False] * n for _ in range(m)]
+    for k in range(L):
+        T[ii[k] - 1][jj[k] - 1] = T[ii[k] - 1][jj[k] - 1] or bool(sl[k])
+    cells = [(a, c) for c in range(n) for a in range(m) if T[a][c]]
+    assert r.irS.tolist() == [a for a, _ in cells]
+    assert r.jcS.tolist() == [0] + np.cumsum(
+        [sum(1 for _, c in cells if c == q) for q in range(n)]).tolist()
+    assert r.prS.dtype == np.uint8 and r.prS.tolist() == [1] * len(cells)
+    where = {cell: t for t, cell in enumerate(cells)}
+    assert r.slot.tolist() == [where.get((ii[k] - 1, jj[k] - 1), -1)
+                               for k in range(L)]
+    assert (r.m, r.n) == (m, n)
+
+
+def test_logical_all_true_is_the_real_pattern_and_all_false_is_empty():
+    t = W.fem2d(8, 0.2, seed=11)
+    a = oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
+    b = oracle.assemble_logical(t.ii, t.jj, np.ones(t.L, bool))
+    assert np.array_equal(a.jcS, b.jcS) and np.array_equal(a.irS, b.irS)
+    assert np.array_equal(a.slot, b.slot) and (b.m, b.n) == (a.m, a.n)
+    c = oracle.assemble_logical(t.ii, t.jj, np.zeros(t.L, bool))
+    assert c.nnz == 0 and (c.m, c.n) == (a.m, a.n)
+    assert np.all(c.slot == -1)
+
+
+def test_logical_hand_example():
+    # (1,1): false, true -> stored; (2,1): false only -> not stored;
+    # (1,2): true, true -> stored once
+    ii = i32([1, 2, 1, 1, 1])
+    jj = i32([1, 1, 2, 1, 2])
+    sl = np.array([False, False, True, True, True])
+    r = oracle.assemble_logical(ii, jj, sl)
+    assert (r.m, r.n) == (2, 2)
+    assert r.jcS.tolist() == [0, 1, 2] and r.irS.tolist() == [0, 0]
+    assert r.slot.tolist() == [0, -1, 1, 0, 1]
