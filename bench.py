@@ -242,6 +242,7 @@ def main():
         line["modes"]["drop_zeros"] = dropped(args, fs, torch, ii, jj, ss, m, n)
         line["modes"]["append"] = appended(args, fs, torch, ii, jj, ss, m, n)
         line["modes"]["complex"] = complexed(args, fs, torch, ii, jj, ss, m, n)
+        line["modes"]["logical"] = logical(args, fs, torch, ii, jj, ss, m, n)
         line["copy_gbps"] = copy_bw(fs, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(t, args.cpu_seconds)
@@ -405,6 +406,31 @@ def complexed(args, fs, torch, ii, jj, ss, m, n):
     ms = (time.perf_counter() - t0) / args.steps * 1e3
     log("complex", "%.4f ms" % ms)
     return {"value": L / (ms * 1e-3) / 1e9, "unit": "Gtriplets/s (complex)",
+            "ms": ms, "nnz": r.nnz, "stages_ms": stages}
+
+
+def logical(args, fs, torch, ii, jj, ss, m, n):
+    """Logical values (true where the workload's value is positive, about
+    half the triplets): indicators, the fp32 fold with the pairs that have
+    no true triplet removed, and the true values."""
+    L = ss.numel()
+    sl = ss > 0
+    ws = torch.empty(fs.logical_workspace_bytes(L, n), dtype=torch.uint8,
+                     device=ss.device)
+
+    def fn():
+        return fs.sparse_logical(ii, jj, sl, m, n, ws=ws)
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    stages, _ = stage_profile(fs, torch, fn, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = fn()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    log("logical", "%.4f ms" % ms)
+    return {"value": L / (ms * 1e-3) / 1e9, "unit": "Gtriplets/s (logical)",
             "ms": ms, "nnz": r.nnz, "stages_ms": stages}
 
 

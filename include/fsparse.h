@@ -168,6 +168,33 @@ fsparse_status fsparse_assemble_complex(const int32_t *ii, const int32_t *jj,
                                         hipStream_t stream);
 
 /*
+ * Logical values (Matlab compatibility, Section 1).  A Matlab logical
+ * matrix stores only true entries, and adding logical values gives true
+ * when any of them is true.  So the result holds the pairs that have at
+ * least one true triplet, rows increasing within columns as for real
+ * values, each with value true.
+ *  sl       [len] device bytes, nonzero = true (torch.bool or uint8).
+ *  prS      [cap] device out, uint8: 1 for every stored pair.
+ *  slot     [len] device out or NULL: the stored pair of triplet k, or -1
+ *           when its pair has no true triplet.
+ *  cap      irS/prS capacity; it must hold every distinct pair before the
+ *           pairs without a true triplet are removed (cap = len always
+ *           suffices); E_CAPACITY reports that count in info->nnz.
+ *  ws       at least fsparse_logical_workspace_bytes(len, n) bytes.
+ * Dimensions default to the largest indices, true or not.  info->nnz is the
+ * number of stored pairs.  Waits for the stream twice.  No plan: the
+ * pattern depends on the values.
+ */
+size_t fsparse_logical_workspace_bytes(int64_t len, int64_t ncols);
+fsparse_status fsparse_assemble_logical(const int32_t *ii, const int32_t *jj,
+                                        const uint8_t *sl, int64_t len,
+                                        int64_t m, int64_t n, int64_t nzmax,
+                                        int32_t *jcS, int64_t jcS_cap,
+                                        int32_t *irS, uint8_t *prS, int64_t cap,
+                                        int32_t *slot, void *ws, size_t ws_bytes,
+                                        fsparse_info *info, hipStream_t stream);
+
+/*
  * Double-valued indices (Matlab's default array type; the pre-processing of
  * Section 2.2 and its appendix listings, which check and convert them).
  * The same as fsparse_assemble / fsparse_dims with ii and jj given as

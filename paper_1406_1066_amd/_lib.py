@@ -82,6 +82,12 @@ fsparse_assemble_complex = _sig(
     [_vp, _vp, _vp, _vp, _st, _i64, _i64, _i64, _i64, _u, _vp, _i64, _vp, _vp,
      _vp, _i64, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp),
      ctypes.POINTER(FsparseInfo), _vp])
+fsparse_logical_workspace_bytes = _sig("fsparse_logical_workspace_bytes",
+                                       ctypes.c_size_t, [_i64, _i64])
+fsparse_assemble_logical = _sig(
+    "fsparse_assemble_logical", _st,
+    [_vp, _vp, _vp, _i64, _i64, _i64, _i64, _vp, _i64, _vp, _vp, _i64, _vp,
+     _vp, ctypes.c_size_t, ctypes.POINTER(FsparseInfo), _vp])
 fsparse_append_workspace_bytes = _sig("fsparse_append_workspace_bytes",
                                       ctypes.c_size_t, [_i64, _i64, _i64, _st])
 fsparse_assemble_append = _sig(
@@ -129,7 +135,8 @@ EXPORTS = [
     "fsparse_version", "fsparse_status_string", "fsparse_workspace_bytes",
     "fsparse_dims", "fsparse_assemble", "fsparse_assemble_expand",
     "fsparse_dims_f64idx", "fsparse_assemble_f64idx",
-    "fsparse_assemble_complex",
+    "fsparse_assemble_complex", "fsparse_logical_workspace_bytes",
+    "fsparse_assemble_logical",
     "fsparse_append_workspace_bytes", "fsparse_assemble_append",
     "fsparse_assemble_reuse",
     "fsparse_backward", "fsparse_assemble_batched", "fsparse_dims_batched",

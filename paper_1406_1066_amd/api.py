@@ -340,6 +340,48 @@ def sparse_complex(ii, jj, sr: torch.Tensor, si: torch.Tensor,
     return res
 
 
+def logical_workspace_bytes(L_: int, ncols: int) -> int:
+    return int(L.fsparse_logical_workspace_bytes(int(L_), int(ncols)))
+
+
+def sparse_logical(ii, jj, sl: torch.Tensor, m: Optional[int] = None,
+                   n: Optional[int] = None, nzmax: Optional[int] = None, *,
+                   keep_slot: bool = False, cap: Optional[int] = None,
+                   ws: Optional[torch.Tensor] = None) -> Assembled:
+    """S = sparse(ii, jj, sl, m, n, nzmax) for logical values.
+
+    ``sl`` is a bool (or uint8, nonzero = true) tensor on the GPU.  Only
+    pairs with at least one true triplet are stored, all with value True
+    (``prS`` is a bool tensor); the slot of a triplet whose pair holds no
+    true value is -1.  Integer indices; m, n default to the largest index.
+    """
+    dev = _device(sl, ii, jj)
+    if sl.dtype not in (torch.bool, torch.uint8):
+        raise TypeError("logical values must be a bool or uint8 tensor")
+    sl = sl.contiguous()
+    if _is_float_index(ii) or _is_float_index(jj):
+        raise TypeError("logical values take integer index arrays")
+    ii, jj = _dev_i32(ii, dev), _dev_i32(jj, dev)
+    Ln = sl.numel()
+    if ii.numel() != Ln or jj.numel() != Ln:
+        raise ValueError("ii, jj and sl must have the same length")
+    if m is None or n is None:
+        dm, dn = dims(ii, jj)
+        m = dm if m is None else m
+        n = dn if n is None else n
+    n = int(n)
+
+    def call(m_, n_, nzmax_, flags, jcS, jcS_cap, irS, prS, cap_, slot, ws_,
+             ws_bytes, plan_ref, info, stream):
+        return L.fsparse_assemble_logical(
+            _ptr(ii), _ptr(jj), _ptr(sl), Ln, m_, n_, nzmax_, jcS, jcS_cap,
+            irS, prS, cap_, slot, ws_, ws_bytes, info, stream)
+    out_type = torch.empty(0, dtype=torch.bool, device=dev)
+    return _fresh(call, Ln, int(m), n, out_type, dev, nzmax, False, keep_slot,
+                  False, cap, ws, None, "fsparse_assemble_logical",
+                  ws_need=lambda: logical_workspace_bytes(Ln, n))
+
+
 def sparse_append(A: "Assembled", ii, jj, ss: torch.Tensor,
                   m: Optional[int] = None, n: Optional[int] = None, *,
                   atomic: bool = False, keep_slot: bool = False,

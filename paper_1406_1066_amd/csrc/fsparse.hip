@@ -902,7 +902,10 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
   // complex values: the imaginary parts are folded along the sorted order
   // that the real parts' pass leaves in the workspace
   const bool keep = plan != nullptr || si != nullptr;
-  int32_t* slot_used = slot ? slot : (keep ? at<int32_t>(ws, lo.islot) : nullptr);
+  // the internal slot map serves a plan's order-free re-use and the atomic
+  // sums; the ordered fold of imaginary parts reads only the sorted order
+  const bool islot = plan != nullptr || (si != nullptr && (flags & FSPARSE_ATOMIC));
+  int32_t* slot_used = slot ? slot : (islot ? at<int32_t>(ws, lo.islot) : nullptr);
   if (len == 0) {
     hipError_t e = launch(kInit, stream, [&] {
       hipLaunchKernelGGL(fsp::k_zero, dim3(grid_for(n + 1, 256, 4)), dim3(256), 0,
@@ -939,7 +942,7 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
       if ((h->err & fsp::kErrSlot) && mode == kSlot) {
         lo = make_layout(len, n, 1, esize_of(dt), tu, true);
         if (ws_bytes < lo.total) return FSPARSE_E_CAPACITY;
-        slot_used = slot ? slot : (keep ? at<int32_t>(ws, lo.islot) : nullptr);
+        slot_used = slot ? slot : (islot ? at<int32_t>(ws, lo.islot) : nullptr);
         mode = lo.g.mode;
         continue;
       }
@@ -1095,6 +1098,74 @@ fsparse_status fsparse_assemble_complex(const int32_t* ii, const int32_t* jj,
   return assemble_impl(ii, jj, sr, dt, len, m, n, nzmax, flags, jcS, jcS_cap, irS,
                        prS, cap, slot, ws, ws_bytes, plan, info, stream, fsp::kIdxI32,
                        nullptr, si, piS);
+}
+
+// Logical values: the fp32 pipeline on 0/1 indicators with the zero sums
+// dropped; ws holds the pipeline's workspace, then the indicators, then the
+// fp32 sums.
+static size_t logical_head(int64_t len, int64_t ncols) {
+  const size_t h = fsparse_workspace_bytes(len, ncols, 1, FSPARSE_F32);
+  return (h + 255) & ~size_t(255);
+}
+
+size_t fsparse_logical_workspace_bytes(int64_t len, int64_t ncols) {
+  if (len < 0 || ncols < 0) return 0;
+  const size_t h = logical_head(len, ncols);
+  if (h == 0) return 0;
+  const size_t a = (4 * (size_t)std::max<int64_t>(len, 1) + 255) & ~size_t(255);
+  return h + 2 * a;
+}
+
+fsparse_status fsparse_assemble_logical(const int32_t* ii, const int32_t* jj,
+                                        const uint8_t* sl, int64_t len, int64_t m,
+                                        int64_t n, int64_t nzmax, int32_t* jcS,
+                                        int64_t jcS_cap, int32_t* irS, uint8_t* prS,
+                                        int64_t cap, int32_t* slot, void* ws,
+                                        size_t ws_bytes, fsparse_info* info,
+                                        hipStream_t stream) {
+  if (len < 0 || len > kMaxI32 || m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
+  if (len > 0 && (!ii || !jj || !sl)) return FSPARSE_E_ARG;
+  if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS))) return FSPARSE_E_ARG;
+  if (m < 0 || n < 0) {
+    int64_t dm = 0, dn = 0;
+    fsparse_status st = fsparse_dims(ii, jj, len, &dm, &dn, ws, ws_bytes, stream);
+    if (st != FSPARSE_OK) return st;
+    if (m < 0) m = dm;
+    if (n < 0) n = dn;
+  }
+  fsparse_info li{};
+  li.m = m;
+  li.n = n;
+  li.nzmax = std::max<int64_t>(nzmax, 0);
+  if (info) *info = li;
+  const size_t head = logical_head(len, n);
+  if (ws_bytes < fsparse_logical_workspace_bytes(len, n)) return FSPARSE_E_CAPACITY;
+  const int64_t L1 = std::max<int64_t>(len, 1);
+  const size_t a = (4 * (size_t)L1 + 255) & ~size_t(255);
+  float* v = at<float>(ws, head);
+  float* pf = at<float>(ws, head + a);
+  if (len > 0) {
+    hipError_t e = launch(kFill, stream, [&] {
+      hipLaunchKernelGGL(fsp::k_logical_ind, dim3(grid_for(len, 256, 8)), dim3(256), 0,
+                         stream, sl, len, v);
+    });
+    if (e != hipSuccess) return FSPARSE_E_HIP;
+  }
+  // irS and the fp32 sums hold min(cap, len) pairs (nnz <= len)
+  fsparse_status st = assemble_impl(ii, jj, v, FSPARSE_F32, len, m, n, nzmax,
+                                    FSPARSE_DROP_ZEROS, jcS, jcS_cap, irS, pf,
+                                    std::min(cap, L1), slot, ws, head, nullptr, &li,
+                                    stream, fsp::kIdxI32, nullptr);
+  if (info) *info = li;
+  if (st != FSPARSE_OK) return st;
+  if (li.nnz > 0) {
+    hipError_t e = launch(kFill, stream, [&] {
+      hipLaunchKernelGGL(fsp::k_fill_true, dim3(grid_for(li.nnz, 256, 8)), dim3(256), 0,
+                         stream, prS, li.nnz);
+    });
+    if (e != hipSuccess) return FSPARSE_E_HIP;
+  }
+  return FSPARSE_OK;
 }
 
 // Exact division by d on [0, 2^31) in the bins' multiply-high form.

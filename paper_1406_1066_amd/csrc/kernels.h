@@ -2389,6 +2389,22 @@ __global__ void k_drop_compact(const int32_t* __restrict__ excl, int64_t nnz,
   }
 }
 
+// logical values: 0/1 indicators (fp32) for the fold, whose sums are nonzero
+// exactly where a triplet is true (a fold of ones from +0 never returns to
+// zero, and saturates at 2^24 rather than wrap); the stored pairs are true
+__global__ void k_logical_ind(const uint8_t* __restrict__ sl, int64_t L,
+                              float* __restrict__ v) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; k < L; k += stride) v[k] = sl[k] ? 1.0f : 0.0f;
+}
+
+__global__ void k_fill_true(uint8_t* __restrict__ p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = 1u;
+}
+
 // a second value array (imaginary parts): kept entries to scratch, then back
 template <typename VT>
 __global__ void k_drop_move(const int32_t* __restrict__ excl, int64_t nnz,

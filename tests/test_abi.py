@@ -78,3 +78,13 @@ def test_argument_errors_without_gpu():
     assert L.fsparse_backward(None, -1, None, 0, L.F64, None, None) == L.E_ARG
     assert L.fsparse_plan_query(None, None, None, None) == L.E_PLAN
     L.fsparse_plan_destroy(None)
+
+
+def test_logical_workspace_bytes_host_only():
+    from paper_1406_1066_amd import _lib as L
+    for n_, c in ((1000, 100), (12345, 7), (0, 0)):
+        w = L.fsparse_logical_workspace_bytes(n_, c)
+        base = L.fsparse_workspace_bytes(n_, c, 1, L.F32)
+        # the fp32 pipeline's workspace, then indicators and sums
+        assert w >= base + 8 * max(n_, 1) and w % 256 == 0
+    assert L.fsparse_logical_workspace_bytes(-1, 3) == 0
