@@ -268,6 +268,9 @@ def modes(args, fs, torch, ii, jj, ss, m, n, L, vb, eb):
             ("fresh_with_plan",
              lambda: fs.sparse(ii, jj, ss, m, n, plan=True, keep_slot=True,
                                ws=res.ws),
+             None),
+            ("fresh_plan_no_slot",
+             lambda: fs.sparse(ii, jj, ss, m, n, plan=True, ws=res.ws),
              None)):
         for _ in range(3):
             fn()

@@ -307,10 +307,12 @@ fsparse_status fsparse_assemble_append(const int32_t *jcA, const int32_t *irA,
  * for, from new values ss[0..len) on the same (ii, jj) -- the repeated
  * assembly of Section 2.1 ("saving various types of information between
  * successive calls").  Ordered mode folds each pair in increasing k and is
- * bit-identical to a fresh assembly with the same ss.  FSPARSE_ATOMIC needs a
- * plan made with a non-NULL slot array or made by this library with the
- * internal one (always the case).  The work is one graph launch of a HIP
- * graph held by the plan; it never waits, so it may itself be captured.
+ * bit-identical to a fresh assembly with the same ss.  FSPARSE_ATOMIC works
+ * on every plan: it reads the slot array the plan was made with, or, for a
+ * plan made without one, a slot map that its first atomic call derives
+ * from the sorted order into the plan's workspace (one kernel more, that
+ * once).  The work is one graph launch of a HIP graph held by the plan; it
+ * never waits, so it may itself be captured.
  */
 fsparse_status fsparse_assemble_reuse(fsparse_plan *plan, const void *ss,
                                       void *prS, unsigned flags,

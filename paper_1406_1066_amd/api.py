@@ -258,7 +258,7 @@ def _fresh(call, Ln, m, n, ss, dev, nzmax, atomic, keep_slot, plan, cap, ws,
         irS0 = prS0 = None
         if cap is None:
             cap = max(Ln, 1)
-    if slot is None and (keep_slot or plan or atomic):
+    if slot is None and (keep_slot or atomic):
         slot = torch.empty(max(Ln, 1), dtype=torch.int32, device=dev)
     while True:
         if irS0 is not None:

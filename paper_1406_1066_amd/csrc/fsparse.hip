@@ -382,6 +382,7 @@ struct fsparse_plan {
   const int32_t* perm = nullptr;
   const int32_t* seg = nullptr;
   const int32_t* slot = nullptr;
+  int32_t* islot = nullptr;        // where a missing slot map is derived
   const int32_t* rtile = nullptr;  // first output of every re-use tile
   int64_t ntiles = 0;
   int rblock = 256;
@@ -902,9 +903,10 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
   // complex values: the imaginary parts are folded along the sorted order
   // that the real parts' pass leaves in the workspace
   const bool keep = plan != nullptr || si != nullptr;
-  // the internal slot map serves a plan's order-free re-use and the atomic
-  // sums; the ordered fold of imaginary parts reads only the sorted order
-  const bool islot = plan != nullptr || (si != nullptr && (flags & FSPARSE_ATOMIC));
+  // the atomic sums need a slot map (the caller's, else an internal one);
+  // a plan's ordered re-use and the imaginary fold read only the sorted
+  // order, and a plan derives its slot map on its first atomic re-use
+  const bool islot = (plan != nullptr || si != nullptr) && (flags & FSPARSE_ATOMIC);
   int32_t* slot_used = slot ? slot : (islot ? at<int32_t>(ws, lo.islot) : nullptr);
   if (len == 0) {
     hipError_t e = launch(kInit, stream, [&] {
@@ -996,6 +998,7 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
       pl->perm = at<int32_t>(ws, lo.perm);
       pl->seg = at<int32_t>(ws, lo.seg);
       pl->slot = slot_used;
+      pl->islot = at<int32_t>(ws, lo.islot);
       pl->rtile = at<int32_t>(ws, lo.rtile);
       pl->ntiles = (len + kReuseTP - 1) / kReuseTP;
       pl->rblock = tu.rblock;
@@ -1331,7 +1334,19 @@ fsparse_status fsparse_assemble_reuse(fsparse_plan* plan, const void* ss,
   hipGetDevice(&dev);
   if (dev != plan->device) return FSPARSE_E_PLAN;
   if (flags & FSPARSE_ATOMIC) {
-    if (!plan->slot) return FSPARSE_E_PLAN;
+    if (!plan->slot) {
+      if (!plan->islot || !plan->perm || !plan->seg) return FSPARSE_E_PLAN;
+      const int32_t* perm = plan->perm;
+      const int32_t* seg = plan->seg;
+      int32_t* islot = plan->islot;
+      const int64_t nnz = plan->nnz;
+      hipError_t e = launch(kReuse, stream, [&] {
+        hipLaunchKernelGGL(fsp::k_slot_from_order, dim3(grid_for(nnz, 256, 8)), dim3(256),
+                           0, stream, perm, seg, nnz, islot);
+      });
+      if (e != hipSuccess) return FSPARSE_E_HIP;
+      plan->slot = islot;
+    }
     return plan_reuse_atomic(plan, ss, prS, stream);
   }
   return plan_reuse_ordered(plan, ss, prS, stream);

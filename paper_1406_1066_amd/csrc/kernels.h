@@ -2304,6 +2304,17 @@ k_reuse(const int32_t* __restrict__ perm, const int32_t* __restrict__ seg,
   }
 }
 
+// The slot map from a plan's sorted order: every position p of output j's
+// run seg[j]..seg[j+1] holds a triplet number perm[p] whose slot is j.
+__global__ void k_slot_from_order(const int32_t* __restrict__ perm,
+                                  const int32_t* __restrict__ seg, int64_t nnz,
+                                  int32_t* __restrict__ slot) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; j < nnz; j += stride)
+    for (int32_t p = seg[j]; p < seg[j + 1]; ++p) slot[perm[p]] = (int32_t)j;
+}
+
 template <typename VT>
 __global__ void k_fill(VT* __restrict__ p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

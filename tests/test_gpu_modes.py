@@ -85,6 +85,25 @@ def test_atomic_mode_tolerance(fs, dtype, tol):
         assert np.all(err <= tol * np.maximum(scale, 1e-300)), err.max()
 
 
+def test_atomic_reuse_on_plan_without_slot(fs):
+    # a plan made without a slot array derives the slot map from its sorted
+    # order on the first atomic re-use; ordered re-use is unaffected
+    t = W.fem3d(12, 0.15, seed=9)
+    res = run(fs, t.ii, t.jj, t.ss, t.m, t.n, plan=True)
+    assert res.slot is None
+    ref = oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
+    whole = np.round(t.ss * 8.0)               # whole numbers: exact sums
+    want = oracle.assemble(t.ii, t.jj, whole, t.m, t.n).prS
+    for _ in range(2):
+        got = fs.reassemble(res, to_dev(whole), atomic=True).cpu().numpy()
+        assert got.tobytes() == want.tobytes()
+    scale = oracle.assemble(t.ii, t.jj, np.abs(t.ss), t.m, t.n).prS
+    got = fs.reassemble(res, to_dev(t.ss), atomic=True).cpu().numpy()
+    assert np.all(np.abs(got - ref.prS) <= 1e-14 * np.maximum(scale, 1e-300))
+    got = fs.reassemble(res, to_dev(t.ss)).cpu().numpy()
+    assert got.tobytes() == ref.prS.tobytes()
+
+
 def test_atomic_mode_exact_on_counts(fs):
     t = W.ransparse(2000, 20, 10, seed=6)
     ref = oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
