@@ -488,12 +488,7 @@ template <typename VT>
 hipError_t drop_zeros(void* ws, const Layout& lo, int64_t nnz, int64_t n, int64_t L,
                       int32_t* jcS, int32_t* irS, VT* prS, int32_t* slot,
                       Ctrl* h, hipStream_t stream, VT* piS = nullptr) {
-  uint32_t* keep = at<uint32_t>(ws, lo.perm);          // nnz words
   int32_t* excl = at<int32_t>(ws, lo.seg);             // nnz + 1 words
-  int32_t* ir2 = at<int32_t>(ws, lo.tmp);              // scratch: nnz rows,
-  // then the values, 8-byte aligned: 4 (nnz + 1) + sizeof(VT) nnz bytes fit
-  // the region's (8 + sizeof(VT)) L
-  VT* pr2 = reinterpret_cast<VT*>(ir2 + ((nnz + 1) & ~int64_t(1)));
   uint32_t* ticket = at<uint32_t>(ws, lo.dropst);
   uint64_t* status = at<uint64_t>(ws, lo.dropst + 64);
   const int64_t tiles = (nnz + 1 + kScanTile - 1) / kScanTile;
@@ -501,25 +496,12 @@ hipError_t drop_zeros(void* ws, const Layout& lo, int64_t nnz, int64_t n, int64_
   hipError_t e = launch(kDrop, stream, [&] {
     hipLaunchKernelGGL(fsp::k_zero, dim3(grid_for(zw, 256, 4)), dim3(256), 0, stream,
                        ticket, zw);
-    hipLaunchKernelGGL(fsp::k_drop_flags<VT>, dim3(grid_for(nnz, 256, 4)), dim3(256), 0,
-                       stream, (const VT*)prS, (const VT*)piS, nnz, keep);
-    hipLaunchKernelGGL((fsp::k_scan_excl<kScanNT, kScanIPT>), dim3((unsigned)tiles),
-                       dim3(kScanNT), 0, stream, (const uint32_t*)keep, (int32_t)nnz,
-                       excl, status, ticket, UINT32_MAX, (uint32_t*)nullptr,
-                       (int32_t*)nullptr);
-    hipLaunchKernelGGL(fsp::k_drop_compact<VT>, dim3(grid_for(nnz, 256, 4)), dim3(256), 0,
-                       stream, (const int32_t*)excl, nnz, (const int32_t*)irS,
-                       (const VT*)prS, ir2, pr2);
-    hipLaunchKernelGGL(fsp::k_drop_finish<VT>,
-                       dim3(grid_for(std::max<int64_t>(std::max(nnz, L), n + 1), 256, 4)),
-                       dim3(256), 0, stream, (const int32_t*)excl, nnz,
-                       (const int32_t*)ir2, (const VT*)pr2, irS, prS, jcS, n, slot, L);
-    if (piS) {  // pr2 is free again once the finish has read it
-      hipLaunchKernelGGL(fsp::k_drop_move<VT>, dim3(grid_for(nnz, 256, 4)), dim3(256), 0,
-                         stream, (const int32_t*)excl, nnz, (const VT*)piS, pr2);
-      hipLaunchKernelGGL(fsp::k_drop_back<VT>, dim3(grid_for(nnz, 256, 4)), dim3(256), 0,
-                         stream, (const int32_t*)excl, nnz, (const VT*)pr2, piS);
-    }
+    hipLaunchKernelGGL((fsp::k_drop_pass<VT, kScanNT, kScanIPT>), dim3((unsigned)tiles),
+                       dim3(kScanNT), 0, stream, irS, prS, piS, (int32_t)nnz, excl,
+                       status, ticket);
+    hipLaunchKernelGGL(fsp::k_drop_renumber,
+                       dim3(grid_for(std::max<int64_t>(n + 1, slot ? L : 0), 256, 4)),
+                       dim3(256), 0, stream, (const int32_t*)excl, jcS, n, slot, L);
   });
   if (e != hipSuccess) return e;
   return hipMemcpyAsync(&h->kept, excl + nnz, sizeof(int32_t), hipMemcpyDeviceToHost,

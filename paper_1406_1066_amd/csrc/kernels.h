@@ -2366,38 +2366,103 @@ __global__ void k_ccs_triplets(const int32_t* __restrict__ jcA,
 }
 
 // ---------------------------------------------------------------------------
-// drop zeros: remove the pairs whose sum is zero (+0 or -0), as a Matlab
-// sparse matrix stores no zeros.  keep[j] = prS[j] != 0, its exclusive scan
-// gives every kept entry its new place, the kept entries go out of place to
-// scratch and back, and jcS and the slots are renumbered.
+// drop zeros: remove the pairs whose sum is zero (+0 or -0; with imaginary
+// parts, zero in both), as a Matlab sparse matrix stores no zeros.  One
+// pass in ticket order.  Tile q holds IPT rows of NT consecutive pairs
+// (row j = pairs [q*NT*IPT + j*NT, +NT), one per thread, so loads and
+// stores are coalesced); wave ballots count the kept pairs per row, the
+// look-back gives the tile's output offset, and the kept pairs are written
+// in place.  A tile writes only at or below its own end, where earlier
+// tiles or its own threads have already loaded: a tile publishes its count
+// only after all its loads have returned (the count depends on every
+// loaded word), and gets its offset only once every earlier tile has
+// published.  excl[j] = kept pairs before j; excl[nnz] = the total.
 // ---------------------------------------------------------------------------
-// With complex values (piS given) a pair is zero when both parts are.
-template <typename VT>
-__global__ void k_drop_flags(const VT* __restrict__ prS, const VT* __restrict__ piS,
-                             int64_t nnz, uint32_t* __restrict__ keep) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  if (piS)
-    for (; j < nnz; j += stride)
-      keep[j] = (prS[j] != (VT)0 || piS[j] != (VT)0) ? 1u : 0u;
-  else
-    for (; j < nnz; j += stride) keep[j] = prS[j] != (VT)0 ? 1u : 0u;
-}
-
-template <typename VT>
-__global__ void k_drop_compact(const int32_t* __restrict__ excl, int64_t nnz,
-                               const int32_t* __restrict__ irS,
-                               const VT* __restrict__ prS,
-                               int32_t* __restrict__ ir2, VT* __restrict__ pr2) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; j < nnz; j += stride) {
-    const int32_t p = excl[j];
-    if (excl[j + 1] > p) {
-      ir2[p] = irS[j];
-      pr2[p] = prS[j];
+template <typename VT, int NT, int IPT>
+__global__ void __launch_bounds__(NT)
+k_drop_pass(int32_t* __restrict__ irS, VT* __restrict__ prS, VT* __restrict__ piS,
+            int32_t n, int32_t* __restrict__ excl, uint64_t* status, uint32_t* ticket) {
+  constexpr int NW = NT / 64;
+  __shared__ uint32_t sCnt[IPT][NW];
+  __shared__ int sTile;
+  __shared__ int64_t sBase;
+  if (threadIdx.x == 0) sTile = (int)atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int tile = sTile;
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  const int64_t t0 = (int64_t)tile * NT * IPT + threadIdx.x;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  int32_t r[IPT];
+  VT pr[IPT], pi[IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    const int64_t i = t0 + (int64_t)j * NT;
+    r[j] = 0;
+    pr[j] = (VT)0;
+    pi[j] = (VT)0;
+    if (i < n) {
+      r[j] = irS[i];
+      pr[j] = prS[i];
+      if (piS) pi[j] = piS[i];
     }
   }
+  uint32_t keep = 0u, rk[IPT];
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    // r[j] >= 0 always holds; testing it makes the count wait for the load
+    const bool k = t0 + (int64_t)j * NT < n && r[j] >= 0 &&
+                   (pr[j] != (VT)0 || pi[j] != (VT)0);
+    const uint64_t m = __ballot(k);
+    rk[j] = (uint32_t)__popcll(m & lt);
+    if (lane == 0) sCnt[j][wid] = (uint32_t)__popcll(m);
+    keep |= (k ? 1u : 0u) << j;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    uint32_t total = 0u;
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+#pragma unroll
+      for (int w = 0; w < NW; ++w) total += sCnt[j][w];
+    const int64_t ex = lookback(status, tile, total);
+    if (threadIdx.x == 0) sBase = ex;
+  }
+  __syncthreads();
+  int64_t run = sBase;  // kept pairs before the current row
+#pragma unroll
+  for (int j = 0; j < IPT; ++j) {
+    uint32_t before = 0u, row = 0u;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const uint32_t c = sCnt[j][w];
+      before += w < wid ? c : 0u;
+      row += c;
+    }
+    const int64_t i = t0 + (int64_t)j * NT;
+    const int64_t pos = run + before + rk[j];
+    if (i <= n) excl[i] = (int32_t)pos;
+    if ((keep >> j) & 1u) {
+      irS[pos] = r[j];
+      prS[pos] = pr[j];
+      if (piS) piS[pos] = pi[j];
+    }
+    run += row;
+  }
+}
+
+// jcS[c] = kept pairs before the column's old start; slot[k] = the new place
+// of its pair, or -1 when the pair was removed
+__global__ void k_drop_renumber(const int32_t* __restrict__ excl,
+                                int32_t* __restrict__ jcS, int64_t n,
+                                int32_t* __restrict__ slot, int64_t L) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t c = t; c <= n; c += stride) jcS[c] = excl[jcS[c]];
+  if (slot)
+    for (int64_t k = t; k < L; k += stride) {
+      const int32_t s = slot[k];
+      slot[k] = excl[s + 1] > excl[s] ? excl[s] : -1;
+    }
 }
 
 // logical values: 0/1 indicators (fp32) for the fold, whose sums are nonzero
@@ -2416,48 +2481,5 @@ __global__ void k_fill_true(uint8_t* __restrict__ p, int64_t n) {
   for (; i < n; i += stride) p[i] = 1u;
 }
 
-// a second value array (imaginary parts): kept entries to scratch, then back
-template <typename VT>
-__global__ void k_drop_move(const int32_t* __restrict__ excl, int64_t nnz,
-                            const VT* __restrict__ src, VT* __restrict__ dst) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; j < nnz; j += stride) {
-    const int32_t p = excl[j];
-    if (excl[j + 1] > p) dst[p] = src[j];
-  }
-}
-
-template <typename VT>
-__global__ void k_drop_back(const int32_t* __restrict__ excl, int64_t nnz,
-                            const VT* __restrict__ src, VT* __restrict__ dst) {
-  const int64_t kept = excl[nnz];
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; j < kept; j += stride) dst[j] = src[j];
-}
-
-// back into the caller's arrays (excl[nnz] entries), jcS[c] = kept entries
-// before the column's old start, slot[k] = the new place or -1
-template <typename VT>
-__global__ void k_drop_finish(const int32_t* __restrict__ excl, int64_t nnz,
-                              const int32_t* __restrict__ ir2,
-                              const VT* __restrict__ pr2, int32_t* __restrict__ irS,
-                              VT* __restrict__ prS, int32_t* __restrict__ jcS,
-                              int64_t n, int32_t* __restrict__ slot, int64_t L) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t kept = excl[nnz];
-  for (int64_t j = t; j < kept; j += stride) {
-    irS[j] = ir2[j];
-    prS[j] = pr2[j];
-  }
-  for (int64_t c = t; c <= n; c += stride) jcS[c] = excl[jcS[c]];
-  if (slot)
-    for (int64_t k = t; k < L; k += stride) {
-      const int32_t s = slot[k];
-      slot[k] = excl[s + 1] > excl[s] ? excl[s] : -1;
-    }
-}
 
 }  // namespace fsp
