@@ -1277,14 +1277,16 @@ fsparse_status fsparse_assemble_append(const int32_t* jcA, const int32_t* irA,
   // its contributions in order (a fold from +0.0 never ends at -0.0)
   if (nnzA > 0) {
     hipError_t e = launch(kAppend, stream, [&] {
+      // one block per 2048 stored pairs (the kernel's NT * EPT)
+      const dim3 grid((unsigned)((nnzA + 2047) / 2048));
       if (dt == FSPARSE_F64)
-        hipLaunchKernelGGL(fsp::k_ccs_triplets<double>, dim3(grid_for(nnzA, 256, 4)),
-                           dim3(256), 0, stream, jcA, irA, (const double*)prA, nA,
-                           nnzA, ic, jc, (double*)sc);
+        hipLaunchKernelGGL((fsp::k_ccs_triplets<double, 256, 8>), grid, dim3(256), 0,
+                           stream, jcA, irA, (const double*)prA, nA, nnzA, ic, jc,
+                           (double*)sc);
       else
-        hipLaunchKernelGGL(fsp::k_ccs_triplets<float>, dim3(grid_for(nnzA, 256, 4)),
-                           dim3(256), 0, stream, jcA, irA, (const float*)prA, nA,
-                           nnzA, ic, jc, (float*)sc);
+        hipLaunchKernelGGL((fsp::k_ccs_triplets<float, 256, 8>), grid, dim3(256), 0,
+                           stream, jcA, irA, (const float*)prA, nA, nnzA, ic, jc,
+                           (float*)sc);
     });
     if (e != hipSuccess) return FSPARSE_E_HIP;
   }

@@ -2343,24 +2343,51 @@ __global__ void k_backward(const int32_t* __restrict__ slot,
 // ---------------------------------------------------------------------------
 // delayed assembly: an assembled matrix (jcA, irA, prA) as its own triplets,
 // one per stored pair in storage order, ahead of the new triplets.  Column
-// of entry e: the last c with jcA[c] <= e (binary search over jcA[0..n]).
+// of entry e: the last c with jcA[c] <= e.  A block takes NT*EPT
+// consecutive entries and finds the columns c0, c1 of its first and last
+// entry by binary search over jcA[0..n]; when jcA[c0..c1+1] fits its LDS
+// window (empty columns can make it long) every entry searches the window,
+// otherwise jcA[c0..c1+1] in global memory.  Reads and writes coalesced.
 // ---------------------------------------------------------------------------
-template <typename VT>
-__global__ void k_ccs_triplets(const int32_t* __restrict__ jcA,
-                               const int32_t* __restrict__ irA,
-                               const VT* __restrict__ prA, int64_t n, int64_t nnzA,
-                               int32_t* __restrict__ ii, int32_t* __restrict__ jj,
-                               VT* __restrict__ ss) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; e < nnzA; e += stride) {
-    int64_t lo = 0, hi = n;  // jcA[lo] <= e < jcA[hi]
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (jcA[mid] <= e) lo = mid; else hi = mid;
-    }
+__device__ __forceinline__ int64_t ccs_col(const int32_t* __restrict__ p,
+                                           int64_t lo, int64_t hi, int64_t e) {
+  while (hi - lo > 1) {  // p[lo] <= e < p[hi]
+    const int64_t mid = (lo + hi) >> 1;
+    if (p[mid] <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <typename VT, int NT, int EPT>
+__global__ void __launch_bounds__(NT)
+k_ccs_triplets(const int32_t* __restrict__ jcA, const int32_t* __restrict__ irA,
+               const VT* __restrict__ prA, int64_t n, int64_t nnzA,
+               int32_t* __restrict__ ii, int32_t* __restrict__ jj,
+               VT* __restrict__ ss) {
+  constexpr int TE = NT * EPT;
+  constexpr int WSZ = TE + 2;
+  __shared__ int32_t win[WSZ];
+  __shared__ int64_t sC[2];
+  const int64_t E0 = (int64_t)blockIdx.x * TE;
+  if (E0 >= nnzA) return;  // the whole block
+  const int64_t E1 = min(E0 + TE, nnzA) - 1;
+  if (threadIdx.x == 0) sC[0] = ccs_col(jcA, 0, n, E0);
+  if (threadIdx.x == NT - 1) sC[1] = ccs_col(jcA, 0, n, E1);
+  __syncthreads();
+  const int64_t c0 = sC[0], c1 = sC[1];
+  const int64_t cnt = c1 - c0 + 2;  // jcA[c0 .. c1+1]; c1 + 1 <= n
+  const bool inwin = cnt <= WSZ;
+  if (inwin) {
+    for (int t = threadIdx.x; t < cnt; t += NT) win[t] = jcA[c0 + t];
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < TE; k += NT) {
+    const int64_t e = E0 + k;
+    if (e > E1) break;
+    const int64_t c = inwin ? c0 + ccs_col(win, 0, cnt - 1, e)
+                            : ccs_col(jcA, c0, c1 + 1, e);
     ii[e] = irA[e] + 1;
-    jj[e] = (int32_t)lo + 1;
+    jj[e] = (int32_t)c + 1;
     ss[e] = prA[e];
   }
 }
