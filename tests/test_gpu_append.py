@@ -104,3 +104,20 @@ def test_plan_from_append_and_drop_zeros(fs):
     d = fs.sparse_append(a, to_dev(ii[20_000:]), to_dev(jj[20_000:]),
                          to_dev(ss[20_000:]), keep_slot=True, drop_zeros=True)
     assert_same(d, oracle.drop_zeros(ref))
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_stored_pairs_between_empty_column_runs(fs, dtype):
+    # 40 non-empty columns among 200000: most blocks of stored pairs span
+    # runs of empty columns too long for their LDS window and search the
+    # column pointers in global memory, the others use the window
+    rng = np.random.default_rng(97)
+    m, n, L = 3000, 200_000, 120_000
+    cols = rng.choice(np.arange(1, n + 1), 40, replace=False)
+    ii = rng.integers(1, m + 1, L).astype(np.int32)
+    jj = rng.choice(cols, L).astype(np.int32)
+    ss = (rng.standard_normal(L) * 10.0 ** rng.integers(-6, 7, L)).astype(dtype)
+    res, ref = chain(fs, ii, jj, ss, [L // 2], m, n)
+    want = oracle.assemble(ii, jj, ss, m, n)
+    assert ref.prS.tobytes() == want.prS.tobytes()
+    assert np.array_equal(ref.jcS, want.jcS)
