@@ -888,8 +888,8 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
   // the atomic sums need a slot map (the caller's, else an internal one);
   // a plan's ordered re-use and the imaginary fold read only the sorted
   // order, and a plan derives its slot map on its first atomic re-use
-  const bool islot = (plan != nullptr || si != nullptr) && (flags & FSPARSE_ATOMIC);
-  int32_t* slot_used = slot ? slot : (islot ? at<int32_t>(ws, lo.islot) : nullptr);
+  const bool use_islot = (plan != nullptr || si != nullptr) && (flags & FSPARSE_ATOMIC);
+  int32_t* slot_used = slot ? slot : (use_islot ? at<int32_t>(ws, lo.islot) : nullptr);
   if (len == 0) {
     hipError_t e = launch(kInit, stream, [&] {
       hipLaunchKernelGGL(fsp::k_zero, dim3(grid_for(n + 1, 256, 4)), dim3(256), 0,
@@ -926,7 +926,7 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
       if ((h->err & fsp::kErrSlot) && mode == kSlot) {
         lo = make_layout(len, n, 1, esize_of(dt), tu, true);
         if (ws_bytes < lo.total) return FSPARSE_E_CAPACITY;
-        slot_used = slot ? slot : (islot ? at<int32_t>(ws, lo.islot) : nullptr);
+        slot_used = slot ? slot : (use_islot ? at<int32_t>(ws, lo.islot) : nullptr);
         mode = lo.g.mode;
         continue;
       }
