@@ -64,9 +64,14 @@ def _stream():
 
 
 def _ptr(t: Optional[torch.Tensor]):
-    if t is None:
+    """Device address of a tensor for the library (None when empty).  A host
+    tensor is refused here: its address would reach the kernels."""
+    if t is None or t.numel() == 0:
         return None
-    return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else None
+    if not t.is_cuda:
+        raise ValueError("the library takes GPU tensors; got one on %s"
+                         % t.device)
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _as_tensor(x) -> torch.Tensor:

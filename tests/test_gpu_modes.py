@@ -235,3 +235,18 @@ def test_batched_modes_fp32(fs, mode):
             assert pr.cpu().numpy().tobytes() == ref.prS.tobytes()
     finally:
         fs.set_tuning(reset=True)
+
+
+def test_host_value_tensors_are_refused(fs):
+    # values left on the host raise before any launch
+    ii = to_dev(np.array([1, 2], np.int32))
+    host = torch.tensor([1.0, 2.0], dtype=torch.float64)
+    with pytest.raises(ValueError):
+        fs.sparse(ii, ii, host, 2, 2)
+    with pytest.raises(ValueError):
+        fs.sparse_complex(ii, ii, host, host, 2, 2)
+    with pytest.raises(ValueError):
+        fs.sparse_logical(ii, ii, torch.tensor([True, False]), 2, 2)
+    res = fs.sparse(ii, ii, to_dev(np.array([1.0, 2.0])), 2, 2, plan=True)
+    with pytest.raises(ValueError):
+        fs.reassemble(res, host)
