@@ -88,3 +88,41 @@ def test_logical_workspace_bytes_host_only():
         # the fp32 pipeline's workspace, then indicators and sums
         assert w >= base + 8 * max(n_, 1) and w % 256 == 0
     assert L.fsparse_logical_workspace_bytes(-1, 3) == 0
+
+
+def test_complex_and_logical_argument_errors_without_gpu():
+    from paper_1406_1066_amd import _lib as L
+    info = L.FsparseInfo()
+    plan = ctypes.c_void_p()
+    ws = ctypes.c_void_p(1)          # never dereferenced: rejected before use
+    jc = ctypes.c_void_p(1)
+    # complex: unknown value type, unknown flag, drop-zeros with a plan,
+    # triplets without an imaginary array, NULL jcS
+    args = (0, 3, 3, 0)
+    assert L.fsparse_assemble_complex(None, None, None, None, 9, *args, 0, jc,
+                                      4, None, None, None, 0, None, ws, 1 << 20,
+                                      None, ctypes.byref(info), None) == L.E_ARG
+    assert L.fsparse_assemble_complex(None, None, None, None, L.F64, *args, 64,
+                                      jc, 4, None, None, None, 0, None, ws,
+                                      1 << 20, None, None, None) == L.E_ARG
+    assert L.fsparse_assemble_complex(None, None, None, None, L.F64, *args,
+                                      L.DROP_ZEROS, jc, 4, None, None, None, 0,
+                                      None, ws, 1 << 20, ctypes.byref(plan),
+                                      None, None) == L.E_ARG
+    one = ctypes.c_void_p(1)
+    assert L.fsparse_assemble_complex(one, one, one, None, L.F64, 5, 3, 3, 0,
+                                      0, jc, 4, None, None, None, 0, None, ws,
+                                      1 << 20, None, None, None) == L.E_ARG
+    assert L.fsparse_assemble_complex(None, None, None, None, L.F64, *args, 0,
+                                      None, 4, None, None, None, 0, None, ws,
+                                      1 << 20, None, None, None) == L.E_ARG
+    # logical: negative length, triplets without values, NULL workspace
+    assert L.fsparse_assemble_logical(None, None, None, -1, 3, 3, 0, jc, 4,
+                                      None, None, 0, None, ws, 1 << 20, None,
+                                      None) == L.E_ARG
+    assert L.fsparse_assemble_logical(one, one, None, 5, 3, 3, 0, jc, 4, None,
+                                      None, 0, None, ws, 1 << 20, None,
+                                      None) == L.E_ARG
+    assert L.fsparse_assemble_logical(None, None, None, 0, 3, 3, 0, jc, 4,
+                                      None, None, 0, None, None, 0, None,
+                                      None) == L.E_ARG
