@@ -653,3 +653,24 @@ def test_logical_hand_example():
     assert (r.m, r.n) == (2, 2)
     assert r.jcS.tolist() == [0, 1, 2] and r.irS.tolist() == [0, 0]
     assert r.slot.tolist() == [0, -1, 1, 0, 1]
+
+
+def test_complex_hermitian_elements_assemble_hermitian():
+    # symmetric real and antisymmetric imaginary element matrices: (i,j)
+    # and (j,i) receive their terms from the same elements in the same
+    # order, so the real sums agree bit for bit and the imaginary sums are
+    # exact negatives (zero on the diagonal)
+    t = W.fem2d(9, 0.2, seed=13)
+    ne = t.meta["elements"]
+    Wm = np.random.default_rng(14).standard_normal((ne, 3, 3))
+    si = (Wm - Wm.transpose(0, 2, 1)).reshape(-1)
+    r = oracle.assemble_complex(t.ii, t.jj, t.ss, si, t.m, t.n)
+    cols = np.repeat(np.arange(r.n), np.diff(r.jcS))
+    where = {(int(i), int(c)): p for p, (i, c) in enumerate(zip(r.irS, cols))}
+    for (i, c), p in where.items():
+        q = where[(c, i)]
+        assert r.prS[p].tobytes() == r.prS[q].tobytes()
+        assert r.piS[p] == -r.piS[q]
+        if i == c:
+            assert r.piS[p] == 0
+    assert np.any(r.piS != 0)
