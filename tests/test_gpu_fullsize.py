@@ -200,3 +200,26 @@ def test_fem3d_100_expanded(fs):
     assert res.nnz == W.fem3d_counts(100)[1]
     check_invariants(res, to_dev(t.ii), to_dev(t.jj), t.m, t.n)
     check_sampled(res, t, sample_cols(t.n, 200, 21))
+
+
+def test_uniform_1e7_complex_and_logical(fs):
+    # the two other value types at the full random size, every output
+    # against the oracle: complex parts bit for bit, logical pattern exact
+    t = W.config("uniform_1e7")
+    ii, jj = to_dev(t.ii), to_dev(t.jj)
+    si = np.random.default_rng(1406).standard_normal(t.L)
+    ref = oracle.assemble_complex(t.ii, t.jj, t.ss, si, t.m, t.n)
+    res = fs.sparse_complex(ii, jj, to_dev(t.ss), to_dev(si), t.m, t.n)
+    np.testing.assert_array_equal(res.jcS.cpu().numpy(), ref.jcS)
+    np.testing.assert_array_equal(res.irS.cpu().numpy(), ref.irS)
+    assert res.prS.cpu().numpy().tobytes() == ref.prS.tobytes()
+    assert res.piS.cpu().numpy().tobytes() == ref.piS.tobytes()
+    del res, ref
+    sl = t.ss > 0.5                              # about 31% true
+    ref = oracle.assemble_logical(t.ii, t.jj, sl, t.m, t.n)
+    res = fs.sparse_logical(ii, jj, to_dev(sl), t.m, t.n, keep_slot=True)
+    assert res.nnz == ref.nnz and 0 < ref.nnz < t.L
+    np.testing.assert_array_equal(res.jcS.cpu().numpy(), ref.jcS)
+    np.testing.assert_array_equal(res.irS.cpu().numpy(), ref.irS)
+    np.testing.assert_array_equal(res.slot.cpu().numpy(), ref.slot)
+    assert bool(res.prS.all())
