@@ -654,8 +654,11 @@ def assemble_batched(ii, jj, ss: torch.Tensor, trip_off: Sequence[int],
 
 
 def to_torch_csc(res: Assembled) -> torch.Tensor:
+    """The result as a torch sparse CSC tensor (a conversion for the caller,
+    after the assembly); complex results carry prS + i*piS."""
+    vals = res.prS if res.piS is None else torch.complex(res.prS, res.piS)
     return torch.sparse_csc_tensor(res.jcS.to(torch.int64),
-                                   res.irS.to(torch.int64), res.prS,
+                                   res.irS.to(torch.int64), vals,
                                    size=(res.m, res.n))
 
 

@@ -163,3 +163,15 @@ def test_argument_errors(fs):
         fs.sparse_complex(ii, ii, sr, sr, plan=True, drop_zeros=True)
     with pytest.raises(fs.FsparseIndexError):
         fs.sparse_complex(ii, ii, sr, sr, 1, 1)
+
+
+def test_to_dense_carries_both_parts(fs):
+    t = W.fem2d(6, 0.2, seed=86)
+    si = spread(t.L, 87, np.float64)
+    res, ref = check_complex(fs, t.ii, t.jj, t.ss, si, t.m, t.n)
+    D = np.zeros((t.m, t.n), dtype=np.complex128)
+    cols = np.repeat(np.arange(t.n), np.diff(ref.jcS))
+    D[ref.irS, cols] = ref.prS + 1j * ref.piS
+    got = res.to_dense().cpu().numpy()
+    assert got.dtype == np.complex128
+    np.testing.assert_array_equal(got, D)
