@@ -8,7 +8,9 @@ its Python binding) never imports it and shares no code with it.
 one thread); ``brute`` holds an independent pure-Python dense accumulation
 used to pin the C oracle on tiny inputs.  ``backward`` and ``reassemble``
 are the definitions of the derivative of the assembled values with respect
-to the triplet values and of re-assembly with new values; ``expand`` writes
+to the triplet values and of re-assembly with new values; ``postprocess``
+is the paper's serial value pass from a known slot map (a fast re-assembly
+check at full sizes); ``expand`` writes
 out the triplets of an index-expanded input; ``assemble_complex`` sums
 complex values (split real and imaginary arrays) on the same pattern;
 ``assemble_logical`` stores the pairs that have a true triplet.
@@ -65,6 +67,12 @@ def _load():
         lib.oracle_dims.restype = ctypes.c_int
         lib.oracle_dims.argtypes = [i32p, i32p, i64, ctypes.POINTER(i64),
                                     ctypes.POINTER(i64)]
+        for name, vt in (("oracle_postprocess_f64", np.float64),
+                         ("oracle_postprocess_f32", np.float32)):
+            vp = np.ctypeslib.ndpointer(vt, flags="C_CONTIGUOUS")
+            f = getattr(lib, name)
+            f.restype = ctypes.c_int
+            f.argtypes = [i32p, vp, i64, i64, vp]
         _lib = lib
     return _lib
 
@@ -140,13 +148,42 @@ def reassemble(res: Result, ii, jj, ss) -> np.ndarray:
     return assemble(ii, jj, ss, res.m, res.n).prS
 
 
+def postprocess(slot, ss, nnz: int) -> np.ndarray:
+    """Values from a known slot map: the serial post-processing of the
+    appendix ("Post-processing: finalize CCS format"), prS[slot[k]] += ss[k]
+    for k = 0, 1, ... over a prS that starts at +0.0.  With the slot map of
+    an assembly this is the value pass alone, i.e. re-assembly of new
+    values on the same pattern (written in C, one thread)."""
+    lib = _load()
+    slot = np.ascontiguousarray(slot, dtype=np.int32)
+    ss = np.ascontiguousarray(ss)
+    if ss.dtype not in (np.float64, np.float32):
+        ss = ss.astype(np.float64)
+    assert slot.shape[0] == ss.shape[0]
+    prS = np.zeros(max(int(nnz), 1), dtype=ss.dtype)
+    f = (lib.oracle_postprocess_f64 if ss.dtype == np.float64
+         else lib.oracle_postprocess_f32)
+    st = f(slot, ss, ss.shape[0], int(nnz), prS)
+    if st != OK:
+        raise ValueError("slot map outside [0, nnz)")
+    return prS[:int(nnz)].copy()
+
+
 def backward(slot, grad_prS) -> np.ndarray:
     """d(prS)/d(ss) applied to an upstream gradient.
 
     prS[t] = sum over k with slot[k] = t of ss[k] (Section 2.2, eq. (2.3)),
     so d prS[t] / d ss[k] = [slot[k] = t] and grad_ss[k] = grad_prS[slot[k]].
+    A triplet with slot -1 belongs to a pair that is not stored (a zero sum
+    dropped, or a logical pair without a true triplet): no stored value
+    depends on it, so its gradient is 0.
     """
-    return np.asarray(grad_prS)[np.asarray(slot)]
+    slot = np.asarray(slot)
+    g = np.asarray(grad_prS)
+    out = np.zeros(slot.shape[0], dtype=g.dtype)
+    kept = slot >= 0
+    out[kept] = g[slot[kept]]
+    return out
 
 
 def assemble_columns(ii, jj, ss, m: int, n: int, cols: Sequence[int],

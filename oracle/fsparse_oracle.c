@@ -131,3 +131,23 @@ static int ordered_keys(const int32_t *ii, const int32_t *jj, int64_t len,
 
 DEFINE_ASSEMBLE(oracle_assemble_f64, double)
 DEFINE_ASSEMBLE(oracle_assemble_f32, float)
+
+/* The paper's serial post-processing (appendix, "Post-processing: finalize
+ * CCS format") with the inverse rank known: prS starts at +0.0 and every
+ * triplet, in increasing k, adds its value to the entry its slot names.
+ * Given the slot map of an assembly, this is the value pass on its own, so
+ * it re-assembles new values on a known pattern.  Every slot must lie in
+ * [0, nnz). */
+#define DEFINE_POSTPROCESS(NAME, VT)                                           \
+  int NAME(const int32_t *slot, const VT *ss, int64_t len, int64_t nnz,       \
+           VT *prS) {                                                          \
+    if (len < 0 || nnz < 0) return ORACLE_E_ARG;                               \
+    for (int64_t k = 0; k < len; k++)                                          \
+      if (slot[k] < 0 || slot[k] >= nnz) return ORACLE_E_ARG;                  \
+    for (int64_t t = 0; t < nnz; t++) prS[t] = (VT)0.0;                        \
+    for (int64_t k = 0; k < len; k++) prS[slot[k]] = prS[slot[k]] + ss[k];     \
+    return ORACLE_OK;                                                          \
+  }
+
+DEFINE_POSTPROCESS(oracle_postprocess_f64, double)
+DEFINE_POSTPROCESS(oracle_postprocess_f32, float)

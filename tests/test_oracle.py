@@ -326,6 +326,79 @@ def test_backward_definition_fd_and_scatter():
     assert s.grad.numpy().tobytes() == g.tobytes()
 
 
+def test_backward_of_unstored_pairs_is_zero():
+    # a triplet whose pair is not stored (slot -1) moves no stored value
+    ii = np.array([1, 1, 2, 3], dtype=np.int32)
+    jj = np.array([1, 1, 1, 2], dtype=np.int32)
+    ss = np.array([1.0, -1.0, 5.0, 2.0])
+    r = oracle.drop_zeros(oracle.assemble(ii, jj, ss))
+    np.testing.assert_array_equal(r.slot, [-1, -1, 0, 1])
+    g = oracle.backward(r.slot, np.array([3.0, 7.0]))
+    assert g.tobytes() == np.array([0.0, 0.0, 3.0, 7.0]).tobytes()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_backward_with_dropped_pairs_against_autograd(seed):
+    # loss = sum(w * kept prS): torch autograd through a scatter into every
+    # distinct pair followed by the selection of the kept ones
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(seed)
+    L, m, n = 300, 9, 7
+    ii = rng.integers(1, m + 1, L).astype(np.int32)
+    jj = rng.integers(1, n + 1, L).astype(np.int32)
+    ss = rng.integers(-2, 3, L).astype(np.float64)     # many zero sums
+    full = oracle.assemble(ii, jj, ss, m, n)
+    kept = oracle.drop_zeros(full)
+    assert 0 < kept.nnz < full.nnz
+    w = rng.standard_normal(kept.nnz)
+    s = torch.tensor(ss, requires_grad=True)
+    p = torch.zeros(full.nnz, dtype=torch.float64).index_add(
+        0, torch.from_numpy(full.slot.astype(np.int64)), s)
+    keep = torch.from_numpy(full.prS != 0)
+    (torch.from_numpy(w) * p[keep]).sum().backward()
+    assert s.grad.numpy().tobytes() == oracle.backward(kept.slot, w).tobytes()
+
+
+# ---------------------------------------------------------------------------
+# post-processing from a slot map (the value pass of the serial code)
+# ---------------------------------------------------------------------------
+def test_postprocess_worked_example():
+    # the printed irank of Section 2.3.4 and the example's values give the
+    # printed prS of eq. (2.1)
+    pr = oracle.postprocess(i32(EX["example_irank"]), EX["example_s"],
+                            len(EX["prS"]))
+    np.testing.assert_array_equal(pr, EX["prS"])
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("seed", range(6))
+def test_postprocess_equals_assembly(dtype, seed):
+    # the k loop over a zeroed prS against the sort-and-sweep assembly, for
+    # the values of the assembly and for new values on the same pattern;
+    # magnitudes from 1e-8 to 1e8 make any other summation order show
+    rng = np.random.default_rng(seed)
+    L = int(rng.integers(1, 5000))
+    m, n = int(rng.integers(1, 40)), int(rng.integers(1, 40))
+    ii = rng.integers(1, m + 1, L).astype(np.int32)
+    jj = rng.integers(1, n + 1, L).astype(np.int32)
+    for _ in range(2):
+        ss = (rng.standard_normal(L) * 10.0 ** rng.integers(-8, 9, L)
+              ).astype(dtype)
+        r = oracle.assemble(ii, jj, ss, m, n)
+        assert oracle.postprocess(r.slot, ss, r.nnz).tobytes() == \
+            r.prS.tobytes()
+        s2 = (ss * dtype(-0.5) + dtype(1.0)).astype(dtype)
+        assert oracle.postprocess(r.slot, s2, r.nnz).tobytes() == \
+            oracle.reassemble(r, ii, jj, s2).tobytes()
+
+
+def test_postprocess_rejects_slots_out_of_range():
+    with pytest.raises(ValueError):
+        oracle.postprocess(np.array([0, 2], dtype=np.int32), np.ones(2), 2)
+    with pytest.raises(ValueError):
+        oracle.postprocess(np.array([0, -1], dtype=np.int32), np.ones(2), 2)
+
+
 # ---------------------------------------------------------------------------
 # index expansion (Section 2.1 mentions it; the reading is broadcasting)
 # ---------------------------------------------------------------------------
