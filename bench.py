@@ -1,17 +1,29 @@
 #!/usr/bin/env python3
 """Throughput of Matlab-compatible sparse assembly on one MI355X.
 
-A step is one fresh assembly S = sparse(ii, jj, ss, m, n) of the workload
-(validation, column histogram, look-back scan, bucket scatter, and the chunk
-kernel that groups, ranks, orders and folds), inputs resident in HBM.  The
-same run also times, on the same workload, pattern re-use (one HIP-graph
-replay of the ordered fold), the atomic re-use variant and the backward
-gather, and reports them under "modes".
+A step is one fresh assembly of the workload, inputs resident in HBM: by
+default the 64 independent 2D P1 meshes of batched_64 (175M triplets) in one
+batched call -- validation, bin counts, look-back scans, the bin scatter and
+the bin kernel that groups, ranks, orders and folds.  `value` = triplets
+assembled per second (Gtriplets/s) over the K timed steps.
 
-Prints ONE JSON line.  `value` = triplets assembled per second (Gtriplets/s)
-over the K timed steps.  The dominant kernel's roofline uses its algorithmic
-bytes per launch divided by its average HIP-event duration, measured on the
-launch stream inside the timed region.
+The same run reports, under "modes": the graph-replayed pattern re-use of
+the batch; on fem3d_100 (93M triplets) the fresh call, 100 time steps of
+re-assembly with new per-element factors (the value update untimed), the
+order-free re-use and the backward gather; and on uniform_1e7 the fresh call
+and its re-use.  `--config NAME` benchmarks one workload instead, with the
+other calls on it (double indices, drop zeros, delayed assembly, complex and
+logical values, index expansion).
+
+Roofline: algorithmic bytes are those of the method, triplets in and CCS out
+(fresh fp64: 16 L + 12 nnz + 4 (n+1) summed over the matrices; re-use and
+backward: 12 L + 8 nnz), divided by the dominant kernel's average HIP-event
+duration on its launch stream inside the timed region, against the 8 TB/s
+HBM3E peak.  The whole call's fraction and the counter traffic (rocprofv3
+FETCH_SIZE + WRITE_SIZE of the committed profiles, when taken on the current
+kernel source) stand beside it.
+
+Prints ONE JSON line.
 """
 import argparse
 import hashlib
@@ -40,39 +52,28 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def stage_bytes(stage, L, nnz, n, vb, eb, plan=False, slot=False):
-    """Algorithmic bytes of one launch of a stage: every array the stage
-    must read or write, touched once.  eb = bytes of one binned triplet
-    (row and in-bin column in one word, k, value), vb = bytes of one value.
-    (Inputs whose rows and in-bin columns do not share a word add a 4-byte
-    column per triplet to the scatter and the bin kernel; none of the
-    configured workloads does.)"""
-    if stage == "count":
-        return 4 * L
-    if stage == "scatter":
-        return (8 + vb) * L + eb * L
-    if stage == "bin":
-        b = eb * L + (4 + vb) * nnz + 4 * (n + 1)
-        if slot:
-            b += 4 * L
-        if plan:
-            b += 4 * L + 4 * (nnz + 1)
-        return b
-    if stage == "reuse":
-        return 4 * L + 4 * (nnz + 1) + vb * L + vb * nnz
-    if stage == "backward":
-        return 4 * L + vb * nnz + vb * L
-    return None
+def fresh_bytes(L, nnz, ncols, nmat, vb):
+    """Bytes fresh assembly must move: triplets in (two int32 indices and a
+    value each), CCS out (row and value per pair, n+1 column pointers per
+    matrix)."""
+    return (8 + vb) * L + (4 + vb) * nnz + 4 * (ncols + nmat)
 
 
-def path_bytes(L, nnz, n, vb):
-    """Bytes the fresh assembly must move: triplets in, CCS out."""
-    return (8 + vb) * L + (4 + vb) * nnz + 4 * (n + 1)
+def reuse_bytes(L, nnz, vb):
+    """Re-use and backward: values in and the k -> slot map (4 B) per
+    triplet, values out per pair (fp64: 12 L + 8 nnz)."""
+    return (4 + vb) * L + vb * nnz
 
 
-def read_traffic(workload, kernel):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if
-    they were taken on the current kernel source."""
+def backward_bytes(L, nnz, vb):
+    """Backward: slot and gradient out per triplet, gradient in per pair."""
+    return (4 + vb) * L + vb * nnz
+
+
+def read_traffic(workload, kernel=None):
+    """HBM bytes per launch of a stage (or, with kernel None, per call: all
+    the call's kernels) from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel source."""
     path = os.path.join(PROFILE_DIR, "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
@@ -82,27 +83,37 @@ def read_traffic(workload, kernel):
         return None
     if d.get("kernel_hash") != kernel_hash():
         return None
-    k = d.get("kernels", {}).get(kernel)
+    ks = d.get("kernels", {})
+    if kernel is None:
+        tot = d.get("bytes_per_call")
+        return tot if tot else None
+    k = ks.get(kernel)
     if not k:
         return None
     return k.get("bytes_per_launch")
 
 
-def cpu_baseline(t, seconds):
-    import numpy as np  # noqa: F401
+def cpu_baseline(mats, seconds, name):
+    """The oracle, one host thread, on the full input of the workload (every
+    matrix), repeated until `seconds` have passed."""
     import oracle
-    oracle.assemble(t.ii[:1000], t.jj[:1000], t.ss[:1000], t.m, t.n)  # load
+    t0_ = mats[0]
+    oracle.assemble(t0_.ii[:1000], t0_.jj[:1000], t0_.ss[:1000], t0_.m, t0_.n)
+    L = sum(t.L for t in mats)
     reps, el = 0, 0.0
     while reps == 0 or el < seconds:
         t0 = time.perf_counter()
-        oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
+        for t in mats:
+            oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
         el += time.perf_counter() - t0
         reps += 1
         log("oracle rep %d: %.2f s total" % (reps, el))
-    return {"value": t.L * reps / el / 1e9, "unit": "Gtriplets/s", "cores": 1,
+    return {"value": L * reps / el / 1e9, "unit": "Gtriplets/s", "cores": 1,
             "kind": "oracle",
-            "sample": "full %s input (L=%d), %d repetitions, %.1f s, one "
-                      "thread" % (t.name, t.L, reps, el)}
+            "sample": "full %s input (%d matrices, L=%d), %d repetition%s, "
+                      "%.1f s, one thread" % (name, len(mats), L, reps,
+                                              "" if reps == 1 else "s", el),
+            "host_cpu": host_cpu()}
 
 
 def stage_profile(fs, torch, step, steps):
@@ -116,16 +127,83 @@ def stage_profile(fs, torch, step, steps):
     return stages, max(stages, key=stages.get)
 
 
+def time_fresh(fs, torch, step, steps, warmup):
+    """Warm-up, the stage profile, then exactly `steps` timed calls between
+    two synchronisations, with events only around the dominant stage's
+    launches (on the stream they are launched on).  Returns the last result,
+    seconds for the timed calls, the stage times and the dominant stage with
+    its average launch time in ms."""
+    r = None
+    for _ in range(max(1, warmup)):
+        r = step()
+    torch.cuda.synchronize()
+    stages, dom = stage_profile(fs, torch, step, steps)
+    with fs.timing(stages=[dom]) as tm:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    return r, el, stages, dom, tm.ms[dom] / tm.launches[dom]
+
+
+def time_events(torch, fn, steps, warmup=3):
+    """ms per call of stream-ordered work (no host waits inside), by events
+    on the current stream around `steps` calls."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def rate(L, ms, nbytes=None, unit="Gtriplets/s"):
+    r = {"value": L / (ms * 1e-3) / 1e9, "unit": unit, "ms": ms}
+    if nbytes:
+        r["bytes"] = nbytes
+        r["gbps"] = nbytes / (ms * 1e-3) / 1e9
+        r["frac"] = r["gbps"] / HBM_PEAK_GBS
+    return r
+
+
+def roofline(nbytes, dom, dom_ms, workload):
+    achieved = nbytes / (dom_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": read_traffic(workload, dom),
+            "algorithmic_bytes": nbytes, "avg_launch_ms": dom_ms}
+
+
+def tune(fs, args, *a, **kw):
+    if args.no_autotune:
+        fs.set_tuning(reset=True)
+        return None
+    from paper_1406_1066_amd import autotune
+    tuned = autotune.tune(*a, **kw)
+    log("tuning", tuned["best"], "(cached)" if tuned["cached"] else "")
+    return tuned["best"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="uniform_1e7")
+    ap.add_argument("--config", default="batched_64")
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--time-steps", type=int, default=100,
+                    help="re-assembly steps of the fem3d_100 time-stepping row")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 1 GiB copy kernel (counter calibration)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -142,12 +220,6 @@ def main():
     import numpy as np
     import torch
 
-    # tuning choices are cached per device and input class; keep the cache
-    # where every process of this machine finds it
-    import tempfile
-    os.environ.setdefault("FSPARSE_TUNE_CACHE",
-                          os.path.join(tempfile.gettempdir(),
-                                       "fsparse_mi355x_tune.json"))
     import paper_1406_1066_amd as fs
     import workloads as W
 
@@ -159,141 +231,261 @@ def main():
 
     vt = np.float64 if args.dtype == "f64" else np.float32
     vb = 8 if vt == np.float64 else 4
-    eb = 16 if vt == np.float64 else 12
     log("building workload", args.config)
     t = W.config(args.config, dtype=vt)
     if isinstance(t, W.Batch):
-        return bench_batched(args, t, fs, torch, np, vb, eb)
+        line = bench_batched(args, t, fs, torch, np, vb)
+        mats = t.mats
+    else:
+        line = bench_single(args, t, fs, torch, np, vb)
+        mats = [t]
+    if not args.no_modes and args.config == "batched_64":
+        # the other legs of the metric on the other workloads
+        torch.cuda.empty_cache()
+        line["modes"]["fem3d_100"] = mesh_steps(args, fs, torch, np, W, vt, vb)
+        torch.cuda.empty_cache()
+        line["modes"]["uniform_1e7"] = uniform_row(args, fs, torch, W, vt, vb)
+    if not args.no_modes:
+        line["copy_gbps"] = copy_bw(fs, torch)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(mats, args.cpu_seconds,
+                                            args.config)
+    print(json.dumps(line), flush=True)
+
+
+def header(args, value, el):
+    return {"metric": METRIC, "value": value, "unit": "Gtriplets/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
+            "data": "synthetic"}
+
+
+def bench_batched(args, batch, fs, torch, np, vb):
+    """Headline: one batched fresh assembly of all matrices per step, then
+    the graph-replayed re-use of the batch."""
+    dev = torch.device("cuda", 0)
+    ii, jj, ss, m, n = batch.concat()
+    off = batch.trip_off
+    L, nb, N = batch.L, batch.nb, int(n.sum())
+    iid = torch.from_numpy(ii).to(dev)
+    jjd = torch.from_numpy(jj).to(dev)
+    ssd = torch.from_numpy(ss).to(dev)
+    del ii, jj, ss
+    tuning = tune(fs, args, iid, jjd, ssd, list(m), list(n), trip_off=off)
+    ws = torch.empty(fs.workspace_bytes(L, N, nb, ssd.dtype),
+                     dtype=torch.uint8, device=dev)
+
+    def step():
+        return fs.assemble_batched(iid, jjd, ssd, off, m, n, ws=ws)
+
+    log("timed steps", args.steps)
+    r, el, stages, dom, dom_ms = time_fresh(fs, torch, step, args.steps,
+                                            args.warmup)
+    nnz = r.nnz
+    fb = fresh_bytes(L, nnz, N, nb, vb)
+    line = header(args, L * args.steps / el / 1e9, el)
+    line["config"] = {"workload": args.config, "L": L, "nb": nb, "nnz": nnz,
+                      "ncols": N, "mode": "batched fresh"}
+    line["roofline"] = roofline(fb, dom, dom_ms, args.config)
+    tc = read_traffic(args.config)
+    line["path"] = {"bytes": fb, "ms": el / args.steps * 1e3,
+                    "frac": fb / (el / args.steps) / 1e9 / HBM_PEAK_GBS,
+                    "traffic": tc, "traffic_ratio": tc / fb if tc else None}
+    line["stages_ms"] = stages
+    line["tuning"] = tuning or fs.get_tuning()
+    line["modes"] = {}
+    if not args.no_modes:
+        rp = fs.assemble_batched(iid, jjd, ssd, off, m, n, plan=True)
+        outp = torch.empty(nnz, dtype=ssd.dtype, device=dev)
+        ms = time_events(torch, lambda: fs.reassemble(rp, ssd, out=outp),
+                         args.steps)
+        line["modes"]["batched_reuse"] = rate(L, ms, reuse_bytes(L, nnz, vb))
+        log("batched reuse %.4f ms" % ms)
+        del rp, outp
+    return line
+
+
+def mesh_steps(args, fs, torch, np, W, vt, vb):
+    """fem3d_100: fresh assembly, then the time-stepping shape -- re-use
+    with new values scaled per element by U[0.5, 2] every step (the update
+    untimed), order-free re-use, the backward gather and the fresh call
+    from connectivity and element matrices (index expansion)."""
+    dev = torch.device("cuda", 0)
+    t = W.config("fem3d_100", dtype=vt)
+    ii = torch.from_numpy(t.ii).to(dev)
+    jj = torch.from_numpy(t.jj).to(dev)
+    ss = torch.from_numpy(t.ss).to(dev)
+    L, m, n = t.L, t.m, t.n
+    tune(fs, args, ii, jj, ss, m, n)
+    ws = torch.empty(fs.workspace_bytes(L, n, 1, ss.dtype), dtype=torch.uint8,
+                     device=dev)
+    out = (torch.empty(n + 1, dtype=torch.int32, device=dev),
+           torch.empty(L, dtype=torch.int32, device=dev),
+           torch.empty(L, dtype=ss.dtype, device=dev))
+
+    def step():
+        return fs.sparse(ii, jj, ss, m, n, ws=ws, out=out)
+
+    r, el, stages, dom, dom_ms = time_fresh(fs, torch, step, args.steps,
+                                            args.warmup)
+    nnz = r.nnz
+    fb = fresh_bytes(L, nnz, n, 1, vb)
+    row = {"L": L, "nnz": nnz}
+    row["fresh"] = rate(L, el / args.steps * 1e3, fb)
+    row["fresh"]["roofline"] = roofline(fb, dom, dom_ms, "fem3d_100")
+    row["fresh"]["stages_ms"] = stages
+    log("fem3d_100 fresh %.4f ms" % row["fresh"]["ms"])
+    del ws, out, r
+    res = fs.sparse(ii, jj, ss, m, n, plan=True, keep_slot=True)
+    prS = torch.empty(nnz, dtype=ss.dtype, device=dev)
+    # time steps: new per-element factors each step, the update outside the
+    # events around each re-use
+    ne = L // t.per_elem
+    g = torch.Generator(device=dev)
+    s_t = torch.empty_like(ss)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    u0 = torch.cuda.Event(enable_timing=True)
+    rms, ums = 0.0, 0.0
+    for _ in range(3):
+        fs.reassemble(res, ss, out=prS)
+    for stp in range(args.time_steps):
+        g.manual_seed(1068 * 1000 + stp)
+        u0.record()
+        f = torch.rand(ne, dtype=ss.dtype, device=dev, generator=g) * 1.5 + 0.5
+        torch.mul(ss.view(ne, t.per_elem), f[:, None],
+                  out=s_t.view(ne, t.per_elem))
+        e0.record()
+        fs.reassemble(res, s_t, out=prS)
+        e1.record()
+        torch.cuda.synchronize()
+        rms += e0.elapsed_time(e1)
+        ums += u0.elapsed_time(e0)
+    rb = reuse_bytes(L, nnz, vb)
+    row["reuse_steps"] = rate(L, rms / args.time_steps, rb)
+    row["reuse_steps"]["steps"] = args.time_steps
+    row["reuse_steps"]["update_ms"] = ums / args.time_steps
+    log("fem3d_100 reuse step %.4f ms" % row["reuse_steps"]["ms"])
+    ms = time_events(torch, lambda: fs.reassemble(res, s_t, out=prS,
+                                                  atomic=True), args.steps)
+    row["reuse_atomic"] = rate(L, ms, rb)
+    gp = torch.randn(nnz, dtype=ss.dtype, device=dev)
+    gs = torch.empty(L, dtype=ss.dtype, device=dev)
+    ms = time_events(torch, lambda: fs.backward(res.slot, gp, out=gs),
+                     args.steps)
+    row["backward"] = rate(L, ms, backward_bytes(L, nnz, vb))
+    log("fem3d_100 atomic %.4f ms, backward %.4f ms"
+        % (row["reuse_atomic"]["ms"], ms))
+    del res, prS, gp, gs, s_t, ii, jj
+    torch.cuda.empty_cache()
+    row["expand"] = expanded(args, fs, torch, t, ss)
+    return row
+
+
+def uniform_row(args, fs, torch, W, vt, vb):
+    """uniform_1e7 (random triplets): fresh assembly and its re-use."""
+    dev = torch.device("cuda", 0)
+    t = W.config("uniform_1e7", dtype=vt)
+    ii = torch.from_numpy(t.ii).to(dev)
+    jj = torch.from_numpy(t.jj).to(dev)
+    ss = torch.from_numpy(t.ss).to(dev)
+    L, m, n = t.L, t.m, t.n
+    tune(fs, args, ii, jj, ss, m, n)
+    ws = torch.empty(fs.workspace_bytes(L, n, 1, ss.dtype), dtype=torch.uint8,
+                     device=dev)
+    out = (torch.empty(n + 1, dtype=torch.int32, device=dev),
+           torch.empty(L, dtype=torch.int32, device=dev),
+           torch.empty(L, dtype=ss.dtype, device=dev))
+    r, el, stages, dom, dom_ms = time_fresh(
+        fs, torch, lambda: fs.sparse(ii, jj, ss, m, n, ws=ws, out=out),
+        args.steps, args.warmup)
+    nnz = r.nnz
+    fb = fresh_bytes(L, nnz, n, 1, vb)
+    row = {"L": L, "nnz": nnz, "fresh": rate(L, el / args.steps * 1e3, fb)}
+    row["fresh"]["roofline"] = roofline(fb, dom, dom_ms, "uniform_1e7")
+    row["fresh"]["stages_ms"] = stages
+    res = fs.sparse(ii, jj, ss, m, n, plan=True)
+    prS = torch.empty(nnz, dtype=ss.dtype, device=dev)
+    ms = time_events(torch, lambda: fs.reassemble(res, ss, out=prS),
+                     args.steps)
+    row["reuse"] = rate(L, ms, reuse_bytes(L, nnz, vb))
+    log("uniform_1e7 fresh %.4f ms, reuse %.4f ms" % (row["fresh"]["ms"], ms))
+    return row
+
+
+def bench_single(args, t, fs, torch, np, vb):
+    """One workload: its fresh call as the step; re-use, order-free re-use,
+    backward and the other calls on the same input under "modes"."""
     dev = torch.device("cuda", 0)
     ii = torch.from_numpy(t.ii).to(dev)
     jj = torch.from_numpy(t.jj).to(dev)
     ss = torch.from_numpy(t.ss).to(dev)
     L, m, n = t.L, t.m, t.n
-    tuned = None
-    if not args.no_autotune:
-        from paper_1406_1066_amd import autotune
-        log("autotuning")
-        tuned = autotune.tune(ii, jj, ss, m, n)
-        log("tuning", tuned["best"], "cached" if tuned["cached"] else "")
+    tuning = tune(fs, args, ii, jj, ss, m, n)
     ws = torch.empty(fs.workspace_bytes(L, n, 1, ss.dtype), dtype=torch.uint8,
                      device=dev)
-    jcS = torch.empty(n + 1, dtype=torch.int32, device=dev)
-    irS = torch.empty(L, dtype=torch.int32, device=dev)
-    prS = torch.empty(L, dtype=ss.dtype, device=dev)
-    out = (jcS, irS, prS)
+    out = (torch.empty(n + 1, dtype=torch.int32, device=dev),
+           torch.empty(L, dtype=torch.int32, device=dev),
+           torch.empty(L, dtype=ss.dtype, device=dev))
 
     def step():
         return fs.sparse(ii, jj, ss, m, n, ws=ws, out=out)
 
-    log("warmup", args.warmup)
-    r = None
-    for _ in range(max(1, args.warmup)):
-        r = step()
-    nnz = r.nnz
-    torch.cuda.synchronize()
-    stages, dom = stage_profile(fs, torch, step, args.steps)
     log("timed steps", args.steps)
-    # events only around the dominant kernel's launches inside the timed
-    # region (events around every launch would add their own gaps)
-    with fs.timing(stages=[dom]) as tm:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-    el = t1 - t0
-    dom_ms = tm.ms[dom] / tm.launches[dom]
-    ab = stage_bytes(dom, L, nnz, n, vb, eb)
-    achieved = ab / (dom_ms * 1e-3) / 1e9
-    traffic = read_traffic(args.config, dom)
-    line = {
-        "metric": METRIC,
-        "value": L * args.steps / el / 1e9,
-        "unit": "Gtriplets/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": args.dtype,
-        "data": "synthetic",
-        "config": {"workload": args.config, "L": L, "m": m, "n": n,
-                   "nnz": nnz, "mode": "fresh"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes": ab,
-                     "avg_launch_ms": dom_ms},
-        "stages_ms": stages,
-        "tuning": fs.get_tuning(),
-        "path": {"bytes": path_bytes(L, nnz, n, vb),
-                 "frac": path_bytes(L, nnz, n, vb) / (el / args.steps)
-                 / 1e9 / HBM_PEAK_GBS},
-    }
-    if not args.no_modes:
-        line["modes"] = modes(args, fs, torch, ii, jj, ss, m, n, L, vb, eb)
-        if "conn" in t.meta:
-            line["modes"]["expand"] = expanded(args, fs, torch, t, ss, vb, eb)
-        line["modes"]["f64_index"] = double_indices(args, fs, torch, ii, jj,
-                                                    ss, m, n)
-        line["modes"]["drop_zeros"] = dropped(args, fs, torch, ii, jj, ss, m, n)
-        line["modes"]["append"] = appended(args, fs, torch, ii, jj, ss, m, n)
-        line["modes"]["complex"] = complexed(args, fs, torch, ii, jj, ss, m, n)
-        line["modes"]["logical"] = logical(args, fs, torch, ii, jj, ss, m, n)
-        line["copy_gbps"] = copy_bw(fs, torch)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(t, args.cpu_seconds)
-        line["cpu_baseline"]["host_cpu"] = host_cpu()
-    print(json.dumps(line), flush=True)
-
-
-def modes(args, fs, torch, ii, jj, ss, m, n, L, vb, eb):
+    r, el, stages, dom, dom_ms = time_fresh(fs, torch, step, args.steps,
+                                            args.warmup)
+    nnz = r.nnz
+    fb = fresh_bytes(L, nnz, n, 1, vb)
+    line = header(args, L * args.steps / el / 1e9, el)
+    line["config"] = {"workload": args.config, "L": L, "m": m, "n": n,
+                      "nnz": nnz, "mode": "fresh"}
+    line["roofline"] = roofline(fb, dom, dom_ms, args.config)
+    tc = read_traffic(args.config)
+    line["path"] = {"bytes": fb, "ms": el / args.steps * 1e3,
+                    "frac": fb / (el / args.steps) / 1e9 / HBM_PEAK_GBS,
+                    "traffic": tc, "traffic_ratio": tc / fb if tc else None}
+    line["stages_ms"] = stages
+    line["tuning"] = tuning or fs.get_tuning()
+    line["modes"] = {}
+    if args.no_modes:
+        return line
+    del ws, out, r
+    md = line["modes"]
     res = fs.sparse(ii, jj, ss, m, n, plan=True, keep_slot=True)
-    nnz = res.nnz
-    out = torch.empty(nnz, dtype=ss.dtype, device=ss.device)
-    g = torch.randn(nnz, dtype=ss.dtype, device=ss.device)
-    gs = torch.empty(L, dtype=ss.dtype, device=ss.device)
-    d = {}
-    for name, fn, nbytes in (
-            ("reuse", lambda: fs.reassemble(res, ss, out=out),
-             stage_bytes("reuse", L, nnz, n, vb, eb)),
-            ("reuse_atomic",
-             lambda: fs.reassemble(res, ss, out=out, atomic=True),
-             4 * L + vb * L + vb * nnz),
-            ("backward", lambda: fs.backward(res.slot, g, out=gs),
-             stage_bytes("backward", L, nnz, n, vb, eb)),
-            ("fresh_with_plan",
-             lambda: fs.sparse(ii, jj, ss, m, n, plan=True, keep_slot=True,
-                               ws=res.ws),
-             None),
-            ("fresh_plan_no_slot",
-             lambda: fs.sparse(ii, jj, ss, m, n, plan=True, ws=res.ws),
-             None)):
-        for _ in range(3):
-            fn()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.steps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
-        rec = {"value": L / (ms * 1e-3) / 1e9, "unit": "Gtriplets/s",
-               "ms": ms}
-        if nbytes:
-            rec["gbps"] = nbytes / (ms * 1e-3) / 1e9
-            rec["frac"] = rec["gbps"] / HBM_PEAK_GBS
-        d[name] = rec
-        log(name, "%.4f ms" % ms)
-    return d
+    prS = torch.empty(nnz, dtype=ss.dtype, device=dev)
+    rb = reuse_bytes(L, nnz, vb)
+    md["reuse"] = rate(L, time_events(
+        torch, lambda: fs.reassemble(res, ss, out=prS), args.steps), rb)
+    md["reuse_atomic"] = rate(L, time_events(
+        torch, lambda: fs.reassemble(res, ss, out=prS, atomic=True),
+        args.steps), rb)
+    gp = torch.randn(nnz, dtype=ss.dtype, device=dev)
+    gs = torch.empty(L, dtype=ss.dtype, device=dev)
+    md["backward"] = rate(L, time_events(
+        torch, lambda: fs.backward(res.slot, gp, out=gs), args.steps),
+        backward_bytes(L, nnz, vb))
+    md["fresh_with_plan"] = rate(L, time_events(
+        torch, lambda: fs.sparse(ii, jj, ss, m, n, plan=True, keep_slot=True,
+                                 ws=res.ws), args.steps))
+    md["fresh_plan_no_slot"] = rate(L, time_events(
+        torch, lambda: fs.sparse(ii, jj, ss, m, n, plan=True, ws=res.ws),
+        args.steps))
+    for k in ("reuse", "reuse_atomic", "backward", "fresh_with_plan",
+              "fresh_plan_no_slot"):
+        log(k, "%.4f ms" % md[k]["ms"])
+    del res, prS, gp, gs
+    if "conn" in t.meta:
+        md["expand"] = expanded(args, fs, torch, t, ss)
+    md["f64_index"] = double_indices(args, fs, torch, ii, jj, ss, m, n)
+    md["drop_zeros"] = dropped(args, fs, torch, ii, jj, ss, m, n)
+    md["append"] = appended(args, fs, torch, ii, jj, ss, m, n)
+    md["complex"] = complexed(args, fs, torch, ii, jj, ss, m, n)
+    md["logical"] = logical(args, fs, torch, ii, jj, ss, m, n)
+    return line
 
 
-def expanded(args, fs, torch, t, ss, vb, eb):
+def expanded(args, fs, torch, t, ss):
     """Fresh assembly from the element connectivity and element matrices
     (index expansion), with the launch shapes of the plain call."""
     conn = torch.from_numpy(t.meta["conn"]).to(ss.device)
@@ -491,77 +683,6 @@ def host_cpu():
     except OSError:
         pass
     return "nproc=%d" % os.cpu_count()
-
-
-def bench_batched(args, batch, fs, torch, np, vb, eb):
-    dev = torch.device("cuda", 0)
-    ii, jj, ss, m, n = batch.concat()
-    off = batch.trip_off
-    L = batch.L
-    iid = torch.from_numpy(ii).to(dev)
-    jjd = torch.from_numpy(jj).to(dev)
-    ssd = torch.from_numpy(ss).to(dev)
-    if not args.no_autotune:
-        from paper_1406_1066_amd import autotune
-        log("autotuning")
-        tuned = autotune.tune(iid, jjd, ssd, list(m), list(n), trip_off=off)
-        log("tuning", tuned["best"], "cached" if tuned["cached"] else "")
-    ws = torch.empty(fs.workspace_bytes(L, int(n.sum()), batch.nb, ssd.dtype),
-                     dtype=torch.uint8, device=dev)
-
-    def step():
-        return fs.assemble_batched(iid, jjd, ssd, off, m, n, ws=ws)
-
-    r = None
-    for _ in range(max(1, args.warmup)):
-        r = step()
-    torch.cuda.synchronize()
-    stages, dom = stage_profile(fs, torch, step, args.steps)
-    with fs.timing(stages=[dom]) as tm:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-    dom_ms = tm.ms[dom] / tm.launches[dom]
-    nnz, N = r.nnz, int(n.sum())
-    ab = stage_bytes(dom, L, nnz, N, vb, eb)
-    achieved = ab / (dom_ms * 1e-3) / 1e9
-    rp = fs.assemble_batched(iid, jjd, ssd, off, m, n, plan=True)
-    outp = torch.empty(nnz, dtype=ssd.dtype, device=dev)
-    for _ in range(3):
-        fs.reassemble(rp, ssd, out=outp)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        fs.reassemble(rp, ssd, out=outp)
-    e1.record()
-    torch.cuda.synchronize()
-    rms = e0.elapsed_time(e1) / args.steps
-    line = {
-        "metric": METRIC, "value": L * args.steps / el / 1e9,
-        "unit": "Gtriplets/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": args.config, "L": L, "nb": batch.nb,
-                   "nnz": nnz, "mode": "batched"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": read_traffic(args.config, dom),
-                     "algorithmic_bytes": ab, "avg_launch_ms": dom_ms},
-        "stages_ms": stages,
-        "tuning": fs.get_tuning(),
-        "modes": {"reuse": {"value": L / (rms * 1e-3) / 1e9, "ms": rms,
-                            "unit": "Gtriplets/s",
-                            "frac": stage_bytes("reuse", L, nnz, N, vb, eb)
-                            / (rms * 1e-3) / 1e9 / HBM_PEAK_GBS}},
-    }
-    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -18,8 +18,8 @@
  *    comes from the caller's workspace `ws`.
  *  - Work is stream-ordered on `stream`.  Only fsparse_assemble,
  *    fsparse_assemble_batched and fsparse_dims wait for the stream (once, to
- *    read back result sizes and the error flags); re-assembly and backward
- *    never synchronise.
+ *    read back result sizes and the error flags), and fsparse_assemble does
+ *    not with FSPARSE_NO_SYNC; re-assembly and backward never synchronise.
  *  - Values are IEEE binary64 (FSPARSE_F64) or binary32 (FSPARSE_F32); the sum
  *    of a repeated pair is computed in that type.
  *  - In the default ordered mode the contributions to prS[t] are added from
@@ -52,7 +52,8 @@ typedef enum { FSPARSE_F64 = 0, FSPARSE_F32 = 1 } fsparse_dtype;
 enum {
   FSPARSE_ORDERED = 0u,    /* increasing-k fold, bit-exact (default)       */
   FSPARSE_ATOMIC = 1u,     /* device atomics, order unspecified            */
-  FSPARSE_DROP_ZEROS = 2u  /* fresh calls: remove pairs whose sum is zero  */
+  FSPARSE_DROP_ZEROS = 2u, /* fresh calls: remove pairs whose sum is zero  */
+  FSPARSE_NO_SYNC = 4u     /* fresh calls: queue the work, do not wait     */
 };
 
 typedef enum {
@@ -128,7 +129,24 @@ fsparse_status fsparse_dims(const int32_t *ii, const int32_t *jj, int64_t len,
  *           starts) and to slot; those buffers must outlive the plan and must
  *           not be reused for another call while the plan is in use.
  *  info     host out, may be NULL.
- * Waits for the stream once (to read nnz and the error flags).
+ * Waits for the stream once (to read nnz and the error flags), except with
+ * FSPARSE_NO_SYNC:
+ *  - The call queues its work on `stream` and returns FSPARSE_OK without
+ *    waiting, so it can be issued ahead of later work (and from code that
+ *    must not block).  Index and capacity errors are not known yet: they,
+ *    and nnz, stay in the control block at the start of ws, and
+ *    fsparse_assemble_status(ws, ...) reports them once the stream gets
+ *    there; nnz is also jcS[n].  info->nnz is set to -1.
+ *  - m and n must be given (the defaults take a wait), cap must be at least
+ *    len (so no capacity retry can be needed: E_CAPACITY otherwise, with
+ *    info->nnz = len), and FSPARSE_DROP_ZEROS is refused (E_ARG; the kept
+ *    count is read back between two passes).
+ *  - Triplets are placed in counted bins (the one-pass fixed-capacity bins
+ *    may overflow, which needs a redo that the host decides).
+ *  - A plan may be made; it reads nnz from ws where it needs it, and
+ *    fsparse_plan_query reads it back with a blocking copy.
+ * The same flag works for fsparse_assemble_f64idx, fsparse_assemble_expand
+ * and fsparse_assemble_complex.
  */
 fsparse_status fsparse_assemble(const int32_t *ii, const int32_t *jj,
                                 const void *ss, fsparse_dtype dt, int64_t len,
@@ -138,6 +156,30 @@ fsparse_status fsparse_assemble(const int32_t *ii, const int32_t *jj,
                                 int32_t *slot, void *ws, size_t ws_bytes,
                                 fsparse_plan **plan, fsparse_info *info,
                                 hipStream_t stream);
+
+/*
+ * Status of a call made with FSPARSE_NO_SYNC on workspace ws: waits for
+ * `stream`, then returns FSPARSE_E_INDEX (an index below 1 or beyond m/n),
+ * FSPARSE_E_CAPACITY, or FSPARSE_OK, and sets info->nnz (may be NULL) to the
+ * number of distinct pairs.  Only info->nnz is written.
+ */
+fsparse_status fsparse_assemble_status(const void *ws, fsparse_info *info,
+                                       hipStream_t stream);
+
+/*
+ * Index arrays of a wider integer type narrowed to the int32 the calls take
+ * (the validation of the pre-processing, Section 2.2, for integer input):
+ * dst[k] = src[k] when 1 <= src[k] <= 2^31 - 1, else 0, which every call
+ * then rejects with FSPARSE_E_INDEX as an index below 1 (an out-of-range
+ * value never wraps into range).
+ *  src       [len] device, of type src_type
+ *  dst       [len] device int32 out (not overlapping src)
+ * Never waits.
+ */
+enum { FSPARSE_IDX_I64 = 0, FSPARSE_IDX_U32 = 1, FSPARSE_IDX_U64 = 2 };
+fsparse_status fsparse_indices_i32(const void *src, int32_t src_type,
+                                   int64_t len, int32_t *dst,
+                                   hipStream_t stream);
 
 /*
  * Complex values (Matlab compatibility, Section 1).  Matlab's classic
@@ -323,8 +365,11 @@ fsparse_status fsparse_assemble_reuse(fsparse_plan *plan, const void *ss,
  * prS[t] = sum of ss[k] over slot[k] = t, so d prS[t] / d ss[k] = [slot[k]=t]
  * and
  *      grad_ss[k] = grad_prS[slot[k]],   k = 0..len-1.
- * slot [len] int32 values in [0, nnz); grad_prS [nnz], grad_ss [len] of dt.
- * Never waits.
+ * slot [len] int32 values in [0, nnz), or -1 for a triplet whose pair is not
+ * stored (dropped zero sums, logical pairs without a true triplet): no
+ * stored value depends on it, so grad_ss[k] = 0.  Any other value outside
+ * [0, nnz) also gives 0 and reads nothing.  grad_prS [nnz], grad_ss [len]
+ * of dt; nnz = 0 is allowed (every gradient is then 0).  Never waits.
  */
 fsparse_status fsparse_backward(const int32_t *slot, int64_t len,
                                 const void *grad_prS, int64_t nnz,
@@ -372,10 +417,13 @@ fsparse_status fsparse_dims_batched(int32_t nb, const int64_t *trip_off,
                                     size_t ws_bytes, hipStream_t stream);
 
 /* Release a plan (host memory and its graph only; device buffers are the
- * caller's).  NULL is ignored. */
+ * caller's).  Waits for the plan's latest re-assembly launch to finish
+ * first.  NULL is ignored. */
 void fsparse_plan_destroy(fsparse_plan *plan);
 
-/* Sizes a plan was made for (any pointer may be NULL). */
+/* Sizes a plan was made for (any pointer may be NULL).  For a plan made
+ * with FSPARSE_NO_SYNC, nnz is read back from the workspace (a blocking
+ * copy). */
 fsparse_status fsparse_plan_query(const fsparse_plan *plan, int64_t *len,
                                   int64_t *nnz, int32_t *dtype);
 

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FSPARSE_LIBRARY") or os.path.join(HERE, "libfsparse.so")
 
 F64, F32 = 0, 1
-ORDERED, ATOMIC, DROP_ZEROS = 0, 1, 2
+ORDERED, ATOMIC, DROP_ZEROS, NO_SYNC = 0, 1, 2, 4
+IDX_I64, IDX_U32, IDX_U64 = 0, 1, 2
 OK, E_INDEX, E_ARG, E_CAPACITY, E_PLAN, E_HIP = range(6)
 
 
@@ -130,6 +131,10 @@ fsparse_timing_read = _sig("fsparse_timing_read", ctypes.c_int,
 fsparse_stage_name = _sig("fsparse_stage_name", ctypes.c_char_p, [ctypes.c_int])
 fsparse_stream_copy = _sig("fsparse_stream_copy", _st,
                            [_vp, _vp, ctypes.c_size_t, _vp])
+fsparse_assemble_status = _sig("fsparse_assemble_status", _st,
+                               [_vp, ctypes.POINTER(FsparseInfo), _vp])
+fsparse_indices_i32 = _sig("fsparse_indices_i32", _st,
+                           [_vp, _i32, _i64, _vp, _vp])
 
 EXPORTS = [
     "fsparse_version", "fsparse_status_string", "fsparse_workspace_bytes",
@@ -144,5 +149,5 @@ EXPORTS = [
     "fsparse_plan_query", "fsparse_set_tuning", "fsparse_get_tuning",
     "fsparse_timing_enable", "fsparse_timing_read", "fsparse_stage_name",
     "fsparse_timing_select",
-    "fsparse_stream_copy",
+    "fsparse_stream_copy", "fsparse_assemble_status", "fsparse_indices_i32",
 ]

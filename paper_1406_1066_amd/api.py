@@ -82,22 +82,53 @@ def _is_float_index(x) -> bool:
     return _as_tensor(x).dtype.is_floating_point
 
 
+_WIDE = {torch.int64: L.IDX_I64}
+for _name, _code in (("uint32", L.IDX_U32), ("uint64", L.IDX_U64)):
+    if hasattr(torch, _name):
+        _WIDE[getattr(torch, _name)] = _code
+
+
 def _dev_i32(x, device) -> torch.Tensor:
-    """Integer indices as contiguous int32 on the device.  A value that int32
-    cannot hold becomes 0, which the library rejects as an index below 1
-    (instead of wrapping into range)."""
+    """Integer indices as contiguous int32 on the device.  Wider types are
+    narrowed by the library (fsparse_indices_i32), which turns a value that
+    int32 cannot hold into 0, rejected later as an index below 1 (instead of
+    wrapping into range); narrower types convert exactly."""
     if (isinstance(x, torch.Tensor) and x.dtype == torch.int32 and
             x.device == device and x.is_contiguous()):
         return x
     t = _as_tensor(x)
-    if t.dtype.is_floating_point or t.dtype.is_complex:
+    if t.dtype.is_floating_point or t.dtype.is_complex or t.dtype == torch.bool:
         raise TypeError("integer index arrays expected here, got %s" % t.dtype)
-    t = t.to(device)
-    if t.dtype != torch.int32:
-        if t.dtype in (torch.int64, torch.uint32, torch.uint64):
-            t = torch.where((t < 1) | (t > 2**31 - 1), torch.zeros_like(t), t)
-        t = t.to(torch.int32)
-    return t.contiguous()
+    t = t.to(device).contiguous()
+    if t.dtype == torch.int32:
+        return t
+    code = _WIDE.get(t.dtype)
+    if code is None:                      # int8, int16, uint8: exact
+        return t.to(torch.int32).contiguous()
+    out = torch.empty(t.shape, dtype=torch.int32, device=device)
+    _check(L.fsparse_indices_i32(_ptr(t), code, t.numel(), _ptr(out),
+                                 _stream()), "fsparse_indices_i32")
+    return out
+
+
+def _need(t: Optional[torch.Tensor], name: str, numel: int, dtype=None,
+          device=None):
+    """A caller-supplied buffer that a call without capacity arguments will
+    write or read: it must be a GPU tensor of the given type, contiguous,
+    with at least ``numel`` elements (checked before anything is queued)."""
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % name)
+    if device is not None and t.device != device:
+        raise ValueError("%s is on %s, expected %s" % (name, t.device, device))
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < numel:
+        raise ValueError("%s holds %d elements, needs %d"
+                         % (name, t.numel(), numel))
 
 
 def _dev_f64(x, device) -> torch.Tensor:
@@ -167,9 +198,32 @@ class Assembled:
     plan: Optional["_Plan"] = None
     ws: Optional[torch.Tensor] = field(default=None, repr=False)
     piS: Optional[torch.Tensor] = None     # imaginary sums (complex values)
+    # queued with wait=False: nnz is -1 and irS/prS hold the full capacity
+    # until wait() reads the status back
+    pending: bool = False
+
+    def wait(self) -> "Assembled":
+        """Status and nnz of a call made with wait=False (waits for the
+        stream); raises like the waiting call would."""
+        if not self.pending:
+            return self
+        info = L.FsparseInfo()
+        _check(L.fsparse_assemble_status(_ptr(self.ws), ctypes.byref(info),
+                                         _stream()), "fsparse_assemble_status")
+        nnz = int(info.nnz)
+        self.nnz = nnz
+        self.nzmax = max(self.nzmax, nnz)
+        self.irS = self.irS[:nnz]
+        self.prS = self.prS[:nnz]
+        if self.piS is not None:
+            self.piS = self.piS[:nnz]
+        if self.plan is not None:
+            self.plan.nnz = nnz
+        self.pending = False
+        return self
 
     def to_dense(self) -> torch.Tensor:
-        return to_torch_csc(self).to_dense()
+        return to_torch_csc(self.wait()).to_dense()
 
 
 class _Plan:
@@ -201,7 +255,7 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
            cap: Optional[int] = None,
            ws: Optional[torch.Tensor] = None,
            out: Optional[tuple] = None,
-           drop_zeros: bool = False) -> Assembled:
+           drop_zeros: bool = False, wait: bool = True) -> Assembled:
     """S = sparse(ii, jj, ss, m, n, nzmax) on the GPU.
 
     ``ii``/``jj`` unit-offset indices: integer arrays (converted to int32 on
@@ -215,6 +269,8 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
     preallocated output buffers (irS/prS capacity = their length).
     ``drop_zeros`` removes the pairs whose sum is zero, as Matlab stores no
     zeros (the slot of a dropped pair's triplets is -1; no plan then).
+    ``wait=False`` queues the call without waiting (FSPARSE_NO_SYNC; m and n
+    must be given): the result's nnz is -1 until ``result.wait()``.
     """
     dev = _device(ss, ii, jj)
     ss = ss.contiguous()
@@ -235,28 +291,37 @@ def sparse(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
     def call(*a):
         return fn(_ptr(ii), _ptr(jj), _ptr(ss), _dt(ss.dtype), Ln, *a)
     return _fresh(call, Ln, int(m), int(n), ss, dev, nzmax, atomic, keep_slot,
-                  plan, cap, ws, out, "fsparse_assemble", drop_zeros)
+                  plan, cap, ws, out, "fsparse_assemble", drop_zeros,
+                  wait=wait)
 
 
 def _fresh(call, Ln, m, n, ss, dev, nzmax, atomic, keep_slot, plan, cap, ws,
-           out, name, drop_zeros=False, ws_need=None) -> Assembled:
+           out, name, drop_zeros=False, ws_need=None, wait=True) -> Assembled:
     """Output buffers and the capacity / workspace retry around one fresh
     assembly call ``call(m, n, nzmax, flags, jcS, jcS_cap, irS, prS, cap,
     slot, ws, ws_bytes, plan_out, info, stream)``."""
     if drop_zeros and plan:
         raise ValueError("drop_zeros: the pattern depends on the values, "
                          "so no re-use plan can be made")
+    if not wait and drop_zeros:
+        raise ValueError("drop_zeros reads the kept count back: it waits")
     flags = (L.ATOMIC if atomic else L.ORDERED) | (
-        L.DROP_ZEROS if drop_zeros else 0)
+        L.DROP_ZEROS if drop_zeros else 0) | (0 if wait else L.NO_SYNC)
     if ws_need is None:
         ws_need = lambda: workspace_bytes(Ln, n, 1, ss.dtype)  # noqa: E731
     if ws is None:
         ws = _workspace(ws_need(), dev)
     slot = None
+    if ws is not None:
+        _need(ws, "ws", 0, torch.uint8, dev)
     if out is not None:
         jcS, irS0, prS0 = out[0], out[1], out[2]
+        _need(jcS, "jcS", n + 1, torch.int32, dev)
+        _need(irS0, "irS", 0, torch.int32, dev)
+        _need(prS0, "prS", 0, ss.dtype, dev)
         if len(out) > 3:
             slot = out[3]
+            _need(slot, "slot", Ln, torch.int32, dev)
         cap = min(irS0.numel(), prS0.numel())
     else:
         jcS = torch.empty(n + 1, dtype=torch.int32, device=dev)
@@ -292,6 +357,10 @@ def _fresh(call, Ln, m, n, ss, dev, nzmax, atomic, keep_slot, plan, cap, ws,
     p = None
     if plan:
         p = _Plan(ph, [ws, slot], Ln, nnz, ss.dtype)
+    if not wait:
+        return Assembled(jcS, irS, prS, m, n, -1, int(info.nzmax),
+                         slot[:Ln] if slot is not None else None, p, ws,
+                         pending=True)
     return Assembled(jcS, irS[:nnz], prS[:nnz], m, n, nnz, int(info.nzmax),
                      slot[:Ln] if slot is not None else None, p, ws)
 
@@ -409,7 +478,11 @@ def sparse_append(A: "Assembled", ii, jj, ss: torch.Tensor,
     Ln = ss.numel()
     if ii.numel() != Ln or jj.numel() != Ln:
         raise ValueError("ii, jj and ss must have the same length")
+    A = A.wait() if getattr(A, "pending", False) else A
     nnzA = int(A.nnz)
+    _need(A.jcS, "A.jcS", A.n + 1, torch.int32, dev)
+    _need(A.irS, "A.irS", nnzA, torch.int32, dev)
+    _need(A.prS, "A.prS", nnzA, ss.dtype, dev)
     if m is None or n is None:
         dm, dn = dims(ii, jj)
         m = max(A.m, dm) if m is None else m
@@ -490,11 +563,15 @@ def reassemble(res: Assembled, ss: torch.Tensor,
     """Values for new ``ss`` on the pattern of ``res`` (needs plan=True)."""
     if res.plan is None:
         raise ValueError("assembled without plan=True")
+    if getattr(res, "pending", False):
+        res.wait()
     ss = ss.contiguous()
     if ss.numel() != res.plan.len or ss.dtype != res.plan.dtype:
         raise ValueError("ss does not match the plan")
+    _need(ss, "ss", res.plan.len, res.plan.dtype)
     if out is None:
         out = torch.empty(max(res.nnz, 1), dtype=ss.dtype, device=ss.device)
+    _need(out, "out", res.nnz, res.plan.dtype, ss.device)
     _check(L.fsparse_assemble_reuse(res.plan.handle, _ptr(ss), _ptr(out),
                                     L.ATOMIC if atomic else L.ORDERED,
                                     _stream()), "fsparse_assemble_reuse")
@@ -503,12 +580,17 @@ def reassemble(res: Assembled, ss: torch.Tensor,
 
 def backward(slot: torch.Tensor, grad_prS: torch.Tensor,
              out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """grad_ss[k] = grad_prS[slot[k]] (derivative of eq. (2.3))."""
+    """grad_ss[k] = grad_prS[slot[k]] (derivative of eq. (2.3)); a triplet
+    whose pair is not stored (slot -1) gets 0."""
     grad_prS = grad_prS.contiguous()
     slot = slot.contiguous()
+    _dt(grad_prS.dtype)
+    _need(slot, "slot", 0, torch.int32)
+    _need(grad_prS, "grad_prS", 0, grad_prS.dtype, slot.device)
     if out is None:
         out = torch.empty(slot.numel(), dtype=grad_prS.dtype,
                           device=grad_prS.device)
+    _need(out, "out", slot.numel(), grad_prS.dtype, slot.device)
     _check(L.fsparse_backward(_ptr(slot), slot.numel(), _ptr(grad_prS),
                               grad_prS.numel(), _dt(grad_prS.dtype), _ptr(out),
                               _stream()), "fsparse_backward")
@@ -524,8 +606,6 @@ class Assembler:
 
     def __init__(self, ii, jj, ss: torch.Tensor, m=None, n=None):
         self.result = sparse(ii, jj, ss, m, n, plan=True, keep_slot=True)
-        self._out = torch.empty(max(self.result.nnz, 1), dtype=ss.dtype,
-                                device=ss.device)
 
     @property
     def jcS(self):
@@ -541,8 +621,9 @@ class Assembler:
 
     def reassemble(self, ss: torch.Tensor, out: Optional[torch.Tensor] = None,
                    atomic: bool = False) -> torch.Tensor:
-        return reassemble(self.result, ss, out if out is not None else
-                          self._out, atomic)
+        """New values on the pattern: a new tensor per call (so earlier
+        results stay as they were), or ``out`` when given."""
+        return reassemble(self.result, ss, out, atomic)
 
 
 class SparseAssemble(torch.autograd.Function):
@@ -604,6 +685,18 @@ def assemble_batched(ii, jj, ss: torch.Tensor, trip_off: Sequence[int],
     ii = _dev_i32(ii, dev)
     jj = _dev_i32(jj, dev)
     nb = len(m)
+    # the library reads the arrays through trip_off and has no lengths of
+    # its own to check them against
+    if len(n) != nb or len(trip_off) != nb + 1:
+        raise ValueError("trip_off needs nb+1 entries and m, n nb each")
+    if int(trip_off[0]) != 0 or any(int(trip_off[b + 1]) < int(trip_off[b])
+                                    for b in range(nb)):
+        raise ValueError("trip_off must start at 0 and not decrease")
+    if not (int(trip_off[-1]) == ii.numel() == jj.numel() == ss.numel()):
+        raise ValueError("trip_off[-1] must equal the length of ii, jj, ss")
+    _need(ss, "ss", ss.numel(), ss.dtype, dev)
+    if ws is not None:
+        _need(ws, "ws", 0, torch.uint8, dev)
     to = (ctypes.c_int64 * (nb + 1))(*[int(x) for x in trip_off])
     mm = (ctypes.c_int64 * nb)(*[int(x) for x in m])
     nn = (ctypes.c_int64 * nb)(*[int(x) for x in n])

@@ -1,14 +1,20 @@
 """Launch-shape autotuner for the assembly kernels.
 
-For a given input it times every candidate tuning (LDS capacity of the
-sort/fold workgroups, their thread count, the streaming block size, the
-bin-placement mode and the re-assembly block size) on the device, checks
-that every candidate produces byte-identical output, applies the fastest,
-and caches the choice per device and per *config class* -- the size of the
-problem in powers of two of L (triplets), N (columns) and L/N, plus the
-value type -- so later problems of the same class reuse it without timing.
+For a given input it times candidate tunings on the device -- the
+bin-placement mode (count matrix, fixed-capacity bins, count then place)
+with the LDS capacity of the bin workgroups, then their thread count, then
+the streaming block size, each stage keeping the best of the one before
+(coordinate descent over the space), then the re-assembly block size --
+checks that every candidate produces byte-identical output, applies the
+fastest, and caches the choice per device and per *config class* -- the
+size of the problem in powers of two of L (triplets), N (columns) and L/N,
+the value type, single or batched -- so later problems of the same class
+reuse it without timing.
 
-Cache file: ``$FSPARSE_TUNE_CACHE`` or ``~/.cache/fsparse_mi355x/tune.json``.
+Look-up order: the cache file ``$FSPARSE_TUNE_CACHE`` (default
+``~/.cache/fsparse_mi355x/tune.json``), then the table of choices measured
+on MI355X that ships beside this module (``tune_table.json``; set
+``FSPARSE_TUNE_TABLE=0`` to ignore it), else a measurement.
 """
 from __future__ import annotations
 
@@ -22,13 +28,18 @@ import torch
 
 from . import api
 
-DEFAULT_SPACE = {
-    "chunk_cap": [2048, 4096],
-    "chunk_block": [512, 1024],
-    "stream_block": [256, 512],
-    "bin_mode": ["auto"],
-}
+# searched in this order, each stage over the best of the stages before
+STAGES = [
+    {"bin_mode": ["auto", "dense", "slot", "claim"],
+     "chunk_cap": [1024, 2048, 4096]},
+    {"chunk_block": [256, 512, 1024]},
+    {"stream_block": [256, 512]},
+]
+START = {"chunk_cap": 4096, "chunk_block": 1024, "stream_block": 256,
+         "bin_mode": "auto"}
 REUSE_BLOCKS = [256, 512, 1024]
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                     "tune_table.json")
 
 
 def cache_path() -> str:
@@ -39,12 +50,18 @@ def cache_path() -> str:
                         "tune.json")
 
 
-def _load() -> dict:
+def _load(path: Optional[str] = None) -> dict:
     try:
-        with open(cache_path()) as f:
+        with open(path or cache_path()) as f:
             return json.load(f)
     except (OSError, ValueError):
         return {}
+
+
+def _table() -> dict:
+    if os.environ.get("FSPARSE_TUNE_TABLE", "1") == "0":
+        return {}
+    return _load(TABLE)
 
 
 def _store(d: dict):
@@ -96,8 +113,17 @@ def _digest(res) -> bytes:
     return b"".join(p.cpu().numpy().tobytes() for p in parts)
 
 
+def _effective(c: dict) -> tuple:
+    """The launch a candidate gives: the bin workgroup uses at least
+    chunk_cap/8 and at most chunk_cap threads (so e.g. 4096/256 runs as
+    4096/512)."""
+    cap = c["chunk_cap"]
+    nt = max(cap // 8, min(c["chunk_block"], cap))
+    return (c["bin_mode"], cap, nt, c["stream_block"])
+
+
 def tune(ii, jj, ss: torch.Tensor, m: int, n: int, *, trip_off=None,
-         space: Optional[Dict[str, List]] = None, reps: int = 3,
+         stages: Optional[List[Dict[str, List]]] = None, reps: int = 3,
          use_cache: bool = True, check: bool = True) -> dict:
     """Pick and apply the fastest tuning for this kind of input.
 
@@ -109,13 +135,16 @@ def tune(ii, jj, ss: torch.Tensor, m: int, n: int, *, trip_off=None,
     L = int(ss.numel())
     N = int(sum(n)) if batched else int(n)
     key = config_class(L, N, ss.dtype, len(m) if batched else 1)
-    cache = _load() if use_cache else {}
-    if use_cache and key in cache:
-        best = cache[key]["best"]
-        api.set_tuning(**best)
-        return {"key": key, "best": best, "cached": True}
+    if use_cache:
+        for src, d in (("cache", _load()), ("table", _table())):
+            if key in d:
+                best = d[key]["best"]
+                api.set_tuning(reset=True)
+                api.set_tuning(**best)
+                return {"key": key, "best": best, "cached": True,
+                        "source": src}
 
-    space = space or DEFAULT_SPACE
+    stages = stages or STAGES
 
     def fresh(keep=False):
         if batched:
@@ -123,22 +152,32 @@ def tune(ii, jj, ss: torch.Tensor, m: int, n: int, *, trip_off=None,
                                         keep_slot=keep)
         return api.sparse(ii, jj, ss, m, n, keep_slot=keep)
 
-    times, ref, best, best_t = {}, None, None, float("inf")
-    for cand in _candidates(space):
-        api.set_tuning(reset=True)
-        api.set_tuning(**cand)
-        out = fresh(keep=True)
-        if check:
-            dig = _digest(out)
-            if ref is None:
-                ref = dig
-            elif dig != ref:
-                raise AssertionError("candidate %r changed the result" % cand)
-        del out
-        t = _time(fresh, reps)  # the plain call, as it is used
-        times[json.dumps(cand, sort_keys=True)] = t
-        if t < best_t:
-            best, best_t = cand, t
+    times, ref, best_t = {}, None, float("inf")
+    best = dict(START)
+    seen = {}
+    for space in stages:
+        base = dict(best)
+        for vals in _candidates(space):
+            cand = dict(base, **vals)
+            eff = _effective(cand)
+            if eff in seen:            # the same launch as one already timed
+                continue
+            api.set_tuning(reset=True)
+            api.set_tuning(**cand)
+            out = fresh(keep=True)
+            if check:
+                dig = _digest(out)
+                if ref is None:
+                    ref = dig
+                elif dig != ref:
+                    raise AssertionError("candidate %r changed the result"
+                                         % cand)
+            del out
+            t = _time(fresh, reps)  # the plain call, as it is used
+            seen[eff] = t
+            times[json.dumps(cand, sort_keys=True)] = t
+            if t < best_t:
+                best, best_t = cand, t
     # re-assembly block size, with the best fresh tuning
     api.set_tuning(reset=True)
     api.set_tuning(**best)

@@ -376,9 +376,11 @@ T* at(void* ws, size_t off) {
 // plan
 // ---------------------------------------------------------------------------
 struct fsparse_plan {
-  int64_t len = 0, nnz = 0;
+  int64_t len = 0, nnz = 0;       // nnz < 0: not read back yet (see dnnz)
+  const int64_t* dnnz = nullptr;  // nnz in device memory (the control block)
   fsparse_dtype dt = FSPARSE_F64;
   int device = 0;
+  hipEvent_t done = nullptr;      // recorded after every graph launch
   const int32_t* perm = nullptr;
   const int32_t* seg = nullptr;
   const int32_t* slot = nullptr;
@@ -410,11 +412,21 @@ void* reuse_fn(int nt) {
 }
 template <typename VT>
 void* fill_fn() {
-  return reinterpret_cast<void*>(&fsp::k_fill<VT>);
+  return reinterpret_cast<void*>(&fsp::k_fill_dev<VT>);
 }
 template <typename VT>
 void* atomic_fn() {
   return reinterpret_cast<void*>(&fsp::k_atomic<VT>);
+}
+
+// Records the plan's completion event after its latest launch, so that
+// destroying the plan can wait for launches still queued.
+fsparse_status plan_mark(fsparse_plan* pl, hipStream_t stream) {
+  if (!pl->done && hipEventCreateWithFlags(&pl->done, hipEventDisableTiming) != hipSuccess) {
+    pl->done = nullptr;
+    return FSPARSE_E_HIP;
+  }
+  return hipEventRecord(pl->done, stream) == hipSuccess ? FSPARSE_OK : FSPARSE_E_HIP;
 }
 
 fsparse_status plan_reuse_ordered(fsparse_plan* pl, const void* ss, void* prS,
@@ -443,17 +455,19 @@ fsparse_status plan_reuse_ordered(fsparse_plan* pl, const void* ss, void* prS,
     pl->pr_ord = prS;
   }
   hipError_t e = launch(kReuse, stream, [&] { (void)hipGraphLaunch(pl->x_ord, stream); });
-  return e == hipSuccess ? FSPARSE_OK : FSPARSE_E_HIP;
+  if (e != hipSuccess) return FSPARSE_E_HIP;
+  return plan_mark(pl, stream);
 }
 
 fsparse_status plan_reuse_atomic(fsparse_plan* pl, const void* ss, void* prS,
                                  hipStream_t stream) {
   const int blk = pl->rblock;
-  const int gf = grid_for(pl->nnz, blk, 8);
+  const int gf = grid_for(pl->nnz >= 0 ? pl->nnz : pl->len, blk, 8);
   const int ga = grid_for(pl->len, blk, 16);
   const int32_t* slot = pl->slot;
-  int64_t nnz = pl->nnz, len = pl->len;
-  void* fargs[] = {(void*)&prS, (void*)&nnz};
+  const int64_t* dnnz = pl->dnnz;
+  int64_t len = pl->len;
+  void* fargs[] = {(void*)&prS, (void*)&dnnz, (void*)&len};
   void* aargs[] = {(void*)&slot, (void*)&ss, (void*)&len, (void*)&prS};
   hipKernelNodeParams fp{}, ap{};
   fp.func = pl->dt == FSPARSE_F64 ? fill_fn<double>() : fill_fn<float>();
@@ -478,7 +492,8 @@ fsparse_status plan_reuse_atomic(fsparse_plan* pl, const void* ss, void* prS,
     pl->pr_at = prS;
   }
   hipError_t e = launch(kReuse, stream, [&] { (void)hipGraphLaunch(pl->x_at, stream); });
-  return e == hipSuccess ? FSPARSE_OK : FSPARSE_E_HIP;
+  if (e != hipSuccess) return FSPARSE_E_HIP;
+  return plan_mark(pl, stream);
 }
 
 // Removes the zero sums from the nnz pairs in place (irS, prS, jcS, and
@@ -508,13 +523,19 @@ hipError_t drop_zeros(void* ws, const Layout& lo, int64_t nnz, int64_t n, int64_
                         stream);
 }
 
+// nnz < 0: the count is only in device memory (dnnz), at most L
 template <typename VT>
 hipError_t launch_atomic_values(const int32_t* slot, const void* ss, int64_t L,
                                 void* prS, int64_t nnz, int blk,
-                                hipStream_t stream) {
+                                hipStream_t stream,
+                                const int64_t* dnnz = nullptr) {
   hipError_t e = launch(kFill, stream, [&] {
-    hipLaunchKernelGGL(fsp::k_fill<VT>, dim3(grid_for(nnz, blk)), dim3(blk), 0,
-                       stream, (VT*)prS, nnz);
+    if (nnz >= 0)
+      hipLaunchKernelGGL(fsp::k_fill<VT>, dim3(grid_for(nnz, blk)), dim3(blk), 0,
+                         stream, (VT*)prS, nnz);
+    else
+      hipLaunchKernelGGL(fsp::k_fill_dev<VT>, dim3(grid_for(L, blk)), dim3(blk), 0,
+                         stream, (VT*)prS, dnnz, L);
   });
   if (e != hipSuccess) return e;
   return launch(kAtomic, stream, [&] {
@@ -734,6 +755,17 @@ fsparse_status check_dt(fsparse_dtype dt) {
   return (dt == FSPARSE_F64 || dt == FSPARSE_F32) ? FSPARSE_OK : FSPARSE_E_ARG;
 }
 
+// Flags of the fresh calls: FSPARSE_NO_SYNC needs given dimensions (the
+// defaults take a wait) and excludes dropping zeros (the kept count is read
+// back between two passes).
+fsparse_status check_flags(unsigned flags, int64_t m, int64_t n) {
+  if (flags & ~(unsigned)(FSPARSE_ATOMIC | FSPARSE_DROP_ZEROS | FSPARSE_NO_SYNC))
+    return FSPARSE_E_ARG;
+  if ((flags & FSPARSE_NO_SYNC) && (m < 0 || n < 0 || (flags & FSPARSE_DROP_ZEROS)))
+    return FSPARSE_E_ARG;
+  return FSPARSE_OK;
+}
+
 constexpr int64_t kMaxI32 = 0x7FFFFFFE;
 
 // Per-matrix largest row / column index of a batch (defaults of the batched
@@ -878,8 +910,20 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
     info->nzmax = std::max<int64_t>(nzmax, 0);
   }
   if (jcS_cap < n + 1) return FSPARSE_E_CAPACITY;
-  const Tuning tu = tuning();
+  // without a wait the host cannot redo the call, so fixed-capacity bins
+  // (which may overflow and need a counted redo) give way to counting first,
+  // and cap must hold every distinct pair there can be (len)
+  const bool nosync = (flags & FSPARSE_NO_SYNC) != 0;
+  if (nosync && cap < len) {
+    if (info) info->nnz = len;
+    return FSPARSE_E_CAPACITY;
+  }
+  Tuning tu = tuning();
   Layout lo = make_layout(len, n, 1, esize_of(dt), tu);
+  if (nosync && lo.g.mode == kSlot) {
+    tu.bmode = 1 + kClaim;
+    lo = make_layout(len, n, 1, esize_of(dt), tu);
+  }
   if (ws_bytes < lo.total) return FSPARSE_E_CAPACITY;
   Ctrl* ctrl = at<Ctrl>(ws, lo.ctrl);
   // complex values: the imaginary parts are folded along the sorted order
@@ -894,9 +938,69 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
     hipError_t e = launch(kInit, stream, [&] {
       hipLaunchKernelGGL(fsp::k_zero, dim3(grid_for(n + 1, 256, 4)), dim3(256), 0,
                          stream, (uint32_t*)jcS, (int64_t)(n + 1));
+      // the control block (nnz = 0, no error) for fsparse_assemble_status
+      hipLaunchKernelGGL(fsp::k_zero, dim3(1), dim3(64), 0, stream,
+                         (uint32_t*)ctrl, (int64_t)(sizeof(Ctrl) / 4));
     });
     if (e != hipSuccess) return FSPARSE_E_HIP;
-    HIPCHK(hipStreamSynchronize(stream));
+    if (!nosync) HIPCHK(hipStreamSynchronize(stream));
+  } else if (nosync) {
+    // queue everything; nnz and the error bits stay in the control block
+    BatchDesc bd{};
+    const fsp::Expand x = ex ? *ex : fsp::Expand{};
+    hipError_t e;
+#define FSP_RUN(VT, S)                                                          \
+  run_pipeline<VT, false, S>(ii, jj, (const VT*)ss, len, (int32_t)m, (int32_t)n, bd, n, \
+                             lo, tu, ws, jcS, irS, (VT*)prS, cap, slot_used, keep, \
+                             lo.g.mode, stream, nullptr, x)
+    if (dt == FSPARSE_F64)
+      e = src == fsp::kIdxExpand ? FSP_RUN(double, fsp::kIdxExpand)
+        : src == fsp::kIdxF64    ? FSP_RUN(double, fsp::kIdxF64)
+                                 : FSP_RUN(double, fsp::kIdxI32);
+    else
+      e = src == fsp::kIdxExpand ? FSP_RUN(float, fsp::kIdxExpand)
+        : src == fsp::kIdxF64    ? FSP_RUN(float, fsp::kIdxF64)
+                                 : FSP_RUN(float, fsp::kIdxI32);
+#undef FSP_RUN
+    if (e != hipSuccess) return FSPARSE_E_HIP;
+    if (keep && launch_reuse_tiles(ws, lo, len, stream) != hipSuccess) return FSPARSE_E_HIP;
+    const int64_t* dnnz = &ctrl->nnz;
+    if (info) info->nnz = -1;
+    if (flags & FSPARSE_ATOMIC) {
+      if (!slot_used) return FSPARSE_E_ARG;
+      hipError_t ea = dt == FSPARSE_F64
+          ? launch_atomic_values<double>(slot_used, ss, len, prS, -1, tu.rblock, stream, dnnz)
+          : launch_atomic_values<float>(slot_used, ss, len, prS, -1, tu.rblock, stream, dnnz);
+      if (ea != hipSuccess) return FSPARSE_E_HIP;
+    }
+    if (si) {
+      hipError_t ei;
+      if (flags & FSPARSE_ATOMIC)
+        ei = dt == FSPARSE_F64
+            ? launch_atomic_values<double>(slot_used, si, len, piS, -1, tu.rblock, stream, dnnz)
+            : launch_atomic_values<float>(slot_used, si, len, piS, -1, tu.rblock, stream, dnnz);
+      else
+        ei = launch_reuse_direct(ws, lo, len, dt, tu.rblock, si, piS, stream);
+      if (ei != hipSuccess) return FSPARSE_E_HIP;
+    }
+    if (plan) {
+      fsparse_plan* pl = new (std::nothrow) fsparse_plan();
+      if (!pl) return FSPARSE_E_ARG;
+      pl->len = len;
+      pl->nnz = -1;
+      pl->dnnz = dnnz;
+      pl->dt = dt;
+      hipGetDevice(&pl->device);
+      pl->perm = at<int32_t>(ws, lo.perm);
+      pl->seg = at<int32_t>(ws, lo.seg);
+      pl->slot = slot_used;
+      pl->islot = at<int32_t>(ws, lo.islot);
+      pl->rtile = at<int32_t>(ws, lo.rtile);
+      pl->ntiles = (len + kReuseTP - 1) / kReuseTP;
+      pl->rblock = tu.rblock;
+      *plan = pl;
+    }
+    return FSPARSE_OK;
   } else {
     BatchDesc bd{};
     Ctrl* h = static_cast<Ctrl*>(pinned());
@@ -975,6 +1079,7 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
       if (!pl) return FSPARSE_E_ARG;
       pl->len = len;
       pl->nnz = nnz;
+      pl->dnnz = &at<Ctrl>(ws, lo.ctrl)->nnz;
       pl->dt = dt;
       hipGetDevice(&pl->device);
       pl->perm = at<int32_t>(ws, lo.perm);
@@ -1009,7 +1114,7 @@ fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
                                 hipStream_t stream) {
   if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
   if (len < 0 || len > kMaxI32 || m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
-  if (flags & ~(unsigned)(FSPARSE_ATOMIC | FSPARSE_DROP_ZEROS)) return FSPARSE_E_ARG;
+  if (check_flags(flags, m, n) != FSPARSE_OK) return FSPARSE_E_ARG;
   // the pattern of a call that drops zeros depends on the values: no plan
   if ((flags & FSPARSE_DROP_ZEROS) && plan) return FSPARSE_E_ARG;
   if (len > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
@@ -1038,7 +1143,7 @@ fsparse_status fsparse_assemble_f64idx(const double* ii, const double* jj,
                                        hipStream_t stream) {
   if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
   if (len < 0 || len > kMaxI32 || m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
-  if (flags & ~(unsigned)(FSPARSE_ATOMIC | FSPARSE_DROP_ZEROS)) return FSPARSE_E_ARG;
+  if (check_flags(flags, m, n) != FSPARSE_OK) return FSPARSE_E_ARG;
   // the pattern of a call that drops zeros depends on the values: no plan
   if ((flags & FSPARSE_DROP_ZEROS) && plan) return FSPARSE_E_ARG;
   if (len > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
@@ -1068,7 +1173,7 @@ fsparse_status fsparse_assemble_complex(const int32_t* ii, const int32_t* jj,
                                         hipStream_t stream) {
   if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
   if (len < 0 || len > kMaxI32 || m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
-  if (flags & ~(unsigned)(FSPARSE_ATOMIC | FSPARSE_DROP_ZEROS)) return FSPARSE_E_ARG;
+  if (check_flags(flags, m, n) != FSPARSE_OK) return FSPARSE_E_ARG;
   if ((flags & FSPARSE_DROP_ZEROS) && plan) return FSPARSE_E_ARG;
   if (len > 0 && (!ii || !jj || !sr || !si)) return FSPARSE_E_ARG;
   if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS || !piS))) return FSPARSE_E_ARG;
@@ -1171,7 +1276,7 @@ fsparse_status fsparse_assemble_expand(const int32_t* ii, const int32_t* jj,
                                        hipStream_t stream) {
   if (check_dt(dt) != FSPARSE_OK || !x) return FSPARSE_E_ARG;
   if (m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
-  if (flags & ~(unsigned)(FSPARSE_ATOMIC | FSPARSE_DROP_ZEROS)) return FSPARSE_E_ARG;
+  if (check_flags(flags, m, n) != FSPARSE_OK) return FSPARSE_E_ARG;
   // the pattern of a call that drops zeros depends on the values: no plan
   if ((flags & FSPARSE_DROP_ZEROS) && plan) return FSPARSE_E_ARG;
   int64_t len = 1;
@@ -1311,7 +1416,8 @@ fsparse_status fsparse_assemble_reuse(fsparse_plan* plan, const void* ss,
                                       void* prS, unsigned flags,
                                       hipStream_t stream) {
   if (!plan) return FSPARSE_E_PLAN;
-  if (flags & ~(unsigned)FSPARSE_ATOMIC) return FSPARSE_E_ARG;
+  // (re-assembly never waits: FSPARSE_NO_SYNC changes nothing here)
+  if (flags & ~(unsigned)(FSPARSE_ATOMIC | FSPARSE_NO_SYNC)) return FSPARSE_E_ARG;
   if (plan->nnz == 0) return FSPARSE_OK;
   if (!ss || !prS) return FSPARSE_E_ARG;
   int dev = 0;
@@ -1319,14 +1425,15 @@ fsparse_status fsparse_assemble_reuse(fsparse_plan* plan, const void* ss,
   if (dev != plan->device) return FSPARSE_E_PLAN;
   if (flags & FSPARSE_ATOMIC) {
     if (!plan->slot) {
-      if (!plan->islot || !plan->perm || !plan->seg) return FSPARSE_E_PLAN;
+      if (!plan->islot || !plan->perm || !plan->seg || !plan->dnnz) return FSPARSE_E_PLAN;
       const int32_t* perm = plan->perm;
       const int32_t* seg = plan->seg;
       int32_t* islot = plan->islot;
-      const int64_t nnz = plan->nnz;
+      const int64_t* dnnz = plan->dnnz;
+      const int64_t nb = plan->nnz >= 0 ? plan->nnz : plan->len;
       hipError_t e = launch(kReuse, stream, [&] {
-        hipLaunchKernelGGL(fsp::k_slot_from_order, dim3(grid_for(nnz, 256, 8)), dim3(256),
-                           0, stream, perm, seg, nnz, islot);
+        hipLaunchKernelGGL(fsp::k_slot_from_order, dim3(grid_for(nb, 256, 8)), dim3(256),
+                           0, stream, perm, seg, dnnz, islot);
       });
       if (e != hipSuccess) return FSPARSE_E_HIP;
       plan->slot = islot;
@@ -1344,17 +1451,16 @@ fsparse_status fsparse_backward(const int32_t* slot, int64_t len,
     return FSPARSE_E_ARG;
   if (len == 0) return FSPARSE_OK;
   if (!slot || !grad_ss || (nnz > 0 && !grad_prS)) return FSPARSE_E_ARG;
-  if (nnz == 0) return FSPARSE_E_ARG;  // every slot must point somewhere
   const int blk = tuning().rblock;
   hipError_t e = launch(kBackward, stream, [&] {
     if (dt == FSPARSE_F64)
       hipLaunchKernelGGL(fsp::k_backward<double>, dim3(grid_for(len, blk, 16)),
                          dim3(blk), 0, stream, slot, (const double*)grad_prS, len,
-                         (double*)grad_ss);
+                         nnz, (double*)grad_ss);
     else
       hipLaunchKernelGGL(fsp::k_backward<float>, dim3(grid_for(len, blk, 16)),
                          dim3(blk), 0, stream, slot, (const float*)grad_prS, len,
-                         (float*)grad_ss);
+                         nnz, (float*)grad_ss);
   });
   return e == hipSuccess ? FSPARSE_OK : FSPARSE_E_HIP;
 }
@@ -1529,6 +1635,7 @@ fsparse_status fsparse_assemble_batched(
     if (!pl) return FSPARSE_E_ARG;
     pl->len = L;
     pl->nnz = nnz;
+    pl->dnnz = &at<Ctrl>(ws, lo.ctrl)->nnz;
     pl->dt = dt;
     hipGetDevice(&pl->device);
     pl->perm = at<int32_t>(ws, lo.perm);
@@ -1570,8 +1677,47 @@ fsparse_status fsparse_dims_batched(int32_t nb, const int64_t* trip_off,
   return FSPARSE_OK;
 }
 
+fsparse_status fsparse_assemble_status(const void* ws, fsparse_info* info,
+                                       hipStream_t stream) {
+  if (!ws) return FSPARSE_E_ARG;
+  Ctrl c{};
+  HIPCHK(hipMemcpyAsync(&c, ws, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (info) info->nnz = c.nnz;
+  if (c.err & (fsp::kErrCol | fsp::kErrRow)) return FSPARSE_E_INDEX;
+  if (c.err & fsp::kErrCap) return FSPARSE_E_CAPACITY;
+  return FSPARSE_OK;
+}
+
+fsparse_status fsparse_indices_i32(const void* src, int32_t src_type, int64_t len,
+                                   int32_t* dst, hipStream_t stream) {
+  if (len < 0 || (len > 0 && (!src || !dst))) return FSPARSE_E_ARG;
+  if (src_type != FSPARSE_IDX_I64 && src_type != FSPARSE_IDX_U32 &&
+      src_type != FSPARSE_IDX_U64)
+    return FSPARSE_E_ARG;
+  if (len == 0) return FSPARSE_OK;
+  hipError_t e = launch(kInit, stream, [&] {
+    const dim3 g(grid_for(len, 256, 16)), b(256);
+    if (src_type == FSPARSE_IDX_I64)
+      hipLaunchKernelGGL(fsp::k_narrow_index<int64_t>, g, b, 0, stream,
+                         (const int64_t*)src, len, dst);
+    else if (src_type == FSPARSE_IDX_U32)
+      hipLaunchKernelGGL(fsp::k_narrow_index<uint32_t>, g, b, 0, stream,
+                         (const uint32_t*)src, len, dst);
+    else
+      hipLaunchKernelGGL(fsp::k_narrow_index<uint64_t>, g, b, 0, stream,
+                         (const uint64_t*)src, len, dst);
+  });
+  return e == hipSuccess ? FSPARSE_OK : FSPARSE_E_HIP;
+}
+
 void fsparse_plan_destroy(fsparse_plan* plan) {
   if (!plan) return;
+  // graph launches may still be queued: wait for the latest one first
+  if (plan->done) {
+    (void)hipEventSynchronize(plan->done);
+    (void)hipEventDestroy(plan->done);
+  }
   if (plan->x_ord) (void)hipGraphExecDestroy(plan->x_ord);
   if (plan->g_ord) (void)hipGraphDestroy(plan->g_ord);
   if (plan->x_at) (void)hipGraphExecDestroy(plan->x_at);
@@ -1583,7 +1729,16 @@ fsparse_status fsparse_plan_query(const fsparse_plan* plan, int64_t* len,
                                   int64_t* nnz, int32_t* dtype) {
   if (!plan) return FSPARSE_E_PLAN;
   if (len) *len = plan->len;
-  if (nnz) *nnz = plan->nnz;
+  if (nnz) {
+    *nnz = plan->nnz;
+    if (plan->nnz < 0 && plan->dnnz) {
+      // a plan made without a wait: read the count now (a blocking copy)
+      int64_t v = 0;
+      if (hipMemcpy(&v, plan->dnnz, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+        return FSPARSE_E_HIP;
+      *nnz = v;
+    }
+  }
   if (dtype) *dtype = (int32_t)plan->dt;
   return FSPARSE_OK;
 }

@@ -2306,9 +2306,12 @@ k_reuse(const int32_t* __restrict__ perm, const int32_t* __restrict__ seg,
 
 // The slot map from a plan's sorted order: every position p of output j's
 // run seg[j]..seg[j+1] holds a triplet number perm[p] whose slot is j.
+// (nnz is read on the device: the plan may not have read it back.)
 __global__ void k_slot_from_order(const int32_t* __restrict__ perm,
-                                  const int32_t* __restrict__ seg, int64_t nnz,
+                                  const int32_t* __restrict__ seg,
+                                  const int64_t* __restrict__ nnz_dev,
                                   int32_t* __restrict__ slot) {
+  const int64_t nnz = *nnz_dev;
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; j < nnz; j += stride)
@@ -2317,6 +2320,17 @@ __global__ void k_slot_from_order(const int32_t* __restrict__ perm,
 
 template <typename VT>
 __global__ void k_fill(VT* __restrict__ p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = (VT)0;
+}
+
+// The same with the count in device memory (a call that has not read nnz
+// back to the host), at most nmax entries.
+template <typename VT>
+__global__ void k_fill_dev(VT* __restrict__ p, const int64_t* __restrict__ ndev,
+                           int64_t nmax) {
+  const int64_t n = min(*ndev, nmax);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) p[i] = (VT)0;
@@ -2331,13 +2345,33 @@ __global__ void k_atomic(const int32_t* __restrict__ slot,
   for (; k < L; k += stride) unsafeAtomicAdd(&prS[slot[k]], ss[k]);
 }
 
+// grad_ss[k] = grad_prS[slot[k]]; a triplet of a pair that is not stored
+// (slot -1 after dropping zeros or false logical pairs) moves no stored
+// value, so its gradient is 0.  Slots outside [0, nnz) read nothing.
 template <typename VT>
 __global__ void k_backward(const int32_t* __restrict__ slot,
-                           const VT* __restrict__ g, int64_t L,
+                           const VT* __restrict__ g, int64_t L, int64_t nnz,
                            VT* __restrict__ gs) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; k < L; k += stride) gs[k] = g[slot[k]];
+  for (; k < L; k += stride) {
+    const int32_t s = slot[k];
+    gs[k] = (s >= 0 && s < nnz) ? g[s] : (VT)0;
+  }
+}
+
+// Wide integer indices narrowed to int32 for the passes: a value that is not
+// in [1, 2^31 - 1] becomes 0, which every pass rejects as an index below 1
+// (instead of wrapping into range).
+template <typename IT>
+__global__ void k_narrow_index(const IT* __restrict__ src, int64_t L,
+                               int32_t* __restrict__ dst) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; k < L; k += stride) {
+    const IT v = src[k];
+    dst[k] = (v >= (IT)1 && v <= (IT)2147483647) ? (int32_t)v : 0;
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -126,3 +126,43 @@ def test_complex_and_logical_argument_errors_without_gpu():
     assert L.fsparse_assemble_logical(None, None, None, 0, 3, 3, 0, jc, 4,
                                       None, None, 0, None, None, 0, None,
                                       None) == L.E_ARG
+
+
+def test_no_sync_and_narrowing_argument_errors_without_gpu():
+    from paper_1406_1066_amd import _lib as L
+    jc = ctypes.c_void_p(1)          # never dereferenced: rejected before use
+    ws = ctypes.c_void_p(1)
+    one = ctypes.c_void_p(1)
+    # without a wait the dimensions must be given, and zeros cannot be dropped
+    for m, n in ((-1, 3), (3, -1)):
+        assert L.fsparse_assemble(one, one, one, L.F64, 5, m, n, 0, L.NO_SYNC,
+                                  jc, 4, one, one, 5, None, ws, 1 << 20, None,
+                                  None, None) == L.E_ARG
+    assert L.fsparse_assemble(one, one, one, L.F64, 5, 3, 3, 0,
+                              L.NO_SYNC | L.DROP_ZEROS, jc, 4, one, one, 5,
+                              None, ws, 1 << 20, None, None, None) == L.E_ARG
+    assert L.fsparse_assemble_f64idx(one, one, one, L.F64, 5, -1, 3, 0,
+                                     L.NO_SYNC, jc, 4, one, one, 5, None, ws,
+                                     1 << 20, None, None, None) == L.E_ARG
+    assert L.fsparse_assemble(one, one, one, L.F64, 5, 3, 3, 0, 8, jc, 4, one,
+                              one, 5, None, ws, 1 << 20, None, None,
+                              None) == L.E_ARG
+    # a batch and an append always wait
+    assert L.fsparse_assemble_append(jc, one, one, 1, 3, one, one, one, 1,
+                                     L.F64, 3, 3, L.NO_SYNC, jc, 4, one, one,
+                                     2, None, ws, 1 << 20, None, None,
+                                     None) == L.E_ARG
+    to = (ctypes.c_int64 * 2)(0, 1)
+    mm = (ctypes.c_int64 * 1)(3)
+    assert L.fsparse_assemble_batched(1, to, one, one, one, L.F64, mm, mm,
+                                      L.NO_SYNC, jc, 4, one, one, 1, to, None,
+                                      ws, 1 << 20, None, None,
+                                      None) == L.E_ARG
+    assert L.fsparse_assemble_status(None, None, None) == L.E_ARG
+    # narrowing: unknown source type, negative length, missing arrays
+    assert L.fsparse_indices_i32(one, 7, 4, one, None) == L.E_ARG
+    assert L.fsparse_indices_i32(one, L.IDX_I64, -1, one, None) == L.E_ARG
+    assert L.fsparse_indices_i32(None, L.IDX_I64, 4, one, None) == L.E_ARG
+    assert L.fsparse_indices_i32(None, L.IDX_I64, 0, None, None) == L.OK
+    # backward: a negative length is an error, nnz = 0 is not (all zeros)
+    assert L.fsparse_backward(one, 0, None, 0, L.F64, one, None) == L.OK

@@ -19,16 +19,23 @@ def test_autotune_small(tmp_path, monkeypatch):
     import paper_1406_1066_amd as fs
     from paper_1406_1066_amd import autotune
     monkeypatch.setenv("FSPARSE_TUNE_CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setenv("FSPARSE_TUNE_TABLE", "0")   # measure, not look up
     fs.set_tuning(reset=True)
     try:
         t = W.fem3d(20, 0.15, seed=5)
         ii, jj, ss = to_dev(t.ii), to_dev(t.jj), to_dev(t.ss)
         r1 = autotune.tune(ii, jj, ss, t.m, t.n, reps=2)
         assert not r1["cached"]
-        ncand = 1
-        for v in autotune.DEFAULT_SPACE.values():
-            ncand *= len(v)
-        assert len(r1["times_ms"]) == ncand + len(autotune.REUSE_BLOCKS)
+        # every stage's candidates, less the launches already timed
+        first = 1
+        for v in autotune.STAGES[0].values():
+            first *= len(v)
+        nfresh = len(r1["times_ms"]) - len(autotune.REUSE_BLOCKS)
+        assert first <= nfresh <= first + sum(
+            len(v) for st in autotune.STAGES[1:] for v in st.values())
+        assert json.dumps({k: v for k, v in r1["best"].items()
+                           if k != "reuse_block"}, sort_keys=True) \
+            in r1["times_ms"]
         cur = fs.get_tuning()
         for k, v in r1["best"].items():
             if k != "bin_mode":
