@@ -133,9 +133,12 @@ int num_cus() {
 // per lane, at most 8 waves per SIMD, 4 SIMDs per CU).  More blocks than
 // fit is harmless for the ticket-driven kernels (late blocks find no work),
 // fewer would leave CUs idle.
-template <typename K>
-int64_t resident(K kernel, int block) {
-  // one cache per kernel instantiation (each is launched with one block size)
+// The kernel is a template argument, so each instantiation (each bin
+// capacity and block size) keeps its own cached figure; kernels of one
+// function type must not share it.
+template <auto kernel>
+int64_t resident(int block) {
+  // one cache per kernel (each is launched with one block size)
   static std::atomic<int> cache[kMaxDev];
   const int dev = cur_device();
   int per = cache[dev].load(std::memory_order_relaxed);
@@ -703,7 +706,7 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
                          stream, a, binstart, bcol_in, colptr_g, w, slowlist, \
                          slowd);                                               \
     hipLaunchKernelGGL((fsp::k_bin<VT, C, T>),                                 \
-                       dim3((unsigned)std::min<int64_t>(B, resident(fsp::k_bin<VT, C, T>, T))), \
+                       dim3((unsigned)std::min<int64_t>(B, resident<fsp::k_bin<VT, C, T>>(T))), \
                        dim3(T), 0, stream, a, src, w);                         \
     if (may_slow)                                                              \
       hipLaunchKernelGGL((fsp::k_slow_emit<VT, C, T>), dim3(sgrid), dim3(T), 0, \
