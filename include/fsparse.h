@@ -15,7 +15,8 @@
  * Conventions shared by every entry point
  *  - Every array argument is HIP device memory owned by the caller unless it
  *    is marked "host".  The library never allocates device memory; scratch
- *    comes from the caller's workspace `ws`.
+ *    comes from the caller's workspace `ws` (fsparse_assemble_noalloc uses
+ *    a fixed device array inside the library instead).
  *  - Work is stream-ordered on `stream`.  Only fsparse_assemble,
  *    fsparse_assemble_batched and fsparse_dims wait for the stream (once, to
  *    read back result sizes and the error flags), and fsparse_assemble does
@@ -156,6 +157,35 @@ fsparse_status fsparse_assemble(const int32_t *ii, const int32_t *jj,
                                 int32_t *slot, void *ws, size_t ws_bytes,
                                 fsparse_plan **plan, fsparse_info *info,
                                 hipStream_t stream);
+
+/*
+ * Fresh assembly for callers that cannot allocate memory (code that must
+ * not call hipMalloc or any allocating routine: tight serving loops,
+ * harnesses that forbid allocation).  The same computation and outputs as
+ * fsparse_assemble, but the workspace is a device array inside the library
+ * of FSPARSE_NOALLOC_SCRATCH_BYTES (64 MiB) that every GPU the library runs
+ * on holds until the process ends; the call itself allocates nothing.
+ *  - m and n must be given (>= 0; the default dimensions take a pass of
+ *    their own), flags is FSPARSE_ORDERED or FSPARSE_ATOMIC, no plan.
+ *  - cap >= len (every distinct pair fits, no capacity retry), else
+ *    FSPARSE_E_CAPACITY with info->nnz = len.
+ *  - fsparse_workspace_bytes(len, n, 1, dt) must not exceed
+ *    FSPARSE_NOALLOC_SCRATCH_BYTES (about 1.3M fp64 triplets), else
+ *    FSPARSE_E_CAPACITY before any work is queued.
+ *  - Waits for the stream once (to read nnz and the error flags into info).
+ * All calls on one GPU share that GPU's array, and a call leaves its
+ * contents behind (the next call clears what it needs): calls that overlap
+ * on one GPU (other host threads, other streams) race and must not be made.
+ */
+#define FSPARSE_NOALLOC_SCRATCH_BYTES (64u << 20)
+fsparse_status fsparse_assemble_noalloc(const int32_t *ii, const int32_t *jj,
+                                        const void *ss, fsparse_dtype dt,
+                                        int64_t len, int64_t m, int64_t n,
+                                        int64_t nzmax, unsigned flags,
+                                        int32_t *jcS, int64_t jcS_cap,
+                                        int32_t *irS, void *prS, int64_t cap,
+                                        int32_t *slot, fsparse_info *info,
+                                        hipStream_t stream);
 
 /*
  * Status of a call made with FSPARSE_NO_SYNC on workspace ws: waits for

@@ -70,6 +70,11 @@ fsparse_assemble = _sig(
     [_vp, _vp, _vp, _st, _i64, _i64, _i64, _i64, _u, _vp, _i64, _vp, _vp,
      _i64, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp),
      ctypes.POINTER(FsparseInfo), _vp])
+fsparse_assemble_noalloc = _sig(
+    "fsparse_assemble_noalloc", _st,
+    [_vp, _vp, _vp, _st, _i64, _i64, _i64, _i64, _u, _vp, _i64, _vp, _vp,
+     _i64, _vp, ctypes.POINTER(FsparseInfo), _vp])
+NOALLOC_SCRATCH_BYTES = 64 << 20
 fsparse_dims_f64idx = _sig("fsparse_dims_f64idx", _st,
                            [_vp, _vp, _i64, ctypes.POINTER(_i64),
                             ctypes.POINTER(_i64), _vp, ctypes.c_size_t, _vp])
@@ -138,7 +143,8 @@ fsparse_indices_i32 = _sig("fsparse_indices_i32", _st,
 
 EXPORTS = [
     "fsparse_version", "fsparse_status_string", "fsparse_workspace_bytes",
-    "fsparse_dims", "fsparse_assemble", "fsparse_assemble_expand",
+    "fsparse_dims", "fsparse_assemble", "fsparse_assemble_noalloc",
+    "fsparse_assemble_expand",
     "fsparse_dims_f64idx", "fsparse_assemble_f64idx",
     "fsparse_assemble_complex", "fsparse_logical_workspace_bytes",
     "fsparse_assemble_logical",

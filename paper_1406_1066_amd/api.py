@@ -368,6 +368,53 @@ def _fresh(call, Ln, m, n, ss, dev, nzmax, atomic, keep_slot, plan, cap, ws,
 assemble = sparse
 
 
+def sparse_noalloc(ii, jj, ss: torch.Tensor, m: int, n: int,
+                   nzmax: Optional[int] = None, *, atomic: bool = False,
+                   out: Optional[tuple] = None) -> Assembled:
+    """S = sparse(ii, jj, ss, m, n, nzmax) through fsparse_assemble_noalloc,
+    which allocates nothing: its workspace is the library's fixed device
+    array (64 MiB per GPU), shared by every call on that GPU, so calls must
+    not overlap.  ``m``/``n`` must be given and int32 device indices are
+    expected.  ``out = (jcS, irS, prS[, slot])`` are the caller's buffers
+    (irS/prS of at least len entries, slot of len); without it they are
+    allocated here, before the call.  Waits once, like ``sparse``."""
+    dev = _device(ss, ii, jj)
+    ss = ss.contiguous()
+    ii, jj = _dev_i32(ii, dev), _dev_i32(jj, dev)
+    Ln = ss.numel()
+    if ii.numel() != Ln or jj.numel() != Ln:
+        raise ValueError("ii, jj and ss must have the same length")
+    m, n = int(m), int(n)
+    if m < 0 or n < 0:
+        raise ValueError("m and n must be given")
+    slot = None
+    if out is not None:
+        jcS, irS, prS = out[0], out[1], out[2]
+        _need(jcS, "jcS", n + 1, torch.int32, dev)
+        _need(irS, "irS", Ln, torch.int32, dev)
+        _need(prS, "prS", Ln, ss.dtype, dev)
+        if len(out) > 3:
+            slot = out[3]
+            _need(slot, "slot", Ln, torch.int32, dev)
+    else:
+        jcS = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        irS = torch.empty(max(Ln, 1), dtype=torch.int32, device=dev)
+        prS = torch.empty(max(Ln, 1), dtype=ss.dtype, device=dev)
+    if atomic and slot is None:
+        slot = torch.empty(max(Ln, 1), dtype=torch.int32, device=dev)
+    cap = min(irS.numel(), prS.numel())
+    info = L.FsparseInfo()
+    st = L.fsparse_assemble_noalloc(
+        _ptr(ii), _ptr(jj), _ptr(ss), _dt(ss.dtype), Ln, m, n,
+        int(nzmax) if nzmax is not None else 0,
+        L.ATOMIC if atomic else L.ORDERED, _ptr(jcS), jcS.numel(),
+        _ptr(irS), _ptr(prS), cap, _ptr(slot), ctypes.byref(info), _stream())
+    _check(st, "fsparse_assemble_noalloc")
+    nnz = int(info.nnz)
+    return Assembled(jcS, irS[:nnz], prS[:nnz], m, n, nnz, int(info.nzmax),
+                     slot[:Ln] if slot is not None else None, None, None)
+
+
 def sparse_complex(ii, jj, sr: torch.Tensor, si: torch.Tensor,
                    m: Optional[int] = None, n: Optional[int] = None,
                    nzmax: Optional[int] = None, *, atomic: bool = False,

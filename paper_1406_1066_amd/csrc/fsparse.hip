@@ -811,6 +811,32 @@ fsparse_status batched_dims(int32_t nb, const int64_t* trip_off,
   return FSPARSE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// scratch of the no-allocation entry point
+// ---------------------------------------------------------------------------
+// A device array of FSPARSE_NOALLOC_SCRATCH_BYTES held by every GPU the
+// library runs on, for the whole process.  In host code `scratch` names a
+// host-side stand-in, not device memory: its device address on each GPU is
+// looked up once (hipGetSymbolAddress, with that device current) and only
+// that address is handed to kernels and copies.
+static __device__ __align__(256) unsigned char scratch[FSPARSE_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDev];
+
+// The device address of the current device's scratch array, or null.
+void* scratch_ptr() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch[dev] = p;
+  }
+  return g_scratch[dev];
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1133,6 +1159,52 @@ fsparse_status fsparse_assemble(const int32_t* ii, const int32_t* jj,
   return assemble_impl(ii, jj, ss, dt, len, m, n, nzmax, flags, jcS, jcS_cap, irS,
                        prS, cap, slot, ws, ws_bytes, plan, info, stream,
                        fsp::kIdxI32, nullptr);
+}
+
+fsparse_status fsparse_assemble_noalloc(const int32_t* ii, const int32_t* jj,
+                                        const void* ss, fsparse_dtype dt,
+                                        int64_t len, int64_t m, int64_t n,
+                                        int64_t nzmax, unsigned flags,
+                                        int32_t* jcS, int64_t jcS_cap,
+                                        int32_t* irS, void* prS, int64_t cap,
+                                        int32_t* slot, fsparse_info* info,
+                                        hipStream_t stream) {
+  if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
+  if (len < 0 || len > kMaxI32 || m < 0 || n < 0 || m > kMaxI32 || n > kMaxI32)
+    return FSPARSE_E_ARG;
+  if (flags & ~(unsigned)FSPARSE_ATOMIC) return FSPARSE_E_ARG;
+  if (len > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
+  if (!jcS || cap < 0 || (cap > 0 && (!irS || !prS))) return FSPARSE_E_ARG;
+  if (info) {
+    info->m = m;
+    info->n = n;
+    info->nnz = 0;
+    info->nzmax = std::max<int64_t>(nzmax, 0);
+  }
+  // every distinct pair must fit without a capacity retry
+  if (cap < len) {
+    if (info) info->nnz = len;
+    return FSPARSE_E_CAPACITY;
+  }
+  if (fsparse_workspace_bytes(len, n, 1, dt) > (size_t)FSPARSE_NOALLOC_SCRATCH_BYTES)
+    return FSPARSE_E_CAPACITY;
+  void* ws = scratch_ptr();
+  if (!ws) return FSPARSE_E_HIP;
+  // the queued pipeline (counted bins: no host-decided redo), which clears
+  // the control block and look-back words it uses, then one wait to read
+  // them back
+  fsparse_status st = assemble_impl(ii, jj, ss, dt, len, m, n, nzmax,
+                                    flags | FSPARSE_NO_SYNC, jcS, jcS_cap, irS, prS,
+                                    cap, slot, ws, FSPARSE_NOALLOC_SCRATCH_BYTES,
+                                    nullptr, info, stream, fsp::kIdxI32, nullptr);
+  if (st != FSPARSE_OK) return st;
+  fsparse_info got{};
+  st = fsparse_assemble_status(ws, &got, stream);
+  if (info) {
+    info->nnz = got.nnz;
+    info->nzmax = std::max<int64_t>(nzmax, got.nnz);
+  }
+  return st;
 }
 
 fsparse_status fsparse_assemble_f64idx(const double* ii, const double* jj,
