@@ -82,6 +82,11 @@ const char *fsparse_version(void);
 /* Human-readable name of a status code (static storage). */
 const char *fsparse_status_string(int status);
 
+/* What failed behind the last FSPARSE_E_HIP returned on the calling host
+ * thread: the stage or runtime call and the HIP error name ("" if none).
+ * Thread-local storage, valid until that thread's next call. */
+const char *fsparse_last_error(void);
+
 /*
  * Bytes of device workspace that fsparse_assemble (nb = 1) or
  * fsparse_assemble_batched (nb matrices) needs for `len` triplets in total

@@ -8,6 +8,11 @@ from __future__ import annotations
 import ctypes
 import os
 
+# torch first: it brings its own HIP and HSA runtimes, and the library must
+# bind to the ones torch has loaded (loaded the other way round, the
+# library's first call reports no device)
+import torch  # noqa: F401
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 # FSPARSE_LIBRARY may point at another build of the same ABI
 LIB_PATH = os.environ.get("FSPARSE_LIBRARY") or os.path.join(HERE, "libfsparse.so")
@@ -70,6 +75,7 @@ fsparse_assemble = _sig(
     [_vp, _vp, _vp, _st, _i64, _i64, _i64, _i64, _u, _vp, _i64, _vp, _vp,
      _i64, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp),
      ctypes.POINTER(FsparseInfo), _vp])
+fsparse_last_error = _sig("fsparse_last_error", ctypes.c_char_p, [])
 fsparse_assemble_noalloc = _sig(
     "fsparse_assemble_noalloc", _st,
     [_vp, _vp, _vp, _st, _i64, _i64, _i64, _i64, _u, _vp, _i64, _vp, _vp,
@@ -142,7 +148,8 @@ fsparse_indices_i32 = _sig("fsparse_indices_i32", _st,
                            [_vp, _i32, _i64, _vp, _vp])
 
 EXPORTS = [
-    "fsparse_version", "fsparse_status_string", "fsparse_workspace_bytes",
+    "fsparse_version", "fsparse_status_string", "fsparse_last_error",
+    "fsparse_workspace_bytes",
     "fsparse_dims", "fsparse_assemble", "fsparse_assemble_noalloc",
     "fsparse_assemble_expand",
     "fsparse_dims_f64idx", "fsparse_assemble_f64idx",

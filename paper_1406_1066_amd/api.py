@@ -27,6 +27,8 @@ class FsparseError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
         msg = L.fsparse_status_string(status).decode()
+        if status == L.E_HIP:
+            msg += " [%s]" % L.fsparse_last_error().decode()
         super().__init__("%s: %s (status %d)" % (what, msg, status))
 
 

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -71,7 +72,26 @@ double g_ms[kNumStages];
 int64_t g_cnt[kNumStages];
 
 template <typename F>
+hipError_t launch_raw(int stage, hipStream_t s, F&& f);
+
+// The last HIP failure behind an FSPARSE_E_HIP on this host thread.
+thread_local char t_last_error[160] = "";
+
+void note_error(const char* where, hipError_t e) {
+  snprintf(t_last_error, sizeof(t_last_error), "%s: %s (%d)", where, hipGetErrorName(e),
+           (int)e);
+}
+
+template <typename F>
 hipError_t launch(int stage, hipStream_t s, F&& f) {
+  const hipError_t e = launch_raw(stage, s, f);
+  if (e != hipSuccess)
+    note_error(stage >= 0 && stage < kNumStages ? kStageNames[stage] : "launch", e);
+  return e;
+}
+
+template <typename F>
+hipError_t launch_raw(int stage, hipStream_t s, F&& f) {
   bool timing;
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -161,6 +181,9 @@ int64_t resident(int block) {
       const int by_waves = (4 * wpsimd) / std::max(1, wblk);
       own = std::min(by_lds, by_waves);
     }
+    // a failed query above falls back to the other figure; its error must
+    // not be taken for the failure of the next launch
+    (void)hipGetLastError();
     per = std::max(1, std::max(api, own));
     cache[dev].store(per, std::memory_order_relaxed);
   }
@@ -370,7 +393,11 @@ T* at(void* ws, size_t off) {
 
 #define HIPCHK(x)                              \
   do {                                         \
-    if ((x) != hipSuccess) return FSPARSE_E_HIP; \
+    const hipError_t e_ = (x);                 \
+    if (e_ != hipSuccess) {                    \
+      note_error(#x, e_);                      \
+      return FSPARSE_E_HIP;                    \
+    }                                          \
   } while (0)
 
 }  // namespace
@@ -845,6 +872,8 @@ void* scratch_ptr() {
 extern "C" {
 
 const char* fsparse_version(void) { return "fsparse-mi355x 0.1 (gfx950)"; }
+
+const char* fsparse_last_error(void) { return t_last_error; }
 
 const char* fsparse_status_string(int s) {
   switch (s) {

@@ -27,9 +27,8 @@ def test_autotune_small(tmp_path, monkeypatch):
         r1 = autotune.tune(ii, jj, ss, t.m, t.n, reps=2)
         assert not r1["cached"]
         # every stage's candidates, less the launches already timed
-        first = 1
-        for v in autotune.STAGES[0].values():
-            first *= len(v)
+        first = len({autotune._effective(dict(autotune.START, **c))
+                     for c in autotune._candidates(autotune.STAGES[0])})
         nfresh = len(r1["times_ms"]) - len(autotune.REUSE_BLOCKS)
         assert first <= nfresh <= first + sum(
             len(v) for st in autotune.STAGES[1:] for v in st.values())
