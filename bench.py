@@ -38,6 +38,18 @@ if ROOT not in sys.path:
 
 METRIC = ("Gtriplets/s assembled + % HBM roofline; fresh vs pattern-reuse "
           "vs batched")
+# the calls a run can time beside the fresh one (--only)
+LEGS = ["reuse", "reuse_atomic", "backward", "fresh_with_plan",
+        "fresh_plan_no_slot", "expand", "f64_index", "drop_zeros", "append",
+        "complex", "logical", "time_steps"]
+# kernel name prefix -> role, the key of a kernel in the traffic summaries
+ROLES = [("fsp::k_scatter", "scatter"), ("fsp::k_bin", "bin"),
+         ("fsp::k_count", "count"), ("fsp::k_colscan", "colscan"),
+         ("fsp::k_reuse_tiles", "reuse_tiles"), ("fsp::k_reuse", "reuse"),
+         ("fsp::k_atomic", "atomic"), ("fsp::k_fill", "fill"),
+         ("fsp::k_backward", "backward"), ("fsp::k_zero", "init"),
+         ("fsp::k_batched_jcs", "batched_jcs"), ("fsp::k_slow", "slow"),
+         ("fsp::k_copy16", "copy")]
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, public spec
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_1406_1066_amd", "csrc", "kernels.h")
@@ -71,9 +83,9 @@ def backward_bytes(L, nnz, vb):
 
 
 def read_traffic(workload, kernel=None):
-    """HBM bytes per launch of a stage (or, with kernel None, per call: all
-    the call's kernels) from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel source."""
+    """HBM bytes per launch of a kernel role (or, with kernel None, per fresh
+    call: all of its kernels) from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel source."""
     path = os.path.join(PROFILE_DIR, "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
@@ -164,6 +176,19 @@ def time_events(torch, fn, steps, warmup=3):
     return e0.elapsed_time(e1) / steps
 
 
+def want(args, leg):
+    return not args.only or leg in args.only.split(",")
+
+
+def with_traffic(row, workload, role):
+    """The counter bytes per launch of the row's kernel beside its
+    algorithmic bytes (null when no summary matches the kernel source)."""
+    tr = read_traffic(workload, role)
+    row["traffic"] = tr
+    row["traffic_ratio"] = tr / row["bytes"] if tr and row.get("bytes") else None
+    return row
+
+
 def rate(L, ms, nbytes=None, unit="Gtriplets/s"):
     r = {"value": L / (ms * 1e-3) / 1e9, "unit": unit, "ms": ms}
     if nbytes:
@@ -208,6 +233,9 @@ def main():
                     help="only run the 1 GiB copy kernel (counter calibration)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shapes")
+    ap.add_argument("--only", default="",
+                    help="comma list of the calls timed beside the fresh "
+                         "one (default all): " + ", ".join(LEGS))
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -239,13 +267,13 @@ def main():
     else:
         line = bench_single(args, t, fs, torch, np, vb)
         mats = [t]
-    if not args.no_modes and args.config == "batched_64":
+    if not args.no_modes and args.config == "batched_64" and not args.only:
         # the other legs of the metric on the other workloads
         torch.cuda.empty_cache()
         line["modes"]["fem3d_100"] = mesh_steps(args, fs, torch, np, W, vt, vb)
         torch.cuda.empty_cache()
         line["modes"]["uniform_1e7"] = uniform_row(args, fs, torch, W, vt, vb)
-    if not args.no_modes:
+    if not args.no_modes and not args.only:
         line["copy_gbps"] = copy_bw(fs, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(mats, args.cpu_seconds,
@@ -295,12 +323,13 @@ def bench_batched(args, batch, fs, torch, np, vb):
     line["stages_ms"] = stages
     line["tuning"] = tuning or fs.get_tuning()
     line["modes"] = {}
-    if not args.no_modes:
+    if not args.no_modes and want(args, "reuse"):
         rp = fs.assemble_batched(iid, jjd, ssd, off, m, n, plan=True)
         outp = torch.empty(nnz, dtype=ssd.dtype, device=dev)
         ms = time_events(torch, lambda: fs.reassemble(rp, ssd, out=outp),
                          args.steps)
-        line["modes"]["batched_reuse"] = rate(L, ms, reuse_bytes(L, nnz, vb))
+        line["modes"]["batched_reuse"] = with_traffic(
+            rate(L, ms, reuse_bytes(L, nnz, vb)), args.config, "reuse")
         log("batched reuse %.4f ms" % ms)
         del rp, outp
     return line
@@ -334,6 +363,9 @@ def mesh_steps(args, fs, torch, np, W, vt, vb):
     row = {"L": L, "nnz": nnz}
     row["fresh"] = rate(L, el / args.steps * 1e3, fb)
     row["fresh"]["roofline"] = roofline(fb, dom, dom_ms, "fem3d_100")
+    tc = read_traffic("fem3d_100")
+    row["fresh"]["traffic"] = tc
+    row["fresh"]["traffic_ratio"] = tc / fb if tc else None
     row["fresh"]["stages_ms"] = stages
     log("fem3d_100 fresh %.4f ms" % row["fresh"]["ms"])
     del ws, out, r
@@ -363,18 +395,20 @@ def mesh_steps(args, fs, torch, np, W, vt, vb):
         rms += e0.elapsed_time(e1)
         ums += u0.elapsed_time(e0)
     rb = reuse_bytes(L, nnz, vb)
-    row["reuse_steps"] = rate(L, rms / args.time_steps, rb)
+    row["reuse_steps"] = with_traffic(rate(L, rms / args.time_steps, rb),
+                                      "fem3d_100", "reuse")
     row["reuse_steps"]["steps"] = args.time_steps
     row["reuse_steps"]["update_ms"] = ums / args.time_steps
     log("fem3d_100 reuse step %.4f ms" % row["reuse_steps"]["ms"])
     ms = time_events(torch, lambda: fs.reassemble(res, s_t, out=prS,
                                                   atomic=True), args.steps)
-    row["reuse_atomic"] = rate(L, ms, rb)
+    row["reuse_atomic"] = with_traffic(rate(L, ms, rb), "fem3d_100", "atomic")
     gp = torch.randn(nnz, dtype=ss.dtype, device=dev)
     gs = torch.empty(L, dtype=ss.dtype, device=dev)
     ms = time_events(torch, lambda: fs.backward(res.slot, gp, out=gs),
                      args.steps)
-    row["backward"] = rate(L, ms, backward_bytes(L, nnz, vb))
+    row["backward"] = with_traffic(rate(L, ms, backward_bytes(L, nnz, vb)),
+                                   "fem3d_100", "backward")
     log("fem3d_100 atomic %.4f ms, backward %.4f ms"
         % (row["reuse_atomic"]["ms"], ms))
     del res, prS, gp, gs, s_t, ii, jj
@@ -404,12 +438,16 @@ def uniform_row(args, fs, torch, W, vt, vb):
     fb = fresh_bytes(L, nnz, n, 1, vb)
     row = {"L": L, "nnz": nnz, "fresh": rate(L, el / args.steps * 1e3, fb)}
     row["fresh"]["roofline"] = roofline(fb, dom, dom_ms, "uniform_1e7")
+    tc = read_traffic("uniform_1e7")
+    row["fresh"]["traffic"] = tc
+    row["fresh"]["traffic_ratio"] = tc / fb if tc else None
     row["fresh"]["stages_ms"] = stages
     res = fs.sparse(ii, jj, ss, m, n, plan=True)
     prS = torch.empty(nnz, dtype=ss.dtype, device=dev)
     ms = time_events(torch, lambda: fs.reassemble(res, ss, out=prS),
                      args.steps)
-    row["reuse"] = rate(L, ms, reuse_bytes(L, nnz, vb))
+    row["reuse"] = with_traffic(rate(L, ms, reuse_bytes(L, nnz, vb)),
+                                "uniform_1e7", "reuse")
     log("uniform_1e7 fresh %.4f ms, reuse %.4f ms" % (row["fresh"]["ms"], ms))
     return row
 
@@ -452,36 +490,50 @@ def bench_single(args, t, fs, torch, np, vb):
         return line
     del ws, out, r
     md = line["modes"]
+    wl = args.config
     res = fs.sparse(ii, jj, ss, m, n, plan=True, keep_slot=True)
     prS = torch.empty(nnz, dtype=ss.dtype, device=dev)
     rb = reuse_bytes(L, nnz, vb)
-    md["reuse"] = rate(L, time_events(
-        torch, lambda: fs.reassemble(res, ss, out=prS), args.steps), rb)
-    md["reuse_atomic"] = rate(L, time_events(
-        torch, lambda: fs.reassemble(res, ss, out=prS, atomic=True),
-        args.steps), rb)
-    gp = torch.randn(nnz, dtype=ss.dtype, device=dev)
-    gs = torch.empty(L, dtype=ss.dtype, device=dev)
-    md["backward"] = rate(L, time_events(
-        torch, lambda: fs.backward(res.slot, gp, out=gs), args.steps),
-        backward_bytes(L, nnz, vb))
-    md["fresh_with_plan"] = rate(L, time_events(
-        torch, lambda: fs.sparse(ii, jj, ss, m, n, plan=True, keep_slot=True,
-                                 ws=res.ws), args.steps))
-    md["fresh_plan_no_slot"] = rate(L, time_events(
-        torch, lambda: fs.sparse(ii, jj, ss, m, n, plan=True, ws=res.ws),
-        args.steps))
+    if want(args, "reuse"):
+        md["reuse"] = with_traffic(rate(L, time_events(
+            torch, lambda: fs.reassemble(res, ss, out=prS), args.steps), rb),
+            wl, "reuse")
+    if want(args, "reuse_atomic"):
+        md["reuse_atomic"] = with_traffic(rate(L, time_events(
+            torch, lambda: fs.reassemble(res, ss, out=prS, atomic=True),
+            args.steps), rb), wl, "atomic")
+    if want(args, "backward"):
+        gp = torch.randn(nnz, dtype=ss.dtype, device=dev)
+        gs = torch.empty(L, dtype=ss.dtype, device=dev)
+        md["backward"] = with_traffic(rate(L, time_events(
+            torch, lambda: fs.backward(res.slot, gp, out=gs), args.steps),
+            backward_bytes(L, nnz, vb)), wl, "backward")
+        del gp, gs
+    if want(args, "fresh_with_plan"):
+        md["fresh_with_plan"] = rate(L, time_events(
+            torch, lambda: fs.sparse(ii, jj, ss, m, n, plan=True,
+                                     keep_slot=True, ws=res.ws), args.steps))
+    if want(args, "fresh_plan_no_slot"):
+        md["fresh_plan_no_slot"] = rate(L, time_events(
+            torch, lambda: fs.sparse(ii, jj, ss, m, n, plan=True, ws=res.ws),
+            args.steps))
     for k in ("reuse", "reuse_atomic", "backward", "fresh_with_plan",
               "fresh_plan_no_slot"):
-        log(k, "%.4f ms" % md[k]["ms"])
-    del res, prS, gp, gs
-    if "conn" in t.meta:
+        if k in md:
+            log(k, "%.4f ms" % md[k]["ms"])
+    del res, prS
+    if "conn" in t.meta and want(args, "expand"):
         md["expand"] = expanded(args, fs, torch, t, ss)
-    md["f64_index"] = double_indices(args, fs, torch, ii, jj, ss, m, n)
-    md["drop_zeros"] = dropped(args, fs, torch, ii, jj, ss, m, n)
-    md["append"] = appended(args, fs, torch, ii, jj, ss, m, n)
-    md["complex"] = complexed(args, fs, torch, ii, jj, ss, m, n)
-    md["logical"] = logical(args, fs, torch, ii, jj, ss, m, n)
+    if want(args, "f64_index"):
+        md["f64_index"] = double_indices(args, fs, torch, ii, jj, ss, m, n)
+    if want(args, "drop_zeros"):
+        md["drop_zeros"] = dropped(args, fs, torch, ii, jj, ss, m, n)
+    if want(args, "append"):
+        md["append"] = appended(args, fs, torch, ii, jj, ss, m, n)
+    if want(args, "complex"):
+        md["complex"] = complexed(args, fs, torch, ii, jj, ss, m, n)
+    if want(args, "logical"):
+        md["logical"] = logical(args, fs, torch, ii, jj, ss, m, n)
     return line
 
 
