@@ -364,6 +364,17 @@ fsparse_status fsparse_assemble_expand(const int32_t *ii, const int32_t *jj,
  *  ws             fsparse_append_workspace_bytes(nnzA, len, n, dt) bytes;
  *                 a plan covers nnzA + len values (the old sums, then the new
  *                 values)
+ * Without a plan and without FSPARSE_DROP_ZEROS the call merges: the new
+ * triplets are assembled on their own, over the column range they occupy,
+ * with their sorted order kept, and merged column by column with the stored
+ * pairs (a pair in both continues from its stored sum over the new
+ * contributions in increasing k).  The stored pairs are read once and not
+ * sorted again.  It waits three times (the new triplets' index range, their
+ * assembly, the merged nnz); FSPARSE_ATOMIC gives the ordered sums there.
+ * E_CAPACITY then reports nnzA + the new distinct pairs, an upper bound of
+ * nnz.  With a plan or FSPARSE_DROP_ZEROS, or when a merge block finds
+ * columns far longer than the average, the stored pairs become triplets
+ * again and everything is assembled anew.
  */
 size_t fsparse_append_workspace_bytes(int64_t nnzA, int64_t len, int64_t n,
                                       fsparse_dtype dt);

@@ -900,13 +900,14 @@ size_t fsparse_workspace_bytes(int64_t len, int64_t ncols, int32_t nb,
 // not a whole number in [1, 2^31 - 1] reads as 0: E_INDEX).
 static fsparse_status dims_impl(const int32_t* ii, const int32_t* jj, int64_t len,
                                 int64_t* m, int64_t* n, void* ws, size_t ws_bytes,
-                                hipStream_t stream, bool f64) {
+                                hipStream_t stream, bool f64, int64_t* cmin = nullptr) {
   if (!m || !n || len < 0 || len > kMaxI32 || !ws || ws_bytes < 256)
     return FSPARSE_E_ARG;
   if (len > 0 && (!ii || !jj)) return FSPARSE_E_ARG;
   if (len == 0) {
     *m = 0;
     *n = 0;
+    if (cmin) *cmin = 1;
     return FSPARSE_OK;
   }
   Ctrl* h = static_cast<Ctrl*>(pinned());
@@ -918,11 +919,11 @@ static fsparse_status dims_impl(const int32_t* ii, const int32_t* jj, int64_t le
   BatchDesc bd{};
   hipError_t e = launch(kDims, stream, [&] {
     if (f64)
-      hipLaunchKernelGGL((fsp::k_dims<false, fsp::kIdxF64>), dim3(grid_for(len, 256, 8)),
-                         dim3(256), 0, stream, ii, jj, len, bd, (Ctrl*)ws,
+      hipLaunchKernelGGL((fsp::k_dims<false, fsp::kIdxF64>), dim3(grid_for(len, 1024, 2)),
+                         dim3(1024), 0, stream, ii, jj, len, bd, (Ctrl*)ws,
                          (int32_t*)nullptr);
     else
-      hipLaunchKernelGGL(fsp::k_dims<false>, dim3(grid_for(len, 256, 8)), dim3(256),
+      hipLaunchKernelGGL(fsp::k_dims<false>, dim3(grid_for(len, 1024, 2)), dim3(1024),
                          0, stream, ii, jj, len, bd, (Ctrl*)ws, (int32_t*)nullptr);
   });
   if (e != hipSuccess) return FSPARSE_E_HIP;
@@ -931,6 +932,7 @@ static fsparse_status dims_impl(const int32_t* ii, const int32_t* jj, int64_t le
   if (h->rmin < 1 || h->cmin < 1) return FSPARSE_E_INDEX;
   *m = h->rmax;
   *n = h->cmax;
+  if (cmin) *cmin = h->cmin;
   return FSPARSE_OK;
 }
 
@@ -960,7 +962,8 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
                              fsparse_plan** plan, fsparse_info* info,
                              hipStream_t stream, int src,
                              const fsp::Expand* ex,
-                             const void* si = nullptr, void* piS = nullptr) {
+                             const void* si = nullptr, void* piS = nullptr,
+                             bool keep_order = false, Layout* lo_out = nullptr) {
   if (info) {
     info->m = m;
     info->n = n;
@@ -983,10 +986,13 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
     lo = make_layout(len, n, 1, esize_of(dt), tu);
   }
   if (ws_bytes < lo.total) return FSPARSE_E_CAPACITY;
+  if (lo_out) *lo_out = lo;
   Ctrl* ctrl = at<Ctrl>(ws, lo.ctrl);
   // complex values: the imaginary parts are folded along the sorted order
   // that the real parts' pass leaves in the workspace
-  const bool keep = plan != nullptr || si != nullptr;
+  const bool keep = plan != nullptr || si != nullptr || keep_order;
+  // the re-use tiles serve the re-use kernel (plans, imaginary parts) only
+  const bool tiles = plan != nullptr || si != nullptr;
   // the atomic sums need a slot map (the caller's, else an internal one);
   // a plan's ordered re-use and the imaginary fold read only the sorted
   // order, and a plan derives its slot map on its first atomic re-use
@@ -1021,7 +1027,7 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
                                  : FSP_RUN(float, fsp::kIdxI32);
 #undef FSP_RUN
     if (e != hipSuccess) return FSPARSE_E_HIP;
-    if (keep && launch_reuse_tiles(ws, lo, len, stream) != hipSuccess) return FSPARSE_E_HIP;
+    if (tiles && launch_reuse_tiles(ws, lo, len, stream) != hipSuccess) return FSPARSE_E_HIP;
     const int64_t* dnnz = &ctrl->nnz;
     if (info) info->nnz = -1;
     if (flags & FSPARSE_ATOMIC) {
@@ -1081,7 +1087,7 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
                                    : FSP_RUN(float, fsp::kIdxI32);
 #undef FSP_RUN
       if (e != hipSuccess) return FSPARSE_E_HIP;
-      if (keep && launch_reuse_tiles(ws, lo, len, stream) != hipSuccess) return FSPARSE_E_HIP;
+      if (tiles && launch_reuse_tiles(ws, lo, len, stream) != hipSuccess) return FSPARSE_E_HIP;
       // the bin kernel's last block has written err and nnz into h
       HIPCHK(hipStreamSynchronize(stream));
       // a full fixed-capacity bin: count first, in narrower bins, and redo
@@ -1094,6 +1100,7 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
       }
       break;
     }
+    if (lo_out) *lo_out = lo;
     const uint32_t err = h->err;
     const int64_t nnz = h->nnz;
     if (info) {
@@ -1445,33 +1452,54 @@ static size_t append_head(int64_t Lc, fsparse_dtype dt) {
   return al(4 * (size_t)Lc) * 2 + al(vb * (size_t)Lc);
 }
 
+// Workspace of the merge path: its control block, B's CCS, slot map and
+// merged positions, and the look-back words of the merge blocks; then the
+// fresh assembly's workspace for the new triplets.
+struct MergeLayout {
+  size_t ctrl, jcB, irB, prB, slotB, mapB, jjB, st, head;
+};
+
+// (nB: B's columns; n: the result's)
+static MergeLayout merge_layout(int64_t len, int64_t nB, int64_t n, fsparse_dtype dt) {
+  const size_t vb = dt == FSPARSE_F64 ? 8 : 4;
+  const int64_t nscan = n + 1;  // look-back words, one per merge block (at most one per column)
+  MergeLayout o{};
+  size_t p = 0;
+  o.ctrl = p;   p = al(p + sizeof(Ctrl));
+  o.jcB = p;    p = al(p + 4 * (size_t)(nB + 1));
+  o.irB = p;    p = al(p + 4 * (size_t)std::max<int64_t>(len, 1));
+  o.prB = p;    p = al(p + vb * (size_t)std::max<int64_t>(len, 1));
+  o.slotB = p;  p = al(p + 4 * (size_t)len);
+  o.mapB = p;   p = al(p + 4 * (size_t)len);
+  o.jjB = p;    p = al(p + 4 * (size_t)len);
+  o.st = p;     p = al(p + 8 * (size_t)nscan);
+  o.head = p;
+  return o;
+}
+
 size_t fsparse_append_workspace_bytes(int64_t nnzA, int64_t len, int64_t n,
                                       fsparse_dtype dt) {
   if (nnzA < 0 || len < 0 || n < 0 || check_dt(dt) != FSPARSE_OK) return 0;
+  // the larger of the two paths: merge (plain calls) and re-assembly of all
+  // the pairs as triplets (plans, dropped zeros)
   const size_t w = fsparse_workspace_bytes(nnzA + len, n, 1, dt);
-  return w ? append_head(nnzA + len, dt) + w : 0;
+  const size_t wm = fsparse_workspace_bytes(len, n, 1, dt);
+  if (!w || !wm) return 0;
+  return std::max(append_head(nnzA + len, dt) + w, merge_layout(len, n, n, dt).head + wm);
 }
 
-fsparse_status fsparse_assemble_append(const int32_t* jcA, const int32_t* irA,
-                                       const void* prA, int64_t nnzA, int64_t nA,
-                                       const int32_t* ii, const int32_t* jj,
-                                       const void* ss, int64_t len, fsparse_dtype dt,
-                                       int64_t m, int64_t n, unsigned flags,
-                                       int32_t* jcS, int64_t jcS_cap, int32_t* irS,
-                                       void* prS, int64_t cap, int32_t* slot,
-                                       void* ws, size_t ws_bytes,
-                                       fsparse_plan** plan, fsparse_info* info,
-                                       hipStream_t stream) {
-  if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
-  if (nnzA < 0 || len < 0 || nA < 0 || nnzA + len > kMaxI32 || m > kMaxI32 ||
-      n > kMaxI32 || nA > kMaxI32)
-    return FSPARSE_E_ARG;
-  if (flags & ~(unsigned)(FSPARSE_ATOMIC | FSPARSE_DROP_ZEROS)) return FSPARSE_E_ARG;
-  if ((flags & FSPARSE_DROP_ZEROS) && plan) return FSPARSE_E_ARG;
-  if (!jcA || (nnzA > 0 && (!irA || !prA))) return FSPARSE_E_ARG;
-  if (len > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
-  if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS))) return FSPARSE_E_ARG;
-  if (plan) *plan = nullptr;
+// Delayed assembly by re-assembly of everything: the stored pairs become
+// triplets (first, in storage order), followed by the new ones.
+static fsparse_status append_resort(const int32_t* jcA, const int32_t* irA,
+                                    const void* prA, int64_t nnzA, int64_t nA,
+                                    const int32_t* ii, const int32_t* jj,
+                                    const void* ss, int64_t len, fsparse_dtype dt,
+                                    int64_t m, int64_t n, unsigned flags,
+                                    int32_t* jcS, int64_t jcS_cap, int32_t* irS,
+                                    void* prS, int64_t cap, int32_t* slot,
+                                    void* ws, size_t ws_bytes,
+                                    fsparse_plan** plan, fsparse_info* info,
+                                    hipStream_t stream) {
   const int64_t Lc = nnzA + len;
   const size_t head = append_head(Lc, dt);
   if (ws_bytes < head + 256) return FSPARSE_E_CAPACITY;
@@ -1514,6 +1542,174 @@ fsparse_status fsparse_assemble_append(const int32_t* jcA, const int32_t* irA,
   }
   return assemble_impl(ic, jc, sc, dt, Lc, m, n, 0, flags, jcS, jcS_cap, irS, prS, cap,
                        slot, ws2, ws2_bytes, plan, info, stream, fsp::kIdxI32, nullptr);
+}
+
+// Delayed assembly by merge (no plan, no dropped zeros): the new triplets
+// are assembled on their own with their sorted order kept, then merged with
+// the stored columns.  Waits twice (the fresh call's wait, then nnz).
+static fsparse_status append_merge(const int32_t* jcA, const int32_t* irA,
+                                   const void* prA, int64_t nnzA, int64_t nA,
+                                   const int32_t* ii, const int32_t* jj,
+                                   const void* ss, int64_t len, fsparse_dtype dt,
+                                   int64_t m, int64_t n, int32_t* jcS,
+                                   int64_t jcS_cap, int32_t* irS, void* prS,
+                                   int64_t cap, int32_t* slot, void* ws,
+                                   size_t ws_bytes, fsparse_info* info,
+                                   hipStream_t stream) {
+  Ctrl* h = static_cast<Ctrl*>(pinned());
+  if (!h) return FSPARSE_E_HIP;
+  // the new triplets' index range (B is assembled on its own columns, so
+  // that new triplets in a part of the matrix fill its bins as they would
+  // fill those of a matrix of that part alone)
+  if (ws_bytes < 256) return FSPARSE_E_CAPACITY;
+  int64_t dm = 0, dn = 0, dc = 1;
+  {
+    fsparse_status st = dims_impl(ii, jj, len, &dm, &dn, ws, ws_bytes, stream, false, &dc);
+    if (st != FSPARSE_OK) return st;
+  }
+  if (m < 0) {
+    // and the stored matrix's rows
+    Ctrl* c = static_cast<Ctrl*>(ws);
+    hipError_t e = launch(kDims, stream, [&] {
+      hipLaunchKernelGGL(fsp::k_zero, dim3(1), dim3(64), 0, stream, (uint32_t*)c,
+                         (int64_t)(sizeof(Ctrl) / 4));
+      if (nnzA > 0)
+        hipLaunchKernelGGL(fsp::k_rowmax, dim3(grid_for(nnzA, 256, 8)), dim3(256), 0,
+                           stream, irA, nnzA, &c->rmax);
+    });
+    if (e != hipSuccess) return FSPARSE_E_HIP;
+    HIPCHK(hipMemcpyAsync(h, c, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    m = std::max<int64_t>(dm, h->rmax);
+  }
+  if (n < 0) n = std::max(dn, nA);
+  if (info) {
+    info->m = m;
+    info->n = n;
+    info->nnz = 0;
+    info->nzmax = 0;
+  }
+  if (m > kMaxI32 || n > kMaxI32) return FSPARSE_E_ARG;
+  if (nA > n || dn > n) return FSPARSE_E_INDEX;
+  if (jcS_cap < n + 1) return FSPARSE_E_CAPACITY;
+  // B's columns: [boff, boff + nB) of the result
+  const int64_t boff = len > 0 ? dc - 1 : 0;
+  const int64_t nB = len > 0 ? dn - boff : 0;
+  const MergeLayout ml = merge_layout(len, nB, n, dt);
+  if (ws_bytes < ml.head) return FSPARSE_E_CAPACITY;
+  Ctrl* ctrl = at<Ctrl>(ws, ml.ctrl);
+  int32_t* jcB = at<int32_t>(ws, ml.jcB);
+  int32_t* irB = at<int32_t>(ws, ml.irB);
+  void* prB = at<char>(ws, ml.prB);
+  int32_t* slotB = slot ? at<int32_t>(ws, ml.slotB) : nullptr;
+  int32_t* mapB = slot ? at<int32_t>(ws, ml.mapB) : nullptr;
+  void* ws2 = at<char>(ws, ml.head);
+  const int32_t* jjB = jj;
+  if (boff > 0) {
+    int32_t* sh = at<int32_t>(ws, ml.jjB);
+    hipError_t e = launch(kAppend, stream, [&] {
+      hipLaunchKernelGGL(fsp::k_shift_index, dim3(grid_for(len, 256, 16)), dim3(256), 0,
+                         stream, jj, len, (int32_t)boff, sh);
+    });
+    if (e != hipSuccess) return FSPARSE_E_HIP;
+    jjB = sh;
+  }
+  // B: the new triplets alone, ordered, with their sorted order kept
+  Layout lo{};
+  fsparse_info ib{};
+  fsparse_status st = assemble_impl(ii, jjB, ss, dt, len, m, nB, 0, FSPARSE_ORDERED, jcB,
+                                    nB + 1, irB, prB, std::max<int64_t>(len, 1), slotB,
+                                    ws2, ws_bytes - ml.head, nullptr, &ib, stream,
+                                    fsp::kIdxI32, nullptr, nullptr, nullptr, true, &lo);
+  if (st != FSPARSE_OK) return st;
+  const int32_t* permB = at<int32_t>(ws2, lo.perm);
+  const int32_t* segB = at<int32_t>(ws2, lo.seg);
+  // every stored pair and every new pair fits: the merge is written in one
+  // pass (the count is then exact in jcS[n])
+  const int64_t bound = nnzA + ib.nnz;
+  if (bound > cap) {
+    if (info) info->nnz = bound;
+    return FSPARSE_E_CAPACITY;
+  }
+  // lanes per column: about the rows a column holds on either side (a
+  // power of two, 8 to 64); a block of 1024 threads then stages about 1024
+  // rows a side, half its LDS, which leaves room for uneven columns
+  const int64_t per = std::max<int64_t>(nnzA / std::max<int64_t>(nA, 1),
+                                        ib.nnz / std::max<int64_t>(nB, 1)) + 1;
+  int G = 8;
+  while (G < 64 && G < per) G *= 2;
+  constexpr int NT = 1024;
+  const int64_t tiles = (n + NT / G - 1) / (NT / G);
+  const fsp::MergeCols mc{(int32_t)nA, (int32_t)boff, (int32_t)nB};
+  hipError_t e = launch(kAppend, stream, [&] {
+    hipLaunchKernelGGL(fsp::k_zero, dim3(1), dim3(64), 0, stream, (uint32_t*)ctrl,
+                       (int64_t)(sizeof(Ctrl) / 4));
+    hipLaunchKernelGGL(fsp::k_zero, dim3(grid_for(2 * tiles + 2, 256, 4)), dim3(256), 0,
+                       stream, at<uint32_t>(ws, ml.st), (int64_t)(2 * tiles + 2));
+    if (n == 0) {
+      hipLaunchKernelGGL(fsp::k_zero, dim3(1), dim3(64), 0, stream, (uint32_t*)jcS,
+                         (int64_t)1);
+      return;
+    }
+#define FSP_MERGE(VT)                                                                \
+  hipLaunchKernelGGL((fsp::k_merge<VT, NT>), dim3((unsigned)tiles), dim3(NT), 0, stream,  \
+                     jcA, irA, (const VT*)prA, mc, jcB, irB, (const VT*)prB,              \
+                     segB, permB, (const VT*)ss, (int32_t)n, (int32_t)m, jcS, irS,        \
+                     (VT*)prS, slot, mapB, at<uint64_t>(ws, ml.st), ctrl, G)
+    if (dt == FSPARSE_F64)
+      FSP_MERGE(double);
+    else
+      FSP_MERGE(float);
+#undef FSP_MERGE
+    if (slot && len > 0)
+      hipLaunchKernelGGL(fsp::k_slot_gather, dim3(grid_for(len, 256, 16)), dim3(256), 0,
+                         stream, slotB, len, mapB, slot + nnzA);
+  });
+  if (e != hipSuccess) return FSPARSE_E_HIP;
+  int32_t* hnnz = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(h) + 256);
+  HIPCHK(hipMemcpyAsync(h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(hnnz, jcS + n, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (info) {
+    info->nnz = *hnnz;
+    info->nzmax = *hnnz;
+  }
+  if (h->err & (fsp::kErrRow | fsp::kErrCol)) return FSPARSE_E_INDEX;
+  // columns far longer than the average: merge by re-assembling everything
+  if (h->err & fsp::kErrRuns)
+    return append_resort(jcA, irA, prA, nnzA, nA, ii, jj, ss, len, dt, m, n,
+                         FSPARSE_ORDERED, jcS, jcS_cap, irS, prS, cap, slot, ws, ws_bytes,
+                         nullptr, info, stream);
+  return FSPARSE_OK;
+}
+
+fsparse_status fsparse_assemble_append(const int32_t* jcA, const int32_t* irA,
+                                       const void* prA, int64_t nnzA, int64_t nA,
+                                       const int32_t* ii, const int32_t* jj,
+                                       const void* ss, int64_t len, fsparse_dtype dt,
+                                       int64_t m, int64_t n, unsigned flags,
+                                       int32_t* jcS, int64_t jcS_cap, int32_t* irS,
+                                       void* prS, int64_t cap, int32_t* slot,
+                                       void* ws, size_t ws_bytes,
+                                       fsparse_plan** plan, fsparse_info* info,
+                                       hipStream_t stream) {
+  if (check_dt(dt) != FSPARSE_OK) return FSPARSE_E_ARG;
+  if (nnzA < 0 || len < 0 || nA < 0 || nnzA + len > kMaxI32 || m > kMaxI32 ||
+      n > kMaxI32 || nA > kMaxI32)
+    return FSPARSE_E_ARG;
+  if (flags & ~(unsigned)(FSPARSE_ATOMIC | FSPARSE_DROP_ZEROS)) return FSPARSE_E_ARG;
+  if ((flags & FSPARSE_DROP_ZEROS) && plan) return FSPARSE_E_ARG;
+  if (!jcA || (nnzA > 0 && (!irA || !prA))) return FSPARSE_E_ARG;
+  if (len > 0 && (!ii || !jj || !ss)) return FSPARSE_E_ARG;
+  if (!jcS || !ws || cap < 0 || (cap > 0 && (!irS || !prS))) return FSPARSE_E_ARG;
+  if (plan) *plan = nullptr;
+  // plain calls merge; a plan (whose values are the stored sums and the new
+  // values) or dropped zeros take the whole re-assembly below
+  if (!plan && !(flags & FSPARSE_DROP_ZEROS))
+    return append_merge(jcA, irA, prA, nnzA, nA, ii, jj, ss, len, dt, m, n, jcS, jcS_cap,
+                        irS, prS, cap, slot, ws, ws_bytes, info, stream);
+  return append_resort(jcA, irA, prA, nnzA, nA, ii, jj, ss, len, dt, m, n, flags, jcS,
+                       jcS_cap, irS, prS, cap, slot, ws, ws_bytes, plan, info, stream);
 }
 
 fsparse_status fsparse_assemble_reuse(fsparse_plan* plan, const void* ss,

@@ -44,6 +44,7 @@ constexpr uint32_t kErrCol = 1u;
 constexpr uint32_t kErrRow = 2u;
 constexpr uint32_t kErrCap = 4u;
 constexpr uint32_t kErrSlot = 8u;  // a fixed-capacity bin overflowed: redo in two passes
+constexpr uint32_t kErrRuns = 16u;  // a merge block's runs exceeded its LDS: merge otherwise
 
 // Control block at the start of the workspace (zeroed before every call).
 struct Ctrl {
@@ -398,22 +399,55 @@ __global__ void k_dims(const int32_t* __restrict__ ii,
     rmin = min(rmin, r);
     cmin = min(cmin, c);
     if (BATCHED) {
+      // one atomic pair per wave when the whole wave is here and its
+      // triplets share a matrix (matrices are long runs of triplets), else
+      // one per triplet
       const int b = find_mat(bd.trip_off, bd.nb, e);
-      atomicMax(&bmax[2 * b], r);
-      atomicMax(&bmax[2 * b + 1], c);
+      const int b0 = __builtin_amdgcn_readfirstlane(b);
+      if (__ballot(1) == ~0ull && __all(b == b0)) {
+        int32_t wr = r, wc = c;
+        for (int d = 32; d > 0; d >>= 1) {
+          wr = max(wr, __shfl_xor(wr, d, 64));
+          wc = max(wc, __shfl_xor(wc, d, 64));
+        }
+        if (lane_id() == 0) {
+          atomicMax(&bmax[2 * b0], wr);
+          atomicMax(&bmax[2 * b0 + 1], wc);
+        }
+      } else {
+        atomicMax(&bmax[2 * b], r);
+        atomicMax(&bmax[2 * b + 1], c);
+      }
     } else {
       rmax = max(rmax, r);
       cmax = max(cmax, c);
     }
   }
-  // wave reductions then one atomic per wave
+  // wave reductions, then the block's through LDS, then one atomic per
+  // block and field: every atomic goes to the same four words, which the
+  // memory system serialises, so they are kept few
   for (int d = 32; d > 0; d >>= 1) {
     rmax = max(rmax, __shfl_xor(rmax, d, 64));
     cmax = max(cmax, __shfl_xor(cmax, d, 64));
     rmin = min(rmin, __shfl_xor(rmin, d, 64));
     cmin = min(cmin, __shfl_xor(cmin, d, 64));
   }
+  __shared__ int32_t red[4][16];
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   if (lane_id() == 0) {
+    red[0][w] = rmax;
+    red[1][w] = cmax;
+    red[2][w] = rmin;
+    red[3][w] = cmin;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = 1; v < nw; ++v) {
+      rmax = max(rmax, red[0][v]);
+      cmax = max(cmax, red[1][v]);
+      rmin = min(rmin, red[2][v]);
+      cmin = min(cmin, red[3][v]);
+    }
     atomicMax(&ctrl->rmax, rmax);
     atomicMax(&ctrl->cmax, cmax);
     atomicMin(&ctrl->rmin, rmin);
@@ -2424,6 +2458,222 @@ k_ccs_triplets(const int32_t* __restrict__ jcA, const int32_t* __restrict__ irA,
     jj[e] = (int32_t)c + 1;
     ss[e] = prA[e];
   }
+}
+
+// ---------------------------------------------------------------------------
+// delayed assembly by merge.  The stored matrix A (rows strictly increasing
+// per column) and the new triplets, assembled on their own into B with the
+// sorted order of their triplets kept (permB: triplet of each sorted
+// position; segB: first sorted position of each of B's pairs), are merged
+// column by column, one thread per column.  A pair of A alone keeps its
+// stored sum (folded once from +0.0, as a stored pair is the first
+// contribution of its pair); a pair of B alone keeps B's sum; a pair in both
+// continues from the stored sum over B's contributions in increasing k.
+// That is the fold of one assembly of A's pairs (as triplets, first) and the
+// new triplets.
+// ---------------------------------------------------------------------------
+constexpr int kMergeRows = 2048;  // rows (and values) of A and of B one merge block stages
+
+// B is assembled on its own column range: its column j is column j + boff
+// of the result, j in [0, nB).
+struct MergeCols {
+  int32_t nA;    // A's columns (A is empty past them)
+  int32_t boff;  // result column of B's first column
+  int32_t nB;    // B's columns
+};
+
+__device__ __forceinline__ void merge_ranges(const int32_t* __restrict__ jcA,
+                                             const int32_t* __restrict__ jcB,
+                                             const MergeCols& mc, int64_t c, int32_t& a0,
+                                             int32_t& a1, int32_t& b0, int32_t& b1) {
+  a0 = jcA[min(c, (int64_t)mc.nA)];
+  a1 = jcA[min(c + 1, (int64_t)mc.nA)];
+  const int64_t cb = min(max(c - mc.boff, (int64_t)0), (int64_t)mc.nB);
+  const int64_t cb1 = min(max(c + 1 - mc.boff, (int64_t)0), (int64_t)mc.nB);
+  b0 = jcB[cb];
+  b1 = jcB[cb1];
+}
+
+// Rows in r[x, x + len) (increasing) below `row`.
+__device__ __forceinline__ int32_t lower_rank(const int32_t* r, int32_t x, int32_t len,
+                                              int32_t row) {
+  int32_t lo = 0, hi = len;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (r[x + mid] < row) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// A run of rows and values [t0, t1) (at most kMergeRows) into LDS, eight
+// loads per thread in flight before their stores.
+template <typename VT, int NT>
+__device__ __forceinline__ void merge_stage(const int32_t* __restrict__ ir,
+                                            const VT* __restrict__ pr, int32_t t0,
+                                            int32_t t1, int32_t* rs, VT* vs) {
+  constexpr int U = 8;
+  for (int32_t b = t0 + (int32_t)threadIdx.x; b < t1; b += NT * U) {
+    int32_t r[U];
+    VT v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t t = min(b + u * NT, t1 - 1);
+      r[u] = ir[t];
+      v[u] = pr[t];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t t = b + u * NT;
+      if (t < t1) {
+        rs[t - t0] = r[u];
+        vs[t - t0] = v[u];
+      }
+    }
+  }
+}
+
+// One block merges NT / G consecutive columns, G lanes (a power of two, 8 to
+// 64, within one wave) per column, blocks in ticket order.  The block's
+// runs of A and of B (contiguous in both) are loaded into LDS with
+// coalesced loads.  In a column, a row's merged position is the number of
+// distinct rows below it over A and B: for A's i-th row with p rows of B
+// below it, i + p - (common rows among A's first i); for B's j-th row with
+// q rows of A below it, j + q - (common rows among A's first q).  Binary
+// searches give p and q, a ballot scan over A's rows the common prefix.  A
+// row present in both is written by A's lane, which continues the stored
+// sum over B's contributions in increasing k.  The block sums its columns'
+// counts and chains its total to the earlier blocks by a look-back.  A block
+// whose runs exceed kMergeRows writes nothing and flags kErrRuns (the host
+// merges otherwise); a stored row outside [0, m) flags an index error.
+template <typename VT, int NT>
+__global__ void __launch_bounds__(NT)
+k_merge(const int32_t* __restrict__ jcA, const int32_t* __restrict__ irA,
+        const VT* __restrict__ prA, MergeCols mc, const int32_t* __restrict__ jcB,
+        const int32_t* __restrict__ irB, const VT* __restrict__ prB,
+        const int32_t* __restrict__ segB, const int32_t* __restrict__ permB,
+        const VT* __restrict__ ss, int32_t n, int32_t m, int32_t* __restrict__ jcS,
+        int32_t* __restrict__ irS, VT* __restrict__ prS, int32_t* __restrict__ slotA,
+        int32_t* __restrict__ mapB, uint64_t* status, Ctrl* ctrl, int32_t G) {
+  __shared__ int32_t rA[kMergeRows];
+  __shared__ int32_t rB[kMergeRows];
+  __shared__ uint32_t cA[kMergeRows];  // common rows among A's rows before
+  __shared__ VT vA[kMergeRows];
+  __shared__ VT vB[kMergeRows];
+  __shared__ uint32_t sWave[NT / 64];
+  __shared__ int sTile;
+  __shared__ int64_t sBase;
+  if (threadIdx.x == 0) sTile = (int)atomicAdd(&ctrl->tick_scan, 1u);
+  __syncthreads();
+  const int tile = sTile;
+  const int cpb = NT / G;
+  const int64_t cb = (int64_t)tile * cpb;
+  const int64_t ce = min(cb + cpb, (int64_t)n);
+  // the block's runs
+  int32_t A0, A1, B0, B1, t0, t1;
+  merge_ranges(jcA, jcB, mc, cb, A0, t0, B0, t1);
+  merge_ranges(jcA, jcB, mc, ce - 1, t0, A1, t1, B1);
+  const bool fits = A1 - A0 <= kMergeRows && B1 - B0 <= kMergeRows;
+  if (fits) {
+    merge_stage<VT, NT>(irA, prA, A0, A1, rA, vA);
+    merge_stage<VT, NT>(irB, prB, B0, B1, rB, vB);
+  } else if (threadIdx.x == 0) {
+    atomicOr(&ctrl->err, kErrRuns);
+  }
+  __syncthreads();
+  const int g = (int)threadIdx.x & (G - 1);
+  const int64_t c = cb + (int64_t)threadIdx.x / G;
+  const bool mine = fits && c < ce;
+  int32_t a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+  uint32_t common = 0;
+  if (mine) {
+    merge_ranges(jcA, jcB, mc, c, a0, a1, b0, b1);
+    const int32_t la = a1 - a0, lb = b1 - b0, xa = a0 - A0, xb = b0 - B0;
+    // rows increase within a column: the first and last bound them all
+    if (g == 0 && la > 0 && (rA[xa] < 0 || rA[xa + la - 1] >= m))
+      atomicOr(&ctrl->err, kErrRow);
+    // the column's lanes take A's rows G at a time (the same trip count in
+    // every lane of the column)
+    const int lane = lane_id();
+    const uint64_t gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << (lane & ~(G - 1));
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int32_t i0 = 0; i0 < la; i0 += G) {
+      const int32_t i = i0 + g;
+      bool com = false;
+      if (i < la) {
+        const int32_t ra = rA[xa + i];
+        const int32_t p = lower_rank(rB, xb, lb, ra);
+        com = p < lb && rB[xb + p] == ra;
+      }
+      const uint64_t bal = __ballot(com) & gmask;
+      if (i < la) cA[xa + i] = common + (uint32_t)__popcll(bal & below);
+      common += (uint32_t)__popcll(bal);
+    }
+  }
+  const uint32_t cnt = mine ? (uint32_t)((a1 - a0) + (b1 - b0)) - common : 0u;
+  uint32_t total;
+  const uint32_t pre = block_excl_sum<NT>(g == 0 ? cnt : 0u, sWave, total);
+  if (threadIdx.x < 64) {
+    const int64_t ex = lookback(status, tile, total);
+    if (threadIdx.x == 0) sBase = ex;
+  }
+  __syncthreads();
+  if (!mine) return;
+  // the column's first lane holds its offset; the others' prefix includes it
+  const int64_t col0 = sBase + (g == 0 ? pre : pre - cnt);
+  if (g == 0) {
+    jcS[c] = (int32_t)col0;
+    if (c == n - 1) jcS[n] = (int32_t)(col0 + cnt);
+  }
+  const int32_t la = a1 - a0, lb = b1 - b0, xa = a0 - A0, xb = b0 - B0;
+  for (int32_t i = g; i < la; i += G) {
+    const int32_t ra = rA[xa + i];
+    const int32_t p = lower_rank(rB, xb, lb, ra);
+    const int32_t o = (int32_t)(col0 + i + p - (int32_t)cA[xa + i]);
+    VT v = (VT)0 + vA[xa + i];
+    if (p < lb && rB[xb + p] == ra) {
+      for (int32_t t = segB[b0 + p], e = segB[b0 + p + 1]; t < e; ++t) v = v + ss[permB[t]];
+      if (mapB) mapB[b0 + p] = o;
+    }
+    irS[o] = ra;
+    prS[o] = v;
+    if (slotA) slotA[a0 + i] = o;
+  }
+  for (int32_t j = g; j < lb; j += G) {
+    const int32_t rb = rB[xb + j];
+    const int32_t q = lower_rank(rA, xa, la, rb);
+    if (q < la && rA[xa + q] == rb) continue;  // written with A's row
+    const int32_t o =
+        (int32_t)(col0 + j + q - (int32_t)(q < la ? cA[xa + q] : common));
+    irS[o] = rb;
+    prS[o] = vB[xb + j];
+    if (mapB) mapB[b0 + j] = o;
+  }
+}
+
+// Column indices moved down by `off` (B's own column range).
+__global__ void k_shift_index(const int32_t* __restrict__ jj, int64_t len, int32_t off,
+                              int32_t* __restrict__ out) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < len;
+       k += (int64_t)gridDim.x * blockDim.x)
+    out[k] = jj[k] - off;
+}
+
+// slot of new triplet k: the merged position of its pair in B.
+__global__ void k_slot_gather(const int32_t* __restrict__ slotB, int64_t len,
+                              const int32_t* __restrict__ mapB, int32_t* __restrict__ out) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < len;
+       k += (int64_t)gridDim.x * blockDim.x)
+    out[k] = mapB[slotB[k]];
+}
+
+// Rows the stored pairs need (largest 0-based row + 1), into *out (which
+// starts at 0).
+__global__ void k_rowmax(const int32_t* __restrict__ irA, int64_t nnzA, int32_t* out) {
+  int32_t mx = 0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nnzA;
+       t += (int64_t)gridDim.x * blockDim.x)
+    mx = max(mx, irA[t] + 1);
+  if (mx > 0) atomicMax(out, mx);
 }
 
 // ---------------------------------------------------------------------------

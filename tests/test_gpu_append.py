@@ -121,3 +121,45 @@ def test_stored_pairs_between_empty_column_runs(fs, dtype):
     want = oracle.assemble(ii, jj, ss, m, n)
     assert ref.prS.tobytes() == want.prS.tobytes()
     assert np.array_equal(ref.jcS, want.jcS)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_merge_with_stored_negative_zeros_and_bad_rows(fs, dtype):
+    # a stored matrix given by the caller (not assembled here) whose sums
+    # include -0.0: the merge starts every stored pair's fold from +0.0, as
+    # one assembly of the stored pairs as triplets would
+    rng = np.random.default_rng(98)
+    m, n = 50, 30
+    ii = rng.integers(1, m + 1, 3000).astype(np.int32)
+    jj = rng.integers(1, n + 1, 3000).astype(np.int32)
+    ss = rng.integers(-2, 3, 3000).astype(dtype)
+    ss[rng.random(3000) < 0.2] = -0.0
+    a = oracle.assemble(ii[:1000], jj[:1000], ss[:1000], m, n)
+    pr = a.prS.copy()
+    pr[rng.random(pr.size) < 0.3] = -0.0
+    a.prS[:] = pr
+    A = fs.Assembled(to_dev(a.jcS), to_dev(a.irS), to_dev(a.prS), m, n, a.nnz,
+                     a.nnz, None, None)
+    res = fs.sparse_append(A, to_dev(ii[1000:]), to_dev(jj[1000:]),
+                           to_dev(ss[1000:]), m, n, keep_slot=True)
+    ref = oracle.append(a, ii[1000:], jj[1000:], ss[1000:], m, n)
+    assert_same(res, ref)
+    # a stored row beyond the given m is an index error
+    with pytest.raises(fs.FsparseIndexError):
+        fs.sparse_append(A, to_dev(ii[1000:]), to_dev(jj[1000:]),
+                         to_dev(ss[1000:]), int(a.irS.max()), n)
+
+
+def test_merge_of_columns_longer_than_a_merge_block(fs):
+    # three columns with thousands of rows among short ones: the merge
+    # blocks holding them cannot stage their runs and the call takes the
+    # whole re-assembly instead; the result is the same
+    rng = np.random.default_rng(99)
+    m, n, L = 20_000, 64, 200_000
+    ii = rng.integers(1, m + 1, L).astype(np.int32)
+    jj = np.where(rng.random(L) < 0.9, rng.choice([5, 6, 40], L),
+                  rng.integers(1, n + 1, L)).astype(np.int32)
+    ss = rng.standard_normal(L)
+    res, ref = chain(fs, ii, jj, ss, [L // 3], m, n)
+    assert res.prS.cpu().numpy().tobytes() == \
+        oracle.assemble(ii, jj, ss, m, n).prS.tobytes()
