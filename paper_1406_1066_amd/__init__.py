@@ -12,7 +12,7 @@ from .api import (  # noqa: F401
     append_workspace_bytes,
     SparseAssemble, assemble, assemble_batched, backward, dims, get_tuning,
     reassemble, set_tuning, sparse, sparse_append, sparse_complex, sparse_expand,
-    sparse_logical, sparse_noalloc, logical_workspace_bytes,
+    sparse_logical, sparse_noalloc, sparse_stream, logical_workspace_bytes,
     stream_copy,
     timing,
     to_torch_csc, version, workspace_bytes,

@@ -552,6 +552,56 @@ def sparse_append(A: "Assembled", ii, jj, ss: torch.Tensor,
                   drop_zeros, need)
 
 
+def sparse_stream(chunks, m: Optional[int] = None, n: Optional[int] = None,
+                  *, dtype=torch.float64, device=None) -> "Assembled":
+    """Delayed assembly of a stream of triplet chunks held in host memory.
+
+    ``chunks`` yields ``(ii, jj, ss)`` triplets (numpy arrays or CPU
+    tensors; indices unit-offset).  The stream as a whole may be larger than
+    the device memory; the assembled matrix must fit.  Each chunk is copied
+    to the device from pinned memory on a side stream while the previous
+    one is merged into the matrix, then appended (``sparse_append``).  The
+    result is bit-identical to one assembly of the concatenated chunks.
+    ``m``/``n`` default to the largest indices seen.
+    """
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    side = torch.cuda.Stream(device=dev)
+    cur = torch.cuda.current_stream(dev)
+
+    def stage(ch):
+        ii, jj, ss = (_as_tensor(x) for x in ch)
+        ss = ss.to(dtype)
+        host = [t.contiguous().pin_memory() for t in (ii, jj, ss)]
+        with torch.cuda.stream(side):
+            d = [t.to(dev, non_blocking=True) for t in host]
+            ev = torch.cuda.Event()
+            ev.record(side)
+        return d, host, ev
+
+    it = iter(chunks)
+    nxt = None
+    first = next(it, None)
+    if first is None:
+        e = torch.empty(0, dtype=torch.int32, device=dev)
+        return sparse(e, e, torch.empty(0, dtype=dtype, device=dev),
+                      m or 0, n or 0)
+    pending = stage(first)
+    A = None
+    while pending is not None:
+        (ii, jj, ss), host, ev = pending
+        cur.wait_event(ev)
+        for t in (ii, jj, ss):
+            t.record_stream(cur)
+        nxt = next(it, None)
+        pending = stage(nxt) if nxt is not None else None
+        if A is None:
+            A = sparse(ii, jj, ss, m, n)
+        else:
+            A = sparse_append(A, ii, jj, ss, m, n)
+        del host
+    return A
+
+
 def sparse_expand(ii, jj, ss: torch.Tensor, m: Optional[int] = None,
                   n: Optional[int] = None, nzmax: Optional[int] = None, *,
                   atomic: bool = False, keep_slot: bool = False,

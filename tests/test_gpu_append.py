@@ -163,3 +163,22 @@ def test_merge_of_columns_longer_than_a_merge_block(fs):
     res, ref = chain(fs, ii, jj, ss, [L // 3], m, n)
     assert res.prS.cpu().numpy().tobytes() == \
         oracle.assemble(ii, jj, ss, m, n).prS.tobytes()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_stream_of_host_chunks(fs, dtype):
+    # a mesh streamed from host memory in uneven element chunks: the result
+    # is one assembly of everything
+    t = W.fem3d(16, 0.15, seed=74, dtype=dtype)
+    per = t.per_elem
+    ne = t.L // per
+    cuts = [0, per * 3, per * (ne // 3), per * (ne // 2), per * (ne - 1), t.L]
+
+    def chunks():
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            yield t.ii[a:b], t.jj[a:b], t.ss[a:b]
+    res = fs.sparse_stream(chunks(), dtype=torch.float64
+                           if dtype == np.float64 else torch.float32)
+    ref = oracle.assemble(t.ii, t.jj, t.ss)
+    assert (res.m, res.n) == (ref.m, ref.n)
+    assert_same(res, ref, slot=False)
