@@ -1869,7 +1869,7 @@ fsparse_status fsparse_assemble_batched(
     if (keep && launch_reuse_tiles(ws, lo, L, stream) != hipSuccess) return FSPARSE_E_HIP;
     if (nb > 1) {
       e = launch(kBatchedJcs, stream, [&] {
-        hipLaunchKernelGGL(fsp::k_batched_jcs, dim3(grid_for(N + nb, 256, 16)),
+        hipLaunchKernelGGL(fsp::k_batched_jcs, dim3(grid_for((N + nb + 31) / 32, 256, 8)),
                            dim3(256), 0, stream, jcg, at<int64_t>(ws, lo.b_col), nb,
                            (int64_t)(N + nb), jcS, dnnz);
       });

@@ -2237,12 +2237,20 @@ __global__ void k_batched_jcs(const int32_t* __restrict__ jcg,
                               const int64_t* __restrict__ col_off, int32_t nb,
                               int64_t total, int32_t* __restrict__ jcS,
                               int64_t* __restrict__ nnz_off) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t b = idx; b <= nb; b += stride) nnz_off[b] = jcg[col_off[b]];
-  if (idx >= total) return;
-  // matrix b owns positions [col_off[b] + b, col_off[b+1] + b + 1); a thread's
-  // positions increase, so after one search its matrix only moves forward
+  {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t b = i0; b <= nb; b += (int64_t)gridDim.x * blockDim.x)
+      nnz_off[b] = jcg[col_off[b]];
+  }
+  // each block takes one contiguous range of positions and its threads step
+  // through it together (coalesced); matrix b owns positions
+  // [col_off[b] + b, col_off[b+1] + b + 1); a thread's positions increase by
+  // the block size, so after one search its matrix only moves forward
+  const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+  const int64_t p1 = min(total, (int64_t)(blockIdx.x + 1) * per);
+  const int64_t stride = blockDim.x;
+  int64_t idx = (int64_t)blockIdx.x * per + threadIdx.x;
+  if (idx >= p1) return;
   int lo = 0, hi = nb;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -2250,7 +2258,7 @@ __global__ void k_batched_jcs(const int32_t* __restrict__ jcg,
   }
   int64_t first = col_off[lo], start = first + lo, next = col_off[lo + 1] + lo + 1;
   int32_t jb = jcg[first];
-  for (; idx < total; idx += stride) {
+  for (; idx < p1; idx += stride) {
     while (idx >= next) {
       ++lo;
       first = col_off[lo];
