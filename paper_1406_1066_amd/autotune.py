@@ -2,9 +2,10 @@
 
 For a given input it times candidate tunings on the device -- the
 bin-placement mode (count matrix, fixed-capacity bins, count then place)
-with the LDS capacity of the bin workgroups, then their thread count, then
-the streaming block size, each stage keeping the best of the one before
-(coordinate descent over the space), then the re-assembly block size --
+together with the LDS capacity of the bin workgroups and their thread count
+(which together set how many bin workgroups share a compute unit), then the
+streaming block size over the best of those, then the re-assembly block
+size --
 checks that every candidate produces byte-identical output, applies the
 fastest, and caches the choice per device and per *config class* -- the
 size of the problem in powers of two of L (triplets), N (columns) and L/N,
@@ -38,7 +39,7 @@ STAGES = [
      "chunk_block": [256, 512, 1024]},
     {"stream_block": [256, 512]},
 ]
-START = {"chunk_cap": 4096, "chunk_block": 1024, "stream_block": 256,
+START = {"chunk_cap": 2048, "chunk_block": 512, "stream_block": 256,
          "bin_mode": "auto"}
 REUSE_BLOCKS = [256, 512, 1024]
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)),

@@ -31,12 +31,15 @@ namespace {
 // ---------------------------------------------------------------------------
 // tuning
 // ---------------------------------------------------------------------------
+// Defaults: the shapes the autotuner picks on MI355X for the mesh and
+// random benchmark inputs (2048-entry bins with 512 threads, two bin
+// workgroups per CU).
 struct Tuning {
-  int cap = 4096;
+  int cap = 2048;
   int sblock = 256;
   int sitems = 8;
-  int rblock = 256;
-  int cblock = 1024;  // threads of one bin workgroup
+  int rblock = 512;
+  int cblock = 512;  // threads of one bin workgroup
   int bmode = 0;     // 0 automatic, else 1 + BinMode to force one
 };
 std::mutex g_mu;

@@ -51,8 +51,8 @@ def test_tuning_validation():
     import paper_1406_1066_amd as fs
     fs.set_tuning(reset=True)
     d = fs.get_tuning()
-    assert d == {"chunk_cap": 4096, "stream_block": 256, "stream_items": 8,
-                 "reuse_block": 256, "chunk_block": 1024, "bin_mode": 0}
+    assert d == {"chunk_cap": 2048, "stream_block": 256, "stream_items": 8,
+                 "reuse_block": 512, "chunk_block": 512, "bin_mode": 0}
     fs.set_tuning(chunk_cap=64)
     assert fs.get_tuning()["chunk_cap"] == 64
     with pytest.raises(fs.FsparseError):
