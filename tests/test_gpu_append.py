@@ -182,3 +182,38 @@ def test_stream_of_host_chunks(fs, dtype):
     ref = oracle.assemble(t.ii, t.jj, t.ss)
     assert (res.m, res.n) == (ref.m, ref.n)
     assert_same(res, ref, slot=False)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_merge_edges(fs, dtype):
+    rng = np.random.default_rng(100)
+    ii = rng.integers(1, 40, 2000).astype(np.int32)
+    jj = rng.integers(1, 30, 2000).astype(np.int32)
+    ss = rng.standard_normal(2000).astype(dtype)
+    e32 = np.zeros(0, np.int32)
+    # appending to an empty matrix (no stored pairs, no columns)
+    A0 = fs.sparse(to_dev(e32), to_dev(e32), to_dev(np.zeros(0, dtype)), 0, 0)
+    r = fs.sparse_append(A0, to_dev(ii), to_dev(jj), to_dev(ss), keep_slot=True)
+    ref = oracle.append(oracle.assemble(e32, e32, np.zeros(0, dtype), 0, 0),
+                        ii, jj, ss)
+    assert_same(r, ref)
+    # appending nothing
+    A = fs.sparse(to_dev(ii), to_dev(jj), to_dev(ss), 40, 30)
+    r = fs.sparse_append(A, to_dev(e32), to_dev(e32),
+                         to_dev(np.zeros(0, dtype)), keep_slot=True)
+    assert_same(r, oracle.assemble(ii, jj, ss, 40, 30), slot=False)
+    assert r.slot.cpu().numpy().tolist() == list(range(A.nnz))
+    # new triplets only in columns past the stored ones, with a given and
+    # with default dimensions (the new part is assembled over its own
+    # column range)
+    i2 = rng.integers(1, 60, 500).astype(np.int32)
+    j2 = rng.integers(45, 52, 500).astype(np.int32)
+    s2 = rng.standard_normal(500).astype(dtype)
+    ra = oracle.assemble(ii, jj, ss, 40, 30)
+    for m, n in ((60, 55), (None, None)):
+        r = fs.sparse_append(A, to_dev(i2), to_dev(j2), to_dev(s2), m, n,
+                             keep_slot=True)
+        assert_same(r, oracle.append(ra, i2, j2, s2, m, n))
+    # a new column index past a given n is an index error
+    with pytest.raises(fs.FsparseIndexError):
+        fs.sparse_append(A, to_dev(i2), to_dev(j2), to_dev(s2), 60, 50)
