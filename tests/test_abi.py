@@ -166,3 +166,17 @@ def test_no_sync_and_narrowing_argument_errors_without_gpu():
     assert L.fsparse_indices_i32(None, L.IDX_I64, 0, None, None) == L.OK
     # backward: a negative length is an error, nnz = 0 is not (all zeros)
     assert L.fsparse_backward(one, 0, None, 0, L.F64, one, None) == L.OK
+
+
+def test_append_workspace_covers_both_paths():
+    # the append workspace holds the merge path (the new triplets' own
+    # fresh workspace behind B's arrays) and the re-assembly of everything
+    from paper_1406_1066_amd import _lib as L
+    for nnzA, ln, n in ((0, 0, 0), (10, 0, 5), (0, 1000, 50), (5000, 700, 300),
+                        (1 << 20, 1 << 16, 1 << 12)):
+        for dt in (L.F64, L.F32):
+            a = L.fsparse_append_workspace_bytes(nnzA, ln, n, dt)
+            assert a >= L.fsparse_workspace_bytes(nnzA + ln, n, 1, dt)
+            assert a >= L.fsparse_workspace_bytes(ln, n, 1, dt) + 4 * (n + 1)
+    assert L.fsparse_append_workspace_bytes(-1, 1, 1, L.F64) == 0
+    assert L.fsparse_append_workspace_bytes(1, 1, 1, 9) == 0
