@@ -52,7 +52,9 @@ ROLES = [("fsp::k_scatter", "scatter"), ("fsp::k_bin", "bin"),
          ("fsp::k_copy16", "copy")]
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, public spec
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SRC = os.path.join(ROOT, "paper_1406_1066_amd", "csrc", "kernels.h")
+# the kernels and the host code that chooses their launch shapes
+KERNEL_SRC = [os.path.join(ROOT, "paper_1406_1066_amd", "csrc", f)
+              for f in ("kernels.h", "fsparse.hip")]
 
 
 def log(*a):
@@ -60,8 +62,11 @@ def log(*a):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def fresh_bytes(L, nnz, ncols, nmat, vb):
