@@ -17,10 +17,11 @@
  *    is marked "host".  The library never allocates device memory; scratch
  *    comes from the caller's workspace `ws` (fsparse_assemble_noalloc uses
  *    a fixed device array inside the library instead).
- *  - Work is stream-ordered on `stream`.  Only fsparse_assemble,
- *    fsparse_assemble_batched and fsparse_dims wait for the stream (once, to
- *    read back result sizes and the error flags), and fsparse_assemble does
- *    not with FSPARSE_NO_SYNC; re-assembly and backward never synchronise.
+ *  - Work is stream-ordered on `stream`.  The calls that assemble or find
+ *    dimensions wait for the stream to read back result sizes and the error
+ *    flags (each call states how often); fsparse_assemble and its variants
+ *    do not with FSPARSE_NO_SYNC.  Re-assembly, backward and index narrowing
+ *    never synchronise.
  *  - Values are IEEE binary64 (FSPARSE_F64) or binary32 (FSPARSE_F32); the sum
  *    of a repeated pair is computed in that type.
  *  - In the default ordered mode the contributions to prS[t] are added from
