@@ -1826,14 +1826,33 @@ fsparse_status fsparse_assemble_batched(
     m32[b] = (int32_t)mm[b];
     n32[b] = (int32_t)nn[b];
   }
-  HIPCHK(hipMemcpyAsync(at<int64_t>(ws, lo.b_trip), trip_off, 8 * (size_t)(nb + 1),
-                        hipMemcpyHostToDevice, stream));
-  HIPCHK(hipMemcpyAsync(at<int64_t>(ws, lo.b_col), col.data(), 8 * (size_t)(nb + 1),
-                        hipMemcpyHostToDevice, stream));
-  HIPCHK(hipMemcpyAsync(at<int32_t>(ws, lo.b_m), m32.data(), 4 * (size_t)nb,
-                        hipMemcpyHostToDevice, stream));
-  HIPCHK(hipMemcpyAsync(at<int32_t>(ws, lo.b_n), n32.data(), 4 * (size_t)nb,
-                        hipMemcpyHostToDevice, stream));
+  // the four tables lie back to back in ws (b_trip, b_col, b_m, b_n): one
+  // copy from pinned memory laid out the same way, else four copies
+  auto put_tables = [&](const Layout& l) -> hipError_t {
+    const size_t span = l.b_n + 4 * (size_t)nb - l.b_trip;
+    char* hp = static_cast<char*>(pinned());
+    if (hp && span <= kPinnedBytes) {
+      std::memcpy(hp + (l.b_trip - l.b_trip), trip_off, 8 * (size_t)(nb + 1));
+      std::memcpy(hp + (l.b_col - l.b_trip), col.data(), 8 * (size_t)(nb + 1));
+      std::memcpy(hp + (l.b_m - l.b_trip), m32.data(), 4 * (size_t)nb);
+      std::memcpy(hp + (l.b_n - l.b_trip), n32.data(), 4 * (size_t)nb);
+      return hipMemcpyAsync(at<char>(ws, l.b_trip), hp, span, hipMemcpyHostToDevice,
+                            stream);
+    }
+    hipError_t r = hipMemcpyAsync(at<int64_t>(ws, l.b_trip), trip_off,
+                                  8 * (size_t)(nb + 1), hipMemcpyHostToDevice, stream);
+    if (r == hipSuccess)
+      r = hipMemcpyAsync(at<int64_t>(ws, l.b_col), col.data(), 8 * (size_t)(nb + 1),
+                         hipMemcpyHostToDevice, stream);
+    if (r == hipSuccess)
+      r = hipMemcpyAsync(at<int32_t>(ws, l.b_m), m32.data(), 4 * (size_t)nb,
+                         hipMemcpyHostToDevice, stream);
+    if (r == hipSuccess)
+      r = hipMemcpyAsync(at<int32_t>(ws, l.b_n), n32.data(), 4 * (size_t)nb,
+                         hipMemcpyHostToDevice, stream);
+    return r;
+  };
+  HIPCHK(put_tables(lo));
   BatchDesc bd{at<int64_t>(ws, lo.b_trip), at<int64_t>(ws, lo.b_col),
                at<int32_t>(ws, lo.b_m), at<int32_t>(ws, lo.b_n), nb};
   const bool keep = plan != nullptr;
@@ -1895,14 +1914,7 @@ fsparse_status fsparse_assemble_batched(
       // kept their size: copy them again
       l2.mmax = mmax;
       lo = l2;
-      HIPCHK(hipMemcpyAsync(at<int64_t>(ws, lo.b_trip), trip_off, 8 * (size_t)(nb + 1),
-                            hipMemcpyHostToDevice, stream));
-      HIPCHK(hipMemcpyAsync(at<int64_t>(ws, lo.b_col), col.data(), 8 * (size_t)(nb + 1),
-                            hipMemcpyHostToDevice, stream));
-      HIPCHK(hipMemcpyAsync(at<int32_t>(ws, lo.b_m), m32.data(), 4 * (size_t)nb,
-                            hipMemcpyHostToDevice, stream));
-      HIPCHK(hipMemcpyAsync(at<int32_t>(ws, lo.b_n), n32.data(), 4 * (size_t)nb,
-                            hipMemcpyHostToDevice, stream));
+      HIPCHK(put_tables(lo));
       bd = BatchDesc{at<int64_t>(ws, lo.b_trip), at<int64_t>(ws, lo.b_col),
                      at<int32_t>(ws, lo.b_m), at<int32_t>(ws, lo.b_n), nb};
       slot_used = slot ? slot : (keep ? at<int32_t>(ws, lo.islot) : nullptr);
