@@ -1882,28 +1882,28 @@ fsparse_status fsparse_assemble_batched(
   if (!h || sizeof(Ctrl) + 8 * (size_t)(nb + 1) > kPinnedBytes) return FSPARSE_E_ARG;
   int mode = lo.g.mode;
   for (;;) {
+    // the bin kernel's last block writes nnz and the error bits of the
+    // earlier kernels into the pinned control block, and the column-pointer
+    // kernel writes the matrices' offsets beside it: no copy back
     if (dt == FSPARSE_F64)
       e = run_pipeline<double, true>(ii, jj, (const double*)ss, L, 0, 0, bd, N, lo,
                                      tu, ws, jcg, irS, (double*)prS, cap, slot_used,
-                                     keep, mode, stream);
+                                     keep, mode, stream, reinterpret_cast<Ctrl*>(h));
     else
       e = run_pipeline<float, true>(ii, jj, (const float*)ss, L, 0, 0, bd, N, lo, tu,
                                     ws, jcg, irS, (float*)prS, cap, slot_used, keep,
-                                    mode, stream);
+                                    mode, stream, reinterpret_cast<Ctrl*>(h));
     if (e != hipSuccess) return FSPARSE_E_HIP;
     if (keep && launch_reuse_tiles(ws, lo, L, stream) != hipSuccess) return FSPARSE_E_HIP;
     if (nb > 1) {
+      int64_t* hoff = reinterpret_cast<int64_t*>(h + sizeof(Ctrl));
       e = launch(kBatchedJcs, stream, [&] {
         hipLaunchKernelGGL(fsp::k_batched_jcs, dim3(grid_for((N + nb + 31) / 32, 256, 8)),
                            dim3(256), 0, stream, jcg, at<int64_t>(ws, lo.b_col), nb,
-                           (int64_t)(N + nb), jcS, dnnz);
+                           (int64_t)(N + nb), jcS, dnnz, hoff);
       });
       if (e != hipSuccess) return FSPARSE_E_HIP;
     }
-    HIPCHK(hipMemcpyAsync(h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream));
-    if (nb > 1)
-      HIPCHK(hipMemcpyAsync(h + sizeof(Ctrl), dnnz, 8 * (size_t)(nb + 1),
-                            hipMemcpyDeviceToHost, stream));
     HIPCHK(hipStreamSynchronize(stream));
     if ((reinterpret_cast<const Ctrl*>(h)->err & fsp::kErrSlot) && mode == kSlot) {
       // a full fixed-capacity bin: count first, in narrower bins, and redo
@@ -1940,7 +1940,8 @@ fsparse_status fsparse_assemble_batched(
       info[b].nzmax = info[b].nnz;
     }
   if (hc->err & (fsp::kErrCol | fsp::kErrRow)) return FSPARSE_E_INDEX;
-  if (hc->err & fsp::kErrCap) return FSPARSE_E_CAPACITY;
+  // (an overflow flagged after the last bin shows as nnz beyond the capacity)
+  if ((hc->err & fsp::kErrCap) || nnz > cap) return FSPARSE_E_CAPACITY;
   if (flags & FSPARSE_ATOMIC) {
     if (!slot_used) return FSPARSE_E_ARG;
     hipError_t ea = dt == FSPARSE_F64

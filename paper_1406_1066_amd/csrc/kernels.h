@@ -2236,11 +2236,17 @@ k_bin(ChunkArgs<VT> a, BinSrc src, int32_t w) {
 __global__ void k_batched_jcs(const int32_t* __restrict__ jcg,
                               const int64_t* __restrict__ col_off, int32_t nb,
                               int64_t total, int32_t* __restrict__ jcS,
-                              int64_t* __restrict__ nnz_off) {
+                              int64_t* __restrict__ nnz_off, int64_t* host_off) {
   {
+    // the matrices' offsets, on the device and in the caller's pinned host
+    // memory (system-scope stores, read once the stream is synchronized)
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t b = i0; b <= nb; b += (int64_t)gridDim.x * blockDim.x)
-      nnz_off[b] = jcg[col_off[b]];
+    for (int64_t b = i0; b <= nb; b += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t v = jcg[col_off[b]];
+      nnz_off[b] = v;
+      if (host_off)
+        __hip_atomic_store(&host_off[b], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
   // each block takes one contiguous range of positions and its threads step
   // through it together (coalesced); matrix b owns positions
