@@ -250,3 +250,23 @@ def test_host_value_tensors_are_refused(fs):
     res = fs.sparse(ii, ii, to_dev(np.array([1.0, 2.0])), 2, 2, plan=True)
     with pytest.raises(ValueError):
         fs.reassemble(res, host)
+
+
+@pytest.mark.parametrize("mode", ["auto", "slot", "claim"])
+def test_batched_capacity_below_nnz(fs, mode):
+    # a capacity below the total of distinct pairs is refused with the
+    # capacity status (every bin mode), and the same call with room succeeds
+    fs.set_tuning(bin_mode=mode)
+    try:
+        b = W.batched_fem2d(5, 1e3, 2e4, seed=12)
+        ii, jj, ss, m, n = b.concat()
+        d = [to_dev(a) for a in (ii, jj, ss)]
+        full = fs.assemble_batched(*d, b.trip_off, m, n)
+        with pytest.raises(fs.FsparseError) as e:
+            fs.assemble_batched(*d, b.trip_off, m, n, cap=full.nnz_off[-1] - 1)
+        assert e.value.status == 3
+        ok = fs.assemble_batched(*d, b.trip_off, m, n, cap=full.nnz_off[-1])
+        assert ok.prS.cpu().numpy().tobytes() == full.prS.cpu().numpy().tobytes()
+        assert ok.nnz_off == full.nnz_off
+    finally:
+        fs.set_tuning(reset=True)
