@@ -786,20 +786,22 @@ def assemble_batched(ii, jj, ss: torch.Tensor, trip_off: Sequence[int],
     nb = len(m)
     # the library reads the arrays through trip_off and has no lengths of
     # its own to check them against
-    if len(n) != nb or len(trip_off) != nb + 1:
+    tof = np.ascontiguousarray(np.asarray(trip_off, dtype=np.int64))
+    ma = np.ascontiguousarray(np.asarray(m, dtype=np.int64))
+    na = np.ascontiguousarray(np.asarray(n, dtype=np.int64))
+    if na.size != nb or tof.size != nb + 1:
         raise ValueError("trip_off needs nb+1 entries and m, n nb each")
-    if int(trip_off[0]) != 0 or any(int(trip_off[b + 1]) < int(trip_off[b])
-                                    for b in range(nb)):
+    if tof[0] != 0 or (nb > 0 and bool((tof[1:] < tof[:-1]).any())):
         raise ValueError("trip_off must start at 0 and not decrease")
-    if not (int(trip_off[-1]) == ii.numel() == jj.numel() == ss.numel()):
+    if not (int(tof[-1]) == ii.numel() == jj.numel() == ss.numel()):
         raise ValueError("trip_off[-1] must equal the length of ii, jj, ss")
     _need(ss, "ss", ss.numel(), ss.dtype, dev)
     if ws is not None:
         _need(ws, "ws", 0, torch.uint8, dev)
-    to = (ctypes.c_int64 * (nb + 1))(*[int(x) for x in trip_off])
-    mm = (ctypes.c_int64 * nb)(*[int(x) for x in m])
-    nn = (ctypes.c_int64 * nb)(*[int(x) for x in n])
-    if any(int(x) < 0 for x in m) or any(int(x) < 0 for x in n):
+    to = tof.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    mm = ma.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    nn = na.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    if bool((ma < 0).any()) or bool((na < 0).any()):
         dm = (ctypes.c_int64 * nb)()
         dn = (ctypes.c_int64 * nb)()
         w0 = _workspace(workspace_bytes(0, 0, nb, ss.dtype), dev)
@@ -807,14 +809,12 @@ def assemble_batched(ii, jj, ss: torch.Tensor, trip_off: Sequence[int],
                                       _ptr(w0), w0.numel(), _stream()),
                "fsparse_dims_batched")
         for b in range(nb):
-            if mm[b] < 0:
-                mm[b] = dm[b]
-            if nn[b] < 0:
-                nn[b] = dn[b]
-        m = [mm[b] for b in range(nb)]
-        n = [nn[b] for b in range(nb)]
-    Ln = int(trip_off[-1])
-    N = sum(int(x) for x in n)
+            if ma[b] < 0:
+                ma[b] = dm[b]
+            if na[b] < 0:
+                na[b] = dn[b]
+    Ln = int(tof[-1])
+    N = int(na.sum())
     if cap is None:
         cap = max(Ln, 1)
     need = workspace_bytes(Ln, N, nb, ss.dtype)
@@ -826,22 +826,20 @@ def assemble_batched(ii, jj, ss: torch.Tensor, trip_off: Sequence[int],
     slot = None
     if keep_slot or plan or atomic:
         slot = torch.empty(max(Ln, 1), dtype=torch.int32, device=dev)
-    off = (ctypes.c_int64 * (nb + 1))()
-    info = (L.FsparseInfo * nb)()
+    off = np.zeros(nb + 1, dtype=np.int64)
     ph = ctypes.c_void_p()
     _check(L.fsparse_assemble_batched(
         nb, to, _ptr(ii), _ptr(jj), _ptr(ss), _dt(ss.dtype), mm, nn,
         L.ATOMIC if atomic else L.ORDERED, _ptr(jcS), jcS.numel(), _ptr(irS),
-        _ptr(prS), cap, off, _ptr(slot), _ptr(ws), ws.numel(),
-        ctypes.byref(ph) if plan else None, info, _stream()),
+        _ptr(prS), cap, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+        _ptr(slot), _ptr(ws), ws.numel(),
+        ctypes.byref(ph) if plan else None, None, _stream()),
         "fsparse_assemble_batched")
-    nnz_off = [int(off[b]) for b in range(nb + 1)]
-    col_off = [0]
-    for b in range(nb):
-        col_off.append(col_off[-1] + int(n[b]))
+    nnz_off = off.tolist()
+    col_off = [0] + np.cumsum(na).tolist()
     p = _Plan(ph, [ws, slot], Ln, nnz_off[-1], ss.dtype) if plan else None
     return Batched(jcS, irS[:nnz_off[-1]], prS[:nnz_off[-1]], nnz_off,
-                   col_off, [int(x) for x in m], [int(x) for x in n],
+                   col_off, ma.tolist(), na.tolist(),
                    slot[:Ln] if slot is not None else None, p, ws)
 
 
