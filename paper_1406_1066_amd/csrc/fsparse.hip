@@ -93,12 +93,17 @@ hipError_t launch(int stage, hipStream_t s, F&& f) {
   return e;
 }
 
+// Set while fsparse_assemble_noalloc runs on this thread: its launches
+// carry no timing events (creating one would allocate).
+thread_local bool t_noalloc = false;
+
 template <typename F>
 hipError_t launch_raw(int stage, hipStream_t s, F&& f) {
   bool timing;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    timing = g_timing && stage >= 0 && stage < 32 && ((g_stage_mask >> stage) & 1u);
+    timing = g_timing && !t_noalloc && stage >= 0 && stage < 32 &&
+             ((g_stage_mask >> stage) & 1u);
   }
   if (!timing) {
     f();
@@ -1232,6 +1237,10 @@ fsparse_status fsparse_assemble_noalloc(const int32_t* ii, const int32_t* jj,
     return FSPARSE_E_CAPACITY;
   void* ws = scratch_ptr();
   if (!ws) return FSPARSE_E_HIP;
+  struct NoAlloc {
+    NoAlloc() { t_noalloc = true; }
+    ~NoAlloc() { t_noalloc = false; }
+  } guard;
   // the queued pipeline (counted bins: no host-decided redo), which clears
   // the control block and look-back words it uses, then one wait to read
   // them back
