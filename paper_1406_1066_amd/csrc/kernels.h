@@ -1665,11 +1665,29 @@ __device__ __forceinline__ void bin_load(const ChunkArgs<VT>& a, const BinSrc& s
 }
 
 // Fast path: the bin's triplets fit the LDS and are already in registers.
-// Columns are known per triplet, so equal (column,row) pairs are grouped by
-// hashing straight away; the distinct rows of each column are ranked,
-// contributions of a pair are put in increasing k and folded from +0.0.
-// Meanwhile the next bin (ticket `tk`, taken by thread 0) has its range and
-// entries fetched into `nx`.  Returns base + distinct count.
+// Equal (column,row) pairs are grouped by hashing straight away and the
+// triplets of a pair are counted at their pair's hash slot.  Each rank cell
+// (a column's row range) counts its distinct pairs and, once the groups are
+// complete, their triplets, in one packed word, so one scan of the cells
+// gives the column offsets, a coarse rank and the first place of every
+// cell's triplets.  Ranking the distinct rows of a cell then also gives
+// their groups' first places (no scan of the group sizes).  Contributions of
+// a pair are put in increasing k and folded from +0.0.  Meanwhile the next
+// bin (ticket `tk`, taken by thread 0) has its range and entries fetched
+// into `nx`.  Returns base + distinct count.
+//
+// LDS (bytes, capacity CAP; a region's later tenants take it once the
+// earlier ones are dead):
+//   [0, 8CAP)         hash keys u32[2CAP] -> distinct list u32[CAP]
+//                     -> placed values VT[CAP]
+//   [8CAP, 16CAP)     triplets per hash slot u32[2CAP] -> (output, first
+//                     place) per hash slot -> k-ordered values VT[CAP]
+//   [16CAP, 24CAP)    entry rows and columns u32[CAP] each (unshared
+//                     columns) -> (row, triplets) per distinct u32x2[CAP]
+//                     -> placed k u32[CAP] + group of placed u32[CAP]
+//   [24CAP, 28CAP)    row of each output
+//   [28CAP, 32CAP+4)  (distinct, triplets) per rank cell, then scanned
+//   [32CAP+4, 36CAP+8) first place of each output's group (+ the end)
 template <typename VT, int CAP, int NT>
 __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
                             const ChunkCtx<VT, CAP, NT>& x,
@@ -1683,33 +1701,54 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   const int wc = c1 - c0;
   const uint32_t cmask = (1u << a.rshift) - 1u;  // packed keys only
   // packed words are unique keys of the (column, row) pairs (never kEmpty):
-  // the hash table then holds the keys themselves
+  // the hash table then holds the keys themselves, else entry indices
   const bool keyed = src.bcol == nullptr;
   FSP_PHASE(a, q, 1)
-  uint32_t* ht = x.ht();
-  uint32_t* row = x.row();
-  uint32_t* col = x.cs();
-  uint32_t* drow = x.cend();
-  uint32_t* cnt = x.cnt();
-  uint32_t* cd = x.cd();
+  unsigned char* sm = x.smem;
+  uint32_t* ht = reinterpret_cast<uint32_t*>(sm);
+  uint32_t* dlist = ht;
+  VT* mval = reinterpret_cast<VT*>(sm);
+  uint32_t* hcnt = reinterpret_cast<uint32_t*>(sm + 8 * CAP);
+  VT* sval = reinterpret_cast<VT*>(sm + 8 * CAP);
+  uint32_t* row = reinterpret_cast<uint32_t*>(sm + 16 * CAP);
+  uint32_t* col = reinterpret_cast<uint32_t*>(sm + 20 * CAP);
+  uint2* drc = reinterpret_cast<uint2*>(sm + 16 * CAP);
+  uint32_t* mk = reinterpret_cast<uint32_t*>(sm + 16 * CAP);
+  uint32_t* mgrp = reinterpret_cast<uint32_t*>(sm + 20 * CAP);
+  uint32_t* grow = reinterpret_cast<uint32_t*>(sm + 24 * CAP);
+  uint32_t* cd = reinterpret_cast<uint32_t*>(sm + 28 * CAP);
+  uint32_t* gs = reinterpret_cast<uint32_t*>(sm + 32 * CAP + 4);
 
-  // distinct rows are counted per (column, row range) cell, so one scan
-  // gives both the column offsets and a coarse rank; a row is then compared
-  // only with the rows of its own cell
+  // rank cells: distinct pairs (low half) and triplets (high half) of each
+  // (column, row range) cell
   const int ncell = wc << a.nbl;
-  for (int i = tid; i < H; i += NT) ht[i] = kEmpty;
-  for (int i = tid; i < span; i += NT) cnt[i] = 0u;
+  {
+    uint4* h4 = reinterpret_cast<uint4*>(ht);
+    uint4* c4 = reinterpret_cast<uint4*>(hcnt);
+    const uint4 e = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = tid; i < H / 4; i += NT) {
+      h4[i] = e;
+      c4[i] = z;
+    }
+  }
   for (int i = tid; i <= ncell; i += NT) cd[i] = 0u;
-  uint32_t kr[EPT];
+  uint32_t rr[EPT], kr[EPT];
   VT vr[EPT];
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
-    const int i = tid + j * NT;
-    if (i < span) {
-      row[i] = cur.en[j].row;
-      if (!keyed) col[i] = src.bcol[e0 + i];
-      kr[j] = cur.en[j].k;
-      vr[j] = cur.en[j].v;
+    rr[j] = cur.en[j].row;
+    kr[j] = cur.en[j].k;
+    vr[j] = cur.en[j].v;
+  }
+  if (!keyed) {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int i = tid + j * NT;
+      if (i < span) {
+        row[i] = rr[j];
+        col[i] = src.bcol[e0 + i];
+      }
     }
   }
   __syncthreads();
@@ -1717,22 +1756,22 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   FSP_PHASE(a, q, 2)
   // group equal (column,row) pairs.  The first probes of all of a thread's
   // triplets are issued together, then collisions are resolved, then the
-  // group and cell counters are bumped, so the LDS atomics overlap.
-  uint32_t repa[EPT], dpos[EPT], hh[EPT], cell[EPT];
+  // slot and cell counters are bumped, so the LDS atomics overlap.  The
+  // triplet that claims an empty slot represents its pair.
+  // hh: hash slot, then slot | arrival << 16; cell: rank cell, then
+  // cell | place among its cell's distinct pairs << 16 (0xFFFF: not a
+  // representative)
+  uint32_t hh[EPT], cell[EPT], arr[EPT];
   if (keyed) {
-    // the table holds keys; a probe ends at an empty slot (claimed: this
-    // triplet represents its pair) or at its own key.  Representatives then
-    // leave their index beside the slot (hidx: the column-start and
-    // column-end arrays, unused with packed keys, 2*CAP words).
-    uint32_t* hidx = col;
+    // the table holds keys; a probe ends at an empty slot or at its own key
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
       const int i = tid + j * NT;
       if (i < span) {
-        const uint32_t r = row[i];
+        const uint32_t r = rr[j];
         cell[j] = rank_cell(a, r & cmask, r);
         hh[j] = pair_hash(r & cmask, r) & (H - 1);
-        repa[j] = atomicCAS(&ht[hh[j]], kEmpty, r);
+        arr[j] = atomicCAS(&ht[hh[j]], kEmpty, r);
       }
     }
     FSP_PHASE(a, q, 10)
@@ -1742,69 +1781,73 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
       if (i < span) {
         // triangular probing: growing steps visit every slot of the
         // power-of-two table without building long runs
-        const uint32_t r = row[i];
-        uint32_t old = repa[j], h = hh[j], step = 1;
+        const uint32_t r = rr[j];
+        uint32_t old = arr[j], h = hh[j], step = 1;
         while (old != kEmpty && old != r) {
           h = (h + step++) & (H - 1);
           old = atomicCAS(&ht[h], kEmpty, r);
         }
         hh[j] = h;
-        repa[j] = old == kEmpty ? (uint32_t)i : kEmpty;
-        if (old == kEmpty) hidx[h] = (uint32_t)i;
+        arr[j] = old;
       }
     }
-    __syncthreads();
+  } else {
+    // the table holds entry indices; a probe compares the stored pair
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
       const int i = tid + j * NT;
-      if (i < span && repa[j] == kEmpty) repa[j] = hidx[hh[j]];
-    }
-  } else {
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) {
-    const int i = tid + j * NT;
-    if (i < span) {
-      const uint32_t c = col[i], r = row[i];
-      cell[j] = rank_cell(a, c, r);
-      hh[j] = pair_hash(c, r) & (H - 1);
-      repa[j] = atomicCAS(&ht[hh[j]], kEmpty, (uint32_t)i);
-    }
-  }
-  FSP_PHASE(a, q, 10)
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) {
-    const int i = tid + j * NT;
-    if (i < span) {
-      // an empty slot was claimed (this triplet represents its pair), or the
-      // slot holds the same pair, or probing goes on, by growing steps
-      // (triangular probing visits every slot of the power-of-two table and
-      // does not build the long runs that one-slot steps do)
-      uint32_t old = repa[j], h = hh[j], rep = (uint32_t)i, step = 1;
-      if (old != kEmpty) {
-        const uint32_t c = col[i], r = row[i];
-        while (old != kEmpty) {
-          if (col[old] == c && row[old] == r) { rep = old; break; }
-          h = (h + step++) & (H - 1);
-          old = atomicCAS(&ht[h], kEmpty, (uint32_t)i);
-        }
+      if (i < span) {
+        const uint32_t c = col[i], r = rr[j];
+        cell[j] = rank_cell(a, c, r);
+        hh[j] = pair_hash(c, r) & (H - 1);
+        arr[j] = atomicCAS(&ht[hh[j]], kEmpty, (uint32_t)i);
       }
-      repa[j] = rep;
     }
-  }
+    FSP_PHASE(a, q, 10)
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int i = tid + j * NT;
+      if (i < span) {
+        uint32_t old = arr[j], h = hh[j], step = 1;
+        if (old != kEmpty) {
+          const uint32_t c = col[i], r = rr[j];
+          while (old != kEmpty) {
+            if (col[old] == c && row[old] == r) break;
+            h = (h + step++) & (H - 1);
+            old = atomicCAS(&ht[h], kEmpty, (uint32_t)i);
+          }
+        }
+        hh[j] = h;
+        arr[j] = old;
+      }
+    }
   }
   FSP_PHASE(a, q, 11)
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int i = tid + j * NT;
     if (i < span) {
-      const uint32_t arr = atomicAdd(&cnt[repa[j]], 1u);
-      dpos[j] = (repa[j] == (uint32_t)i) ? atomicAdd(&cd[cell[j]], 1u) : kEmpty;
-      repa[j] |= arr << 16;
+      const bool rep = arr[j] == kEmpty;
+      const uint32_t av = atomicAdd(&hcnt[hh[j]], 1u);
+      const uint32_t cw = rep ? atomicAdd(&cd[cell[j]], 0x10001u) : 0xFFFFu;
+      hh[j] |= av << 16;
+      cell[j] |= (cw & 0xFFFFu) << 16;
     }
   }
   FSP_PHASE(a, q, 12)
   if (tid == 0) x.misc()[7] = tk;
   FSP_PHASE(a, q, 13)
+  __syncthreads();
+  // the groups are complete: representatives add the rest of their group's
+  // triplets to their cell
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int i = tid + j * NT;
+    if (i < span && (cell[j] >> 16) != 0xFFFFu) {
+      const uint32_t c = hcnt[hh[j] & 0xFFFFu];
+      if (c > 1u) atomicAdd(&cd[cell[j] & 0xFFFFu], (c - 1u) << 16);
+    }
+  }
   __syncthreads();
   // next bin: its range now, its entries once the placement is done
   nx.q = (int)x.misc()[7];
@@ -1812,150 +1855,128 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   bin_bounds(src, nx, nfill);
 
   FSP_PHASE(a, q, 3)
-  // distinct pairs per column -> offsets; publish the bin's count now, read
-  // the prefix of the earlier bins only when emitting
-  const uint32_t D = lds_excl_scan<NT>(cd, ncell + 1, x.wave());
+  // distinct pairs and triplets per cell -> offsets; publish the bin's count
+  // now, read the prefix of the earlier bins only when emitting
+  const uint32_t D = lds_excl_scan<NT>(cd, ncell + 1, x.wave()) & 0xFFFFu;
   if (tid < 64) lookback_publish(a.status, q, pack_agg((uint64_t)span, D));
-  uint32_t* dlist = x.dlist();
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int i = tid + j * NT;
-    if (i < span && dpos[j] != kEmpty) {
-      const uint32_t r = row[i];
-      const uint32_t d = cd[rank_cell(a, keyed ? (r & cmask) : col[i], r)] + dpos[j];
-      dlist[d] = (uint32_t)i;
-      drow[d] = r;
+    if (i < span && (cell[j] >> 16) != 0xFFFFu) {
+      const uint32_t cl = cell[j] & 0xFFFFu, h = hh[j] & 0xFFFFu;
+      const uint32_t d = (cd[cl] & 0xFFFFu) + (cell[j] >> 16);
+      dlist[d] = h | (cl << 16);
+      drc[d] = make_uint2(rr[j], hcnt[h]);
     }
   }
   __syncthreads();
 
   FSP_PHASE(a, q, 4)
-  // rank the distinct rows of every cell
-  uint32_t* gout = x.gout();
-  uint32_t* gs = x.gs();
-  uint32_t* grow = x.grow();
+  // rank the distinct rows of every cell; the triplets of the smaller rows
+  // give the group's first place.  Each hash slot then holds its pair's
+  // output index (low half) and first place (high half).
   // (EPT distinct rows per thread at a time, so that their loads overlap)
   for (int d0 = tid; d0 < (int)D; d0 += EPT * NT) {
-    uint32_t di[EPT], dr[EPT], lo[EPT], hi[EPT];
+    uint32_t dw[EPT], lo[EPT], hi[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const int d = d0 + u * NT;
-      di[u] = kEmpty;
-      if (d < (int)D) {
-        di[u] = dlist[d];
-        dr[u] = drow[d];
+      dw[u] = d < (int)D ? dlist[d] : kEmpty;
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      if (dw[u] != kEmpty) {
+        const uint32_t cl = dw[u] >> 16;
+        lo[u] = cd[cl];
+        hi[u] = cd[cl + 1];
       }
     }
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
-      if (di[u] != kEmpty) {
-        const uint32_t cell = rank_cell(a, keyed ? (dr[u] & cmask) : col[di[u]], dr[u]);
-        lo[u] = cd[cell];
-        hi[u] = cd[cell + 1];
+      if (dw[u] == kEmpty) continue;
+      // count smaller rows and their triplets, four reads in flight per
+      // step; reads past the cell's end stay inside the LDS block and are
+      // masked out
+      const uint32_t r0 = drc[d0 + u * NT].x, t0 = lo[u] & 0xFFFFu, e = hi[u] & 0xFFFFu;
+      uint32_t rk = 0, tri = 0;
+      for (uint32_t t = t0; t < e; t += 4) {
+        const uint2 v0 = drc[t], v1 = drc[t + 1], v2 = drc[t + 2], v3 = drc[t + 3];
+        const bool b0 = v0.x < r0, b1 = t + 1 < e && v1.x < r0;
+        const bool b2 = t + 2 < e && v2.x < r0, b3 = t + 3 < e && v3.x < r0;
+        rk += (b0 ? 1u : 0u) + (b1 ? 1u : 0u) + (b2 ? 1u : 0u) + (b3 ? 1u : 0u);
+        tri += (b0 ? v0.y : 0u) + (b1 ? v1.y : 0u) + (b2 ? v2.y : 0u) + (b3 ? v3.y : 0u);
       }
-    }
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      if (di[u] == kEmpty) continue;
-      // count smaller rows, four reads in flight per step; reads past the
-      // cell's end stay inside the LDS block and are masked out
-      const uint32_t r0 = dr[u], e = hi[u];
-      uint32_t rk = 0;
-      for (uint32_t t = lo[u]; t < e; t += 4) {
-        const uint32_t v0 = drow[t], v1 = drow[t + 1], v2 = drow[t + 2], v3 = drow[t + 3];
-        rk += (v0 < r0 ? 1u : 0u) + ((t + 1 < e && v1 < r0) ? 1u : 0u) +
-              ((t + 2 < e && v2 < r0) ? 1u : 0u) + ((t + 3 < e && v3 < r0) ? 1u : 0u);
-      }
-      const uint32_t o = lo[u] + rk;
-      gout[di[u]] = o;
-      gs[o] = cnt[di[u]];
+      const uint32_t o = t0 + rk;
+      const uint32_t g = (lo[u] >> 16) + tri;
+      hcnt[dw[u] & 0xFFFFu] = o | (g << 16);
       grow[o] = r0;
+      gs[o] = g;
     }
   }
-  if (tid == 0) gs[D] = 0;
+  if (tid == 0) gs[D] = (uint32_t)span;
   __syncthreads();
   FSP_PHASE(a, q, 5)
   // every pair occurs once (common for scattered inputs): group o is the
-  // single place o, so there is nothing to scan and nothing to order by k
+  // single place o, so there is nothing to order by k
   const bool uniq = D == (uint32_t)span;
-  if (!uniq) lds_excl_scan<NT>(gs, (int)D + 1, x.wave());
   FSP_PHASE(a, q, 6)
 
-  VT* sval = reinterpret_cast<VT*>(x.cend());  // free since the rank
-  uint32_t* mk = row;
-  uint32_t* mgrp = col;
-  uint32_t posr[EPT], orr[EPT];
+  // values in sorted place: the placed values themselves when every pair
+  // occurs once, else the k-ordered copy
+  VT* ovals = uniq ? mval : sval;
+  uint32_t orr[EPT];
   uint32_t spos[EPT];  // sorted position of a triplet (own, or placed)
   uint64_t probe = 0;
-  if (uniq) {
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const int i = tid + j * NT;
-      if (i < span) {
-        const uint32_t o = gout[i];
-        orr[j] = o;
-        spos[j] = o;
-        sval[o] = vr[j];
-      }
-    }
-    bin_range(src, nx, nfill);
-    bin_load<VT, NT, EPT>(a, src, nx);
-    if (tid < 64) probe = lookback_probe(a.status, q);
-  } else {
-  // place triplets into their groups, then order each group by k
+  // place triplets into their groups (by arrival), to be ordered by k
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int i = tid + j * NT;
     if (i < span) {
-      const uint32_t o = gout[repa[j] & 0xFFFFu];
+      const uint32_t w = hcnt[hh[j] & 0xFFFFu];
+      const uint32_t o = w & 0xFFFFu;
+      const uint32_t p = (w >> 16) + (hh[j] >> 16);
       orr[j] = o;
-      posr[j] = gs[o] + (repa[j] >> 16);
-    }
-  }
-  __syncthreads();
-  FSP_PHASE(a, q, 14)
-  VT* mval = x.mval();
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) {
-    const int i = tid + j * NT;
-    if (i < span) {
-      mk[posr[j]] = kr[j];
-      mval[posr[j]] = vr[j];
-      mgrp[posr[j]] = orr[j];
+      spos[j] = p;
+      mval[p] = vr[j];
+      if (!uniq) {
+        mk[p] = kr[j];
+        mgrp[p] = o;
+      }
     }
   }
   bin_range(src, nx, nfill);
   bin_load<VT, NT, EPT>(a, src, nx);
   if (tid < 64) probe = lookback_probe(a.status, q);
-  __syncthreads();
-  FSP_PHASE(a, q, 15)
-  // order each group by k: values go straight to their sorted place, so do
-  // the k of the plan
+  if (!uniq) {
+    __syncthreads();
+    FSP_PHASE(a, q, 15)
+    // order each group by k: values go straight to their sorted place, so do
+    // the k of the plan
 #pragma unroll
-  for (int jj = 0; jj < EPT; ++jj) {
-    const int p = tid + jj * NT;
-    if (p >= span) break;
-    const uint32_t o = mgrp[p];
-    const uint32_t g0 = gs[o], g1 = gs[o + 1];
-    const uint32_t kk = mk[p];
-    // eight reads in flight per step while eight remain, then four, then
-    // one at a time
-    uint32_t r8[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    uint32_t t = g0;
-    for (; t + 8 <= g1; t += 8) {
+    for (int jj = 0; jj < EPT; ++jj) {
+      const int p = tid + jj * NT;
+      if (p >= span) break;
+      const uint32_t o = mgrp[p];
+      const uint32_t g0 = gs[o], g1 = gs[o + 1];
+      const uint32_t kk = mk[p];
+      // eight reads in flight per step while eight remain, then four, then
+      // one at a time
+      uint32_t r8[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+      uint32_t t = g0;
+      for (; t + 8 <= g1; t += 8) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) r8[u] += mk[t + u] < kk ? 1u : 0u;
+        for (int u = 0; u < 8; ++u) r8[u] += mk[t + u] < kk ? 1u : 0u;
+      }
+      if (t + 4 <= g1) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) r8[u] += mk[t + u] < kk ? 1u : 0u;
+        t += 4;
+      }
+      uint32_t rk = ((r8[0] + r8[1]) + (r8[2] + r8[3])) + ((r8[4] + r8[5]) + (r8[6] + r8[7]));
+      for (; t < g1; ++t) rk += mk[t] < kk ? 1u : 0u;
+      sval[g0 + rk] = mval[p];
+      spos[jj] = g0 + rk;
     }
-    if (t + 4 <= g1) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) r8[u] += mk[t + u] < kk ? 1u : 0u;
-      t += 4;
-    }
-    uint32_t rk = ((r8[0] + r8[1]) + (r8[2] + r8[3])) + ((r8[4] + r8[5]) + (r8[6] + r8[7]));
-    for (; t < g1; ++t) rk += mk[t] < kk ? 1u : 0u;
-    sval[g0 + rk] = mval[p];
-    spos[jj] = g0 + rk;
-  }
   }
   FSP_PHASE(a, q, 7)
   if (tid < 64) {
@@ -2013,19 +2034,19 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
     acc[u] = (VT)0;
-    if (g0[u] < g1[u]) acc[u] = acc[u] + sval[g0[u]];
+    if (g0[u] < g1[u]) acc[u] = acc[u] + ovals[g0[u]];
   }
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
     uint32_t t = g0[u] + 1u;
     for (; t + 4 <= g1[u]; t += 4) {
-      const VT v0 = sval[t], v1 = sval[t + 1], v2 = sval[t + 2], v3 = sval[t + 3];
+      const VT v0 = ovals[t], v1 = ovals[t + 1], v2 = ovals[t + 2], v3 = ovals[t + 3];
       acc[u] = acc[u] + v0;
       acc[u] = acc[u] + v1;
       acc[u] = acc[u] + v2;
       acc[u] = acc[u] + v3;
     }
-    for (; t < g1[u]; ++t) acc[u] = acc[u] + sval[t];
+    for (; t < g1[u]; ++t) acc[u] = acc[u] + ovals[t];
   }
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
@@ -2042,7 +2063,8 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
     }
   }
   if (over) atomicOr(&a.ctrl->err, kErrCap);
-  for (int c = tid; c < wc; c += NT) a.jcS[c0 + c] = (int32_t)(base + cd[c << a.nbl]);
+  for (int c = tid; c < wc; c += NT)
+    a.jcS[c0 + c] = (int32_t)(base + (cd[c << a.nbl] & 0xFFFFu));
   FSP_PHASE(a, q, 8)
   return base + D;
 }
@@ -2153,8 +2175,20 @@ k_slow_emit(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
 // published is always either being processed or the next bin of a block
 // whose current bin has only published bins before it, so every wait ends.
 // A block holds at most one ticket beyond the bin it processes.
+// Waves per SIMD that the LDS lets the bin kernel have (160 KB per CU),
+// asked of the register allocator when it still leaves 128 registers a lane
+// (else no request): at 2048 entries and 512 threads two workgroups then
+// share a CU.
+template <int CAP, int NT>
+constexpr int bin_waves() {
+  constexpr int blocks = (160 * 1024) / Lds<CAP>::kBytes;
+  constexpr int w = blocks * (NT / 64) / 4;
+  return w >= 1 && w <= 4 ? w : 1;
+}
+
 template <typename VT, int CAP, int NT>
 __global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(bin_waves<CAP, NT>())))
 k_bin(ChunkArgs<VT> a, BinSrc src, int32_t w) {
   constexpr int EPT = CAP / NT;
   __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<CAP>::kBytes];
