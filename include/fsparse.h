@@ -486,8 +486,14 @@ fsparse_status fsparse_plan_query(const fsparse_plan *plan, int64_t *len,
  * bin_mode chooses how triplets are placed into column bins: 0 automatic,
  * 1 per-tile count matrix (only while the bins fit the LDS counters),
  * 2 fixed-capacity bins filled in one pass, 3 count then place; it is
- * always applied (0 restores the automatic choice).  NULL restores all
- * defaults.
+ * always applied (0 restores the automatic choice).  slot_values: what the
+ * fixed-capacity bins hold for a triplet (zero keeps the current setting):
+ * 1 its value with its row and index k, 2 only its row and k, the sort/fold
+ * stage then reading the value by k from the input (the default: half the
+ * binned bytes, but reads by k that only pay off when triplets of nearby
+ * columns lie near each other in the input, as in element-by-element
+ * assembly; inputs in index-expansion form always bin their values).  NULL
+ * restores all defaults.
  */
 typedef struct {
   int32_t chunk_cap;
@@ -496,6 +502,7 @@ typedef struct {
   int32_t reuse_block;
   int32_t chunk_block;
   int32_t bin_mode;
+  int32_t slot_values;
 } fsparse_tuning;
 
 fsparse_status fsparse_set_tuning(const fsparse_tuning *t);

@@ -39,7 +39,8 @@ class FsparseTuning(ctypes.Structure):
                 ("stream_items", ctypes.c_int32),
                 ("reuse_block", ctypes.c_int32),
                 ("chunk_block", ctypes.c_int32),
-                ("bin_mode", ctypes.c_int32)]
+                ("bin_mode", ctypes.c_int32),
+                ("slot_values", ctypes.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):

@@ -853,14 +853,18 @@ def to_torch_csc(res: Assembled) -> torch.Tensor:
 
 
 BIN_MODES = {"auto": 0, "dense": 1, "slot": 2, "claim": 3}
+SLOT_VALUES = {"binned": 1, "by_k": 2}
 
 
 def set_tuning(chunk_cap: int = 0, stream_block: int = 0,
                stream_items: int = 0, reuse_block: int = 0,
-               chunk_block: int = 0, bin_mode=None, reset: bool = False):
+               chunk_block: int = 0, bin_mode=None, slot_values=None,
+               reset: bool = False):
     """Launch-shape tuning (process-wide); zero / None keeps a field.
 
-    ``bin_mode``: "auto", "dense", "slot" or "claim" (see fsparse.h)."""
+    ``bin_mode``: "auto", "dense", "slot" or "claim"; ``slot_values``:
+    "binned" or "by_k", what the fixed-capacity bins hold for a triplet
+    besides its row and k (see fsparse.h)."""
     if reset:
         _check(L.fsparse_set_tuning(None), "fsparse_set_tuning")
         return
@@ -868,8 +872,12 @@ def set_tuning(chunk_cap: int = 0, stream_block: int = 0,
         bm = get_tuning()["bin_mode"]
     else:
         bm = BIN_MODES[bin_mode] if isinstance(bin_mode, str) else int(bin_mode)
+    sv = 0
+    if slot_values is not None:
+        sv = (SLOT_VALUES[slot_values] if isinstance(slot_values, str)
+              else int(slot_values))
     t = L.FsparseTuning(chunk_cap, stream_block, stream_items, reuse_block,
-                        chunk_block, bm)
+                        chunk_block, bm, sv)
     _check(L.fsparse_set_tuning(ctypes.byref(t)), "fsparse_set_tuning")
 
 
@@ -878,7 +886,8 @@ def get_tuning() -> dict:
     _check(L.fsparse_get_tuning(ctypes.byref(t)), "fsparse_get_tuning")
     return {"chunk_cap": t.chunk_cap, "stream_block": t.stream_block,
             "stream_items": t.stream_items, "reuse_block": t.reuse_block,
-            "chunk_block": t.chunk_block, "bin_mode": t.bin_mode}
+            "chunk_block": t.chunk_block, "bin_mode": t.bin_mode,
+            "slot_values": t.slot_values}
 
 
 class timing:

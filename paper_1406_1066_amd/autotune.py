@@ -3,9 +3,10 @@
 For a given input it times candidate tunings on the device -- the
 bin-placement mode (count matrix, fixed-capacity bins, count then place)
 together with the LDS capacity of the bin workgroups and their thread count
-(which together set how many bin workgroups share a compute unit), then the
-streaming block size over the best of those, then the re-assembly block
-size --
+(which together set how many bin workgroups share a compute unit), then
+whether fixed-capacity bins hold the values or the bin stage reads them by
+triplet index, then the streaming block size over the best of those, then
+the re-assembly block size --
 checks that every candidate produces byte-identical output, applies the
 fastest, and caches the choice per device and per *config class* -- the
 size of the problem in powers of two of L (triplets), N (columns) and L/N,
@@ -37,10 +38,11 @@ STAGES = [
     {"bin_mode": ["auto", "dense", "slot", "claim"],
      "chunk_cap": [1024, 2048, 4096],
      "chunk_block": [256, 512, 1024]},
+    {"slot_values": ["binned", "by_k"]},
     {"stream_block": [256, 512]},
 ]
 START = {"chunk_cap": 2048, "chunk_block": 512, "stream_block": 256,
-         "bin_mode": "auto"}
+         "bin_mode": "auto", "slot_values": "by_k"}
 REUSE_BLOCKS = [256, 512, 1024]
 TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)),
                      "tune_table.json")
@@ -132,7 +134,7 @@ def _effective(c: dict) -> tuple:
     4096/512)."""
     cap = c["chunk_cap"]
     nt = max(cap // 8, min(c["chunk_block"], cap))
-    return (c["bin_mode"], cap, nt, c["stream_block"])
+    return (c["bin_mode"], cap, nt, c["stream_block"], c["slot_values"])
 
 
 def tune(ii, jj, ss: torch.Tensor, m: int, n: int, *, trip_off=None,

@@ -41,6 +41,7 @@ struct Tuning {
   int rblock = 512;
   int cblock = 512;  // threads of one bin workgroup
   int bmode = 0;     // 0 automatic, else 1 + BinMode to force one
+  int keys = 1;      // fixed-capacity bins hold (row, k) only; values read by k
 };
 std::mutex g_mu;
 Tuning g_tune;
@@ -624,6 +625,10 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   if (BATCHED) mmax = lo.mmax;
   const int packed = (mmax < (int64_t(1) << (32 - s))) ? 1 : 0;
   const int32_t slotcap = mode == kSlot ? (int32_t)g.slotcap : 0;
+  // fixed-capacity bins may hold (row, k) alone: the bin kernel then reads
+  // the values by k (not with the expansion map, whose values are indexed
+  // by grid point)
+  const bool keys = mode == kSlot && tu.keys && SRC != fsp::kIdxExpand;
   // 1. bin counts (the slot mode has none)
   if (mode != kSlot) e = launch(kHist, stream, [&] {
     if (mode == kDense)
@@ -672,18 +677,19 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
                            (uint32_t)std::max<int64_t>(L, g.nslot), ctrl, ex);
     } else {
       const uint32_t trash = (uint32_t)std::max<int64_t>(L, g.nslot);
-      if (packed)
-        hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, true, SRC, kClaimNT, kClaimIPT>),
-                           dim3((unsigned)g.T), dim3(kClaimNT),
-                           (size_t)kClaimWindow * 4, stream, ii, jj, ss, L, m, n, bd,
-                           G, kClaimWindow, binstart, slotcap, binfill, bucket, bcol,
-                           trash, ctrl, ex);
-      else
-        hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, false, SRC, kClaimNT, kClaimIPT>),
-                           dim3((unsigned)g.T), dim3(kClaimNT),
-                           (size_t)kClaimWindow * 4, stream, ii, jj, ss, L, m, n, bd,
-                           G, kClaimWindow, binstart, slotcap, binfill, bucket, bcol,
-                           trash, ctrl, ex);
+#define FSP_CLAIM(P, K)                                                        \
+  hipLaunchKernelGGL((fsp::k_scatter_claim<VT, BATCHED, P, SRC, kClaimNT, kClaimIPT, K>), \
+                     dim3((unsigned)g.T), dim3(kClaimNT), (size_t)kClaimWindow * 4, \
+                     stream, ii, jj, ss, L, m, n, bd, G, kClaimWindow, binstart,  \
+                     slotcap, binfill, bucket, bcol, trash, ctrl, ex)
+      if constexpr (SRC != fsp::kIdxExpand) {
+        if (keys) {
+          if (packed) FSP_CLAIM(true, true); else FSP_CLAIM(false, true);
+          return;
+        }
+      }
+      if (packed) FSP_CLAIM(true, false); else FSP_CLAIM(false, false);
+#undef FSP_CLAIM
     }
   });
   if (e != hipSuccess) return e;
@@ -692,6 +698,7 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
   a.colptr = nullptr;
   a.chunk_col = nullptr;
   a.bucket = bucket;
+  a.vals = keys ? ss : nullptr;
   a.tmp = at<Entry<VT>>(ws, lo.tmp);
   a.N = (int32_t)N;
   a.T = 0;
@@ -743,9 +750,14 @@ hipError_t run_pipeline(const int32_t* ii, const int32_t* jj, const VT* ss,
       hipLaunchKernelGGL((fsp::k_slow_count<VT, C, T>), dim3(sgrid), dim3(T), 0, \
                          stream, a, binstart, bcol_in, colptr_g, w, slowlist, \
                          slowd);                                               \
-    hipLaunchKernelGGL((fsp::k_bin<VT, C, T>),                                 \
-                       dim3((unsigned)std::min<int64_t>(B, resident<fsp::k_bin<VT, C, T>>(T))), \
-                       dim3(T), 0, stream, a, src, w);                         \
+    if (keys)                                                                  \
+      hipLaunchKernelGGL((fsp::k_bin<VT, C, T, true>),                         \
+                         dim3((unsigned)std::min<int64_t>(B, resident<fsp::k_bin<VT, C, T, true>>(T))), \
+                         dim3(T), 0, stream, a, src, w);                       \
+    else                                                                       \
+      hipLaunchKernelGGL((fsp::k_bin<VT, C, T, false>),                        \
+                         dim3((unsigned)std::min<int64_t>(B, resident<fsp::k_bin<VT, C, T, false>>(T))), \
+                         dim3(T), 0, stream, a, src, w);                       \
     if (may_slow)                                                              \
       hipLaunchKernelGGL((fsp::k_slow_emit<VT, C, T>), dim3(sgrid), dim3(T), 0, \
                          stream, a, binstart, colptr_g, w, slowlist, slowb);   \
@@ -2104,6 +2116,8 @@ fsparse_status fsparse_set_tuning(const fsparse_tuning* t) {
   }
   if (t->bin_mode < 0 || t->bin_mode > 3) return FSPARSE_E_ARG;
   n.bmode = t->bin_mode;
+  if (t->slot_values < 0 || t->slot_values > 2) return FSPARSE_E_ARG;
+  if (t->slot_values) n.keys = t->slot_values == 2 ? 1 : 0;
   g_tune = n;
   return FSPARSE_OK;
 }
@@ -2117,6 +2131,7 @@ fsparse_status fsparse_get_tuning(fsparse_tuning* t) {
   t->reuse_block = g_tune.rblock;
   t->chunk_block = g_tune.cblock;
   t->bin_mode = g_tune.bmode;
+  t->slot_values = g_tune.keys ? 2 : 1;
   return FSPARSE_OK;
 }
 

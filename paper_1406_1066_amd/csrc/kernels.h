@@ -32,6 +32,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace fsp {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
@@ -73,6 +75,11 @@ template <>
 struct Entry<float> {
   uint32_t row, k;
   float v;
+};
+// A binned triplet without its value (fixed-capacity bins, values read by k
+// in the bin kernel).
+struct __attribute__((aligned(8))) KeyEntry {
+  uint32_t row, k;
 };
 
 // Several matrices assembled by the same launches: matrix b owns triplets
@@ -985,7 +992,7 @@ k_count_claim(const int32_t* __restrict__ jj, int64_t L, int32_t n,
   }
 }
 
-template <typename VT, bool BATCHED, bool PACKED, int SRC, int NT, int IPT>
+template <typename VT, bool BATCHED, bool PACKED, int SRC, int NT, int IPT, bool KEYS>
 __global__ void __launch_bounds__(NT)
 k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
                 const VT* __restrict__ ss, int64_t L, int32_t m, int32_t n,
@@ -1049,7 +1056,7 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
         sv[u] = ss[exp_at(ex.sv, o)];
       } else {
         ri[u] = ld_index<SRC>(ii, e);
-        sv[u] = ss[e];
+        if constexpr (!KEYS) sv[u] = ss[e];
       }
     }
     uint32_t pos[kScatterU], key[kScatterU], bc[kScatterU];
@@ -1082,8 +1089,11 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
     }
 #pragma unroll
     for (int u = 0; u < kScatterU; ++u) {
-      store_entry<VT>(&bucket[pos[u]], key[u],
-                      (uint32_t)(t0 + (int64_t)(j0 + u) * NT + threadIdx.x), sv[u]);
+      const uint32_t k = (uint32_t)(t0 + (int64_t)(j0 + u) * NT + threadIdx.x);
+      if constexpr (KEYS)
+        reinterpret_cast<KeyEntry*>(bucket)[pos[u]] = KeyEntry{key[u], k};
+      else
+        store_entry<VT>(&bucket[pos[u]], key[u], k, sv[u]);
       if (!PACKED) bcol[pos[u]] = bc[u];
     }
   }
@@ -1099,6 +1109,7 @@ struct ChunkArgs {
   const int32_t* colptr;     // [N+1] triplet column pointers
   const int32_t* chunk_col;  // [Q+1]
   Entry<VT>* bucket;         // [Ltot] (overwritten only on the long path)
+  const VT* vals;            // values by triplet when the bins hold KeyEntry
   Entry<VT>* tmp;            // [Ltot] scratch of the long path
   int32_t N;                 // columns (all matrices)
   int32_t T;                 // window length (triplets)
@@ -1613,10 +1624,10 @@ struct BinSrc {
 
 // A bin's range in the bucket and, when it fits the LDS, its entries in
 // registers: the bin kernel loads the next bin while finishing the current.
-template <typename VT, int EPT>
+template <typename VT, int EPT, bool KEYS>
 struct BinRegs {
   int q, e0, e1;
-  Entry<VT> en[EPT];
+  typename std::conditional<KEYS, KeyEntry, Entry<VT>>::type en[EPT];
 };
 
 // Issue the loads of bin q's range.  The same three words are read in every
@@ -1626,9 +1637,8 @@ struct BinRegs {
 // lane 1 binstart[q+1], lane 2 binfill[q]): a wave-uniform load would be
 // moved to scalar registers, and waited for, at once.  A ticket past the
 // last bin reads bin B-1's words; bin_range then makes its range empty.
-template <typename VT, int EPT>
-__device__ __forceinline__ void bin_bounds(const BinSrc& src, BinRegs<VT, EPT>& r,
-                                           uint32_t& w) {
+template <class R>
+__device__ __forceinline__ void bin_bounds(const BinSrc& src, R& r, uint32_t& w) {
   const int qc = min(r.q, src.B - 1);
   const int lane = lane_id();
   const uint32_t* p = lane == 2 ? &src.binfill[qc]
@@ -1636,9 +1646,8 @@ __device__ __forceinline__ void bin_bounds(const BinSrc& src, BinRegs<VT, EPT>& 
   w = *p;
 }
 
-template <typename VT, int EPT>
-__device__ __forceinline__ void bin_range(const BinSrc& src, BinRegs<VT, EPT>& r,
-                                          uint32_t w) {
+template <class R>
+__device__ __forceinline__ void bin_range(const BinSrc& src, R& r, uint32_t w) {
   r.e0 = (int)__builtin_amdgcn_readlane(w, 0);
   r.e1 = (int)__builtin_amdgcn_readlane(w, 1);
   const uint32_t fill = __builtin_amdgcn_readlane(w, 2);
@@ -1653,14 +1662,17 @@ __device__ __forceinline__ void bin_range(const BinSrc& src, BinRegs<VT, EPT>& r
 // bin reading its first place, which is at most the bucket's spare place),
 // so that later waits for other loads never have to cover these.  A slow
 // bin's entries are not used (the slow path reads the bucket).
-template <typename VT, int NT, int EPT>
+template <typename VT, int NT, int EPT, bool KEYS>
 __device__ __forceinline__ void bin_load(const ChunkArgs<VT>& a, const BinSrc& src,
-                                         BinRegs<VT, EPT>& r) {
+                                         BinRegs<VT, EPT, KEYS>& r) {
   const int last = max(r.e1 - r.e0 - 1, 0);
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
     const int i = threadIdx.x + j * NT;
-    r.en[j] = load_entry<VT>(&a.bucket[r.e0 + min(i, last)]);
+    if constexpr (KEYS)
+      r.en[j] = reinterpret_cast<const KeyEntry*>(a.bucket)[r.e0 + min(i, last)];
+    else
+      r.en[j] = load_entry<VT>(&a.bucket[r.e0 + min(i, last)]);
   }
 }
 
@@ -1688,11 +1700,11 @@ __device__ __forceinline__ void bin_load(const ChunkArgs<VT>& a, const BinSrc& s
 //   [24CAP, 28CAP)    row of each output
 //   [28CAP, 32CAP+4)  (distinct, triplets) per rank cell, then scanned
 //   [32CAP+4, 36CAP+8) first place of each output's group (+ the end)
-template <typename VT, int CAP, int NT>
+template <typename VT, int CAP, int NT, bool KEYS>
 __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
                             const ChunkCtx<VT, CAP, NT>& x,
-                            const BinRegs<VT, CAP / NT>& cur, int c0, int c1,
-                            uint32_t tk, BinRegs<VT, CAP / NT>& nx) {
+                            const BinRegs<VT, CAP / NT, KEYS>& cur, int c0, int c1,
+                            uint32_t tk, BinRegs<VT, CAP / NT, KEYS>& nx) {
   constexpr int EPT = CAP / NT;
   constexpr int H = 2 * CAP;
   const int tid = threadIdx.x;
@@ -1739,7 +1751,13 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   for (int j = 0; j < EPT; ++j) {
     rr[j] = cur.en[j].row;
     kr[j] = cur.en[j].k;
-    vr[j] = cur.en[j].v;
+    if constexpr (KEYS) {
+      // read by k now, first used when the triplets are placed
+      vr[j] = (VT)0;
+      if (tid + j * NT < span) vr[j] = a.vals[kr[j]];
+    } else {
+      vr[j] = cur.en[j].v;
+    }
   }
   if (!keyed) {
 #pragma unroll
@@ -1945,7 +1963,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
     }
   }
   bin_range(src, nx, nfill);
-  bin_load<VT, NT, EPT>(a, src, nx);
+  bin_load<VT, NT, EPT, KEYS>(a, src, nx);
   if (tid < 64) probe = lookback_probe(a.status, q);
   if (!uniq) {
     __syncthreads();
@@ -2186,7 +2204,7 @@ constexpr int bin_waves() {
   return w >= 1 && w <= 4 ? w : 1;
 }
 
-template <typename VT, int CAP, int NT>
+template <typename VT, int CAP, int NT, bool KEYS>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(bin_waves<CAP, NT>())))
 k_bin(ChunkArgs<VT> a, BinSrc src, int32_t w) {
@@ -2198,13 +2216,13 @@ k_bin(ChunkArgs<VT> a, BinSrc src, int32_t w) {
   const int B = src.B;
   if (threadIdx.x == 0) misc[0] = (int64_t)atomicAdd(src.tick, 1u);
   __syncthreads();
-  BinRegs<VT, EPT> cur, nx;
+  BinRegs<VT, EPT, KEYS> cur, nx;
   cur.q = (int)misc[0];
   if (cur.q < B) {
     uint32_t fill;
     bin_bounds(src, cur, fill);
     bin_range(src, cur, fill);
-    bin_load<VT, NT, EPT>(a, src, cur);
+    bin_load<VT, NT, EPT, KEYS>(a, src, cur);
   }
   while (cur.q < B) {
     const int q = cur.q;
@@ -2219,7 +2237,7 @@ k_bin(ChunkArgs<VT> a, BinSrc src, int32_t w) {
     if (threadIdx.x == 0) tk = atomicAdd(src.tick, 1u);
     int64_t end = 0;
     if (cur.e1 - cur.e0 <= a.cap) {
-      end = bin_fast<VT, CAP, NT>(a, src, x, cur, c0, c1, tk, nx);
+      end = bin_fast<VT, CAP, NT, KEYS>(a, src, x, cur, c0, c1, tk, nx);
     } else {
       // a slow bin: counted before this kernel, emitted after it; here its
       // count only passes through the look-back
@@ -2242,7 +2260,7 @@ k_bin(ChunkArgs<VT> a, BinSrc src, int32_t w) {
         uint32_t fill;
         bin_bounds(src, nx, fill);
         bin_range(src, nx, fill);
-        bin_load<VT, NT, EPT>(a, src, nx);
+        bin_load<VT, NT, EPT, KEYS>(a, src, nx);
       }
     }
     if (q == B - 1 && threadIdx.x == 0) {

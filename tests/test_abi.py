@@ -52,13 +52,20 @@ def test_tuning_validation():
     fs.set_tuning(reset=True)
     d = fs.get_tuning()
     assert d == {"chunk_cap": 2048, "stream_block": 256, "stream_items": 8,
-                 "reuse_block": 512, "chunk_block": 512, "bin_mode": 0}
+                 "reuse_block": 512, "chunk_block": 512, "bin_mode": 0,
+                 "slot_values": 2}
     fs.set_tuning(chunk_cap=64)
     assert fs.get_tuning()["chunk_cap"] == 64
+    fs.set_tuning(slot_values="binned")
+    assert fs.get_tuning()["slot_values"] == 1
+    fs.set_tuning(chunk_cap=128)          # zero keeps the setting
+    assert fs.get_tuning()["slot_values"] == 1
     with pytest.raises(fs.FsparseError):
         fs.set_tuning(chunk_cap=3000)
     with pytest.raises(fs.FsparseError):
         fs.set_tuning(stream_block=100)
+    with pytest.raises(fs.FsparseError):
+        fs.set_tuning(slot_values=3)
     fs.set_tuning(reset=True)
     assert fs.get_tuning() == d
 

@@ -37,7 +37,9 @@ def test_autotune_small(tmp_path, monkeypatch):
             in r1["times_ms"]
         cur = fs.get_tuning()
         for k, v in r1["best"].items():
-            if k != "bin_mode":
+            if k == "slot_values":
+                assert cur[k] == fs.api.SLOT_VALUES[v]
+            elif k != "bin_mode":
                 assert cur[k] == v
         d = json.load(open(tmp_path / "tune.json"))
         assert r1["key"] in d

@@ -68,6 +68,31 @@ def test_reuse_with_long_columns(fs):
 
 
 # ---------------------------------------------------------------------------
+# fixed-capacity bins with the values binned, or with (row, k) only and the
+# values read by k in the bin stage
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_slot_values_binned_and_by_k(fs, dtype):
+    cases = [W.fem3d(14, 0.15, seed=31, dtype=dtype),
+             W.uniform(60_000, 3000, 2500, seed=32).astype(dtype)]
+    try:
+        for t in cases:
+            ref = oracle.assemble(t.ii, t.jj, t.ss, t.m, t.n)
+            s2 = (t.ss * 1.5 - 0.25).astype(dtype)
+            want = oracle.reassemble(ref, t.ii, t.jj, s2)
+            for sv in ("binned", "by_k"):
+                fs.set_tuning(reset=True)
+                fs.set_tuning(bin_mode="slot", slot_values=sv)
+                res = run(fs, t.ii, t.jj, t.ss, t.m, t.n, plan=True,
+                          keep_slot=True)
+                assert_same(res, ref)
+                got = fs.reassemble(res, to_dev(s2)).cpu().numpy()
+                assert got.tobytes() == want.tobytes()
+    finally:
+        fs.set_tuning(reset=True)
+
+
+# ---------------------------------------------------------------------------
 # atomic mode: order-free sums within the stated tolerance
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-14), (np.float32, 1e-6)])

@@ -92,7 +92,8 @@ def draw_case(seed, lmax=400_000):
                 chunk_block=int(rng.choice([256, 512, 1024])),
                 stream_block=int(rng.choice([64, 256, 512, 1024])),
                 reuse_block=int(rng.choice([64, 256, 1024])),
-                bin_mode=str(rng.choice(MODES)))
+                bin_mode=str(rng.choice(MODES)),
+                slot_values=str(rng.choice(["binned", "by_k"])))
     desc = ("seed %d L %d m %d n %d kind %s rep %.1f %s given %s %r"
             % (seed, Lt, m, n, kind, rep, np.dtype(dtype).name, given, tune))
     return (ii.astype(np.int32), jj.astype(np.int32), ss, mm, nn, tune, desc)
