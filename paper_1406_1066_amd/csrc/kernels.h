@@ -1942,8 +1942,9 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   // values in sorted place: the placed values themselves when every pair
   // occurs once, else the k-ordered copy
   VT* ovals = uniq ? mval : sval;
-  uint32_t orr[EPT];
-  uint32_t spos[EPT];  // sorted position of a triplet (own, or placed)
+  // sorted position of a triplet: its own (every pair once: its output
+  // index), else the placed one's
+  uint32_t spos[EPT];
   uint64_t probe = 0;
   // place triplets into their groups (by arrival), to be ordered by k
 #pragma unroll
@@ -1953,7 +1954,6 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
       const uint32_t w = hcnt[hh[j] & 0xFFFFu];
       const uint32_t o = w & 0xFFFFu;
       const uint32_t p = (w >> 16) + (hh[j] >> 16);
-      orr[j] = o;
       spos[j] = p;
       mval[p] = vr[j];
       if (!uniq) {
@@ -2025,7 +2025,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
 #pragma unroll
       for (int j = 0; j < EPT; ++j) {
         const int i = tid + j * NT;
-        if (i < span) a.slot[kr[j]] = (int32_t)(base + orr[j]);
+        if (i < span) a.slot[kr[j]] = (int32_t)(base + spos[j]);
       }
     } else {
       for (int p = tid; p < span; p += NT) a.slot[mk[p]] = (int32_t)(base + mgrp[p]);
