@@ -1009,6 +1009,13 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
   int32_t bn[IPT], cj[IPT], lo, hi;
   bool bad = false;
   tile_bins<BATCHED, SRC, NT, IPT>(jj, L, n, bd, G, t0, &sB, bn, cj, lo, hi, bad, ex);
+  // the rows too, so that their loads overlap the placement
+  int32_t rpre[IPT];
+  if constexpr (SRC != kIdxExpand) {
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+      rpre[j] = ld_index<SRC>(ii, min(t0 + (int64_t)j * NT + threadIdx.x, L - 1));
+  }
   // (block_minmax ends with a barrier after thread 0's reads below)
   if (slotcap > 0 && threadIdx.x == 0)
     sStop = (__hip_atomic_load(&ctrl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
@@ -1055,7 +1062,7 @@ k_scatter_claim(const int32_t* __restrict__ ii, const int32_t* __restrict__ jj,
         ri[u] = ii[exp_at(ex.si, o)];
         sv[u] = ss[exp_at(ex.sv, o)];
       } else {
-        ri[u] = ld_index<SRC>(ii, e);
+        ri[u] = rpre[j0 + u];
         if constexpr (!KEYS) sv[u] = ss[e];
       }
     }
