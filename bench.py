@@ -225,7 +225,7 @@ def tune(fs, args, *a, **kw):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="batched_64")
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
@@ -308,9 +308,13 @@ def bench_batched(args, batch, fs, torch, np, vb):
     tuning = tune(fs, args, iid, jjd, ssd, list(m), list(n), trip_off=off)
     ws = torch.empty(fs.workspace_bytes(L, N, nb, ssd.dtype),
                      dtype=torch.uint8, device=dev)
+    # output buffers kept across steps (capacity L: nnz <= L)
+    out = (torch.empty(N + nb, dtype=torch.int32, device=dev),
+           torch.empty(L, dtype=torch.int32, device=dev),
+           torch.empty(L, dtype=ssd.dtype, device=dev))
 
     def step():
-        return fs.assemble_batched(iid, jjd, ssd, off, m, n, ws=ws)
+        return fs.assemble_batched(iid, jjd, ssd, off, m, n, ws=ws, out=out)
 
     log("timed steps", args.steps)
     r, el, stages, dom, dom_ms = time_fresh(fs, torch, step, args.steps,

@@ -777,8 +777,14 @@ def assemble_batched(ii, jj, ss: torch.Tensor, trip_off: Sequence[int],
                      m: Sequence[int], n: Sequence[int], *,
                      atomic: bool = False, keep_slot: bool = False,
                      plan: bool = False, cap: Optional[int] = None,
-                     ws: Optional[torch.Tensor] = None) -> Batched:
-    """Assemble nb independent matrices with one set of launches."""
+                     ws: Optional[torch.Tensor] = None,
+                     out: Optional[tuple] = None) -> Batched:
+    """Assemble nb independent matrices with one set of launches.
+
+    ``out = (jcS, irS, prS[, slot])`` supplies preallocated output buffers
+    (jcS at least sum(n) + nb entries; irS/prS capacity = their length; slot
+    the total number of triplets), so that repeated calls allocate nothing
+    for their results."""
     dev = _device(ss, ii, jj)
     ss = ss.contiguous()
     ii = _dev_i32(ii, dev)
@@ -815,16 +821,26 @@ def assemble_batched(ii, jj, ss: torch.Tensor, trip_off: Sequence[int],
                 na[b] = dn[b]
     Ln = int(tof[-1])
     N = int(na.sum())
-    if cap is None:
-        cap = max(Ln, 1)
     need = workspace_bytes(Ln, N, nb, ss.dtype)
     if ws is None or ws.numel() < need:
         ws = _workspace(need, dev)
-    jcS = torch.empty(N + nb, dtype=torch.int32, device=dev)
-    irS = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-    prS = torch.empty(max(cap, 1), dtype=ss.dtype, device=dev)
     slot = None
-    if keep_slot or plan or atomic:
+    if out is not None:
+        jcS, irS, prS = out[0], out[1], out[2]
+        _need(jcS, "jcS", N + nb, torch.int32, dev)
+        _need(irS, "irS", 0, torch.int32, dev)
+        _need(prS, "prS", 0, ss.dtype, dev)
+        if len(out) > 3:
+            slot = out[3]
+            _need(slot, "slot", Ln, torch.int32, dev)
+        cap = min(irS.numel(), prS.numel())
+    else:
+        if cap is None:
+            cap = max(Ln, 1)
+        jcS = torch.empty(N + nb, dtype=torch.int32, device=dev)
+        irS = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        prS = torch.empty(max(cap, 1), dtype=ss.dtype, device=dev)
+    if slot is None and (keep_slot or plan or atomic):
         slot = torch.empty(max(Ln, 1), dtype=torch.int32, device=dev)
     off = np.zeros(nb + 1, dtype=np.int64)
     ph = ctypes.c_void_p()

@@ -120,7 +120,10 @@ hipError_t launch_raw(int stage, hipStream_t s, F&& f) {
       g_pool.pop_back();
     }
   }
-  if (!r.a && (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess))
+  // timing only: no system-scope fence at the events, so that recording
+  // them writes back and invalidates no caches between the timed launches
+  if (!r.a && (hipEventCreateWithFlags(&r.a, hipEventDisableSystemFence) != hipSuccess ||
+               hipEventCreateWithFlags(&r.b, hipEventDisableSystemFence) != hipSuccess))
     return hipErrorOutOfMemory;
   hipEventRecord(r.a, s);
   f();
@@ -233,10 +236,10 @@ constexpr int64_t kDenseBins = 16384;       // LDS counters of the dense mode
 constexpr int kBinFill = 80;                // percent of the capacity per bin
 constexpr int kSlotFill = 88;               // the same with fixed-capacity bins
 constexpr int64_t kDenseMatrix = 8 << 20;   // tiles x bins counters
-// claim tiles: 512 threads with 8 triplets each (4096 per tile); at 16 per
-// thread the scatter needs 136 VGPRs and runs three waves per SIMD, 3% slower
-// on batched_64
-constexpr int kClaimNT = 512;
+// claim tiles: 256 threads with 8 triplets each (2048 per tile).  Measured
+// on the fixed-capacity scatter of batched_64 (ms): 256x8 0.52, 512x8 0.56,
+// 256x16 0.64, 128x16 0.59, 1024x8 0.66, 512x16 0.73, 64x16 0.80.
+constexpr int kClaimNT = 256;
 constexpr int kClaimIPT = 8;
 constexpr int kClaimWindow = 4096;          // LDS bins of one claim tile
 constexpr int kReuseTP = 2048;              // sorted positions per re-use tile

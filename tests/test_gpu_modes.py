@@ -213,6 +213,31 @@ def test_batched_uneven(fs, cap):
         fs.set_tuning(reset=True)
 
 
+def test_batched_out_buffers(fs):
+    # caller-supplied outputs, reused by a second call on other values, and
+    # refused when too small
+    b = W.batched_fem2d(5, 1e3, 2e4, seed=17)
+    bi, bj, bs, bm, bn = b.concat()
+    N, L = int(bn.sum()), len(bi)
+    out = (torch.empty(N + b.nb, dtype=torch.int32, device="cuda"),
+           torch.empty(L, dtype=torch.int32, device="cuda"),
+           torch.empty(L, dtype=torch.float64, device="cuda"))
+    for scale in (1.0, -0.5):
+        s2 = bs * scale
+        res = fs.assemble_batched(to_dev(bi), to_dev(bj), to_dev(s2),
+                                  b.trip_off, bm, bn, out=out)
+        assert res.prS.data_ptr() == out[2].data_ptr()
+        for q, tq in enumerate(b.mats):
+            ref = oracle.assemble(tq.ii, tq.jj, tq.ss * scale, tq.m, tq.n)
+            jc, ir, pr = res.matrix(q)
+            np.testing.assert_array_equal(jc.cpu().numpy(), ref.jcS)
+            np.testing.assert_array_equal(ir.cpu().numpy(), ref.irS)
+            assert pr.cpu().numpy().tobytes() == ref.prS.tobytes()
+    with pytest.raises(ValueError):
+        fs.assemble_batched(to_dev(bi), to_dev(bj), to_dev(bs), b.trip_off,
+                            bm, bn, out=(out[0][:N], out[1], out[2]))
+
+
 def test_batched_reuse_and_default_dims(fs):
     mats = []
     for s in (5, 20, 9):
