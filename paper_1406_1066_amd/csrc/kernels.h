@@ -1683,6 +1683,25 @@ __device__ __forceinline__ void bin_load(const ChunkArgs<VT>& a, const BinSrc& s
   }
 }
 
+// LDS of the bin kernel (bytes, capacity CAP).  The small arrays that
+// threads address by their own index come first, where LDS instructions
+// reach them by immediate offsets (below 64 KB), then three regions of 8CAP
+// bytes whose tenants change phase by phase (see bin_fast), and 32 bytes of
+// padding for reads past the last region's end.
+constexpr int al16(int x) { return (x + 15) & ~15; }
+template <int CAP>
+struct BinLds {
+  static constexpr int kMisc = 0;                          // int64[8]
+  static constexpr int kWave = 64;                         // u32[64]
+  static constexpr int kCd = 320;                          // u32[CAP+1]
+  static constexpr int kGs = al16(kCd + 4 * (CAP + 1));    // u32[CAP+1]
+  static constexpr int kGrow = al16(kGs + 4 * (CAP + 1));  // u32[CAP]
+  static constexpr int kR0 = al16(kGrow + 4 * CAP);
+  static constexpr int kR1 = kR0 + 8 * CAP;
+  static constexpr int kR2 = kR1 + 8 * CAP;
+  static constexpr int kBytes = kR2 + 8 * CAP + 32;
+};
+
 // Fast path: the bin's triplets fit the LDS and are already in registers.
 // Equal (column,row) pairs are grouped by hashing straight away and the
 // triplets of a pair are counted at their pair's hash slot.  Each rank cell
@@ -1695,18 +1714,18 @@ __device__ __forceinline__ void bin_load(const ChunkArgs<VT>& a, const BinSrc& s
 // bin (ticket `tk`, taken by thread 0) has its range and entries fetched
 // into `nx`.  Returns base + distinct count.
 //
-// LDS (bytes, capacity CAP; a region's later tenants take it once the
-// earlier ones are dead):
-//   [0, 8CAP)         hash keys u32[2CAP] -> distinct list u32[CAP]
-//                     -> placed values VT[CAP]
-//   [8CAP, 16CAP)     triplets per hash slot u32[2CAP] -> (output, first
-//                     place) per hash slot -> k-ordered values VT[CAP]
-//   [16CAP, 24CAP)    entry rows and columns u32[CAP] each (unshared
-//                     columns) -> (row, triplets) per distinct u32x2[CAP]
-//                     -> placed k u32[CAP] + group of placed u32[CAP]
-//   [24CAP, 28CAP)    row of each output
-//   [28CAP, 32CAP+4)  (distinct, triplets) per rank cell, then scanned
-//   [32CAP+4, 36CAP+8) first place of each output's group (+ the end)
+// LDS (BinLds; a region's later tenants take it once the earlier ones are
+// dead):
+//   R0 (8CAP)   hash keys u32[2CAP] -> distinct list u32[CAP]
+//               -> placed values VT[CAP]
+//   R1 (8CAP)   triplets per hash slot u32[2CAP] -> (output, first place)
+//               per hash slot -> k-ordered values VT[CAP]
+//   R2 (8CAP)   entry rows and columns u32[CAP] each (unshared columns)
+//               -> (row, triplets) per distinct u32x2[CAP] -> placed k
+//               u32[CAP] + group of placed u32[CAP]
+//   grow        row of each output
+//   cd          (distinct, triplets) per rank cell, then scanned
+//   gs          first place of each output's group (+ the end)
 template <typename VT, int CAP, int NT, bool KEYS>
 __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
                             const ChunkCtx<VT, CAP, NT>& x,
@@ -1723,20 +1742,23 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   // the hash table then holds the keys themselves, else entry indices
   const bool keyed = src.bcol == nullptr;
   FSP_PHASE(a, q, 1)
+  using LY = BinLds<CAP>;
   unsigned char* sm = x.smem;
-  uint32_t* ht = reinterpret_cast<uint32_t*>(sm);
+  int64_t* misc = reinterpret_cast<int64_t*>(sm + LY::kMisc);
+  uint32_t* wave = reinterpret_cast<uint32_t*>(sm + LY::kWave);
+  uint32_t* ht = reinterpret_cast<uint32_t*>(sm + LY::kR0);
   uint32_t* dlist = ht;
-  VT* mval = reinterpret_cast<VT*>(sm);
-  uint32_t* hcnt = reinterpret_cast<uint32_t*>(sm + 8 * CAP);
-  VT* sval = reinterpret_cast<VT*>(sm + 8 * CAP);
-  uint32_t* row = reinterpret_cast<uint32_t*>(sm + 16 * CAP);
-  uint32_t* col = reinterpret_cast<uint32_t*>(sm + 20 * CAP);
-  uint2* drc = reinterpret_cast<uint2*>(sm + 16 * CAP);
-  uint32_t* mk = reinterpret_cast<uint32_t*>(sm + 16 * CAP);
-  uint32_t* mgrp = reinterpret_cast<uint32_t*>(sm + 20 * CAP);
-  uint32_t* grow = reinterpret_cast<uint32_t*>(sm + 24 * CAP);
-  uint32_t* cd = reinterpret_cast<uint32_t*>(sm + 28 * CAP);
-  uint32_t* gs = reinterpret_cast<uint32_t*>(sm + 32 * CAP + 4);
+  VT* mval = reinterpret_cast<VT*>(sm + LY::kR0);
+  uint32_t* hcnt = reinterpret_cast<uint32_t*>(sm + LY::kR1);
+  VT* sval = reinterpret_cast<VT*>(sm + LY::kR1);
+  uint32_t* row = reinterpret_cast<uint32_t*>(sm + LY::kR2);
+  uint32_t* col = reinterpret_cast<uint32_t*>(sm + LY::kR2 + 4 * CAP);
+  uint2* drc = reinterpret_cast<uint2*>(sm + LY::kR2);
+  uint32_t* mk = reinterpret_cast<uint32_t*>(sm + LY::kR2);
+  uint32_t* mgrp = reinterpret_cast<uint32_t*>(sm + LY::kR2 + 4 * CAP);
+  uint32_t* grow = reinterpret_cast<uint32_t*>(sm + LY::kGrow);
+  uint32_t* cd = reinterpret_cast<uint32_t*>(sm + LY::kCd);
+  uint32_t* gs = reinterpret_cast<uint32_t*>(sm + LY::kGs);
 
   // rank cells: distinct pairs (low half) and triplets (high half) of each
   // (column, row range) cell
@@ -1860,7 +1882,7 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
     }
   }
   FSP_PHASE(a, q, 12)
-  if (tid == 0) x.misc()[7] = tk;
+  if (tid == 0) misc[7] = tk;
   FSP_PHASE(a, q, 13)
   __syncthreads();
   // the groups are complete: representatives add the rest of their group's
@@ -1875,14 +1897,14 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   }
   __syncthreads();
   // next bin: its range now, its entries once the placement is done
-  nx.q = (int)x.misc()[7];
+  nx.q = (int)misc[7];
   uint32_t nfill = 0;
   bin_bounds(src, nx, nfill);
 
   FSP_PHASE(a, q, 3)
   // distinct pairs and triplets per cell -> offsets; publish the bin's count
   // now, read the prefix of the earlier bins only when emitting
-  const uint32_t D = lds_excl_scan<NT>(cd, ncell + 1, x.wave()) & 0xFFFFu;
+  const uint32_t D = lds_excl_scan<NT>(cd, ncell + 1, wave) & 0xFFFFu;
   if (tid < 64) lookback_publish(a.status, q, pack_agg((uint64_t)span, D));
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
@@ -2007,17 +2029,17 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
   if (tid < 64) {
     const int64_t b = lookback_wait(a.status, q, pack_agg((uint64_t)span, D), probe);
     if (tid == 0) {
-      x.misc()[1] = b & kLow31;
-      x.misc()[5] = (b >> 31) + span;  // compact triplets up to this bin's end
-      x.misc()[6] = (b >> 31) - e0;
+      misc[1] = b & kLow31;
+      misc[5] = (b >> 31) + span;  // compact triplets up to this bin's end
+      misc[6] = (b >> 31) - e0;
     }
   }
   __syncthreads();
   FSP_PHASE(a, q, 9)
 
   // emit
-  const int64_t base = x.misc()[1];
-  const int64_t pshift = x.misc()[6];
+  const int64_t base = misc[1];
+  const int64_t pshift = misc[6];
   // perm and slot: from the thread's own triplets (uniq), else from the
   // placed ones
   if (a.perm) {
@@ -2206,7 +2228,7 @@ k_slow_emit(ChunkArgs<VT> a, const int32_t* __restrict__ binstart,
 // share a CU.
 template <int CAP, int NT>
 constexpr int bin_waves() {
-  constexpr int blocks = (160 * 1024) / Lds<CAP>::kBytes;
+  constexpr int blocks = (160 * 1024) / BinLds<CAP>::kBytes;
   constexpr int w = blocks * (NT / 64) / 4;
   return w >= 1 && w <= 4 ? w : 1;
 }
@@ -2216,9 +2238,9 @@ __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(bin_waves<CAP, NT>())))
 k_bin(ChunkArgs<VT> a, BinSrc src, int32_t w) {
   constexpr int EPT = CAP / NT;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[Lds<CAP>::kBytes];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[BinLds<CAP>::kBytes];
   ChunkCtx<VT, CAP, NT> x{smem};
-  int64_t* misc = x.misc();
+  int64_t* misc = reinterpret_cast<int64_t*>(smem + BinLds<CAP>::kMisc);
   const int N = a.N;
   const int B = src.B;
   if (threadIdx.x == 0) misc[0] = (int64_t)atomicAdd(src.tick, 1u);
