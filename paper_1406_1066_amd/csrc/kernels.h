@@ -2020,7 +2020,11 @@ __device__ int64_t bin_fast(const ChunkArgs<VT>& a, const BinSrc& src,
         t += 4;
       }
       uint32_t rk = ((r8[0] + r8[1]) + (r8[2] + r8[3])) + ((r8[4] + r8[5]) + (r8[6] + r8[7]));
-      for (; t < g1; ++t) rk += mk[t] < kk ? 1u : 0u;
+      for (; t + 2 <= g1; t += 2) {
+        const uint32_t v0 = mk[t], v1 = mk[t + 1];
+        rk += (v0 < kk ? 1u : 0u) + (v1 < kk ? 1u : 0u);
+      }
+      if (t < g1) rk += mk[t] < kk ? 1u : 0u;
       sval[g0 + rk] = mval[p];
       spos[jj] = g0 + rk;
     }
