@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstdint>
 #include <cstdio>
@@ -234,7 +235,6 @@ constexpr int kScanIPT = 16;
 constexpr int64_t kScanTile = (int64_t)kScanNT * kScanIPT;
 constexpr int64_t kDenseBins = 16384;       // LDS counters of the dense mode
 constexpr int kBinFill = 80;                // percent of the capacity per bin
-constexpr int kSlotFill = 88;               // the same with fixed-capacity bins
 constexpr int64_t kDenseMatrix = 8 << 20;   // tiles x bins counters
 // claim tiles: 256 threads with 8 triplets each (2048 per tile).  Measured
 // on the fixed-capacity scatter of batched_64 (ms): 256x8 0.52, 512x8 0.56,
@@ -277,7 +277,16 @@ void set_divisor(Geom& g, int64_t w) {
   }
 }
 
-void set_width(Geom& g, int64_t L, int64_t N, int cap, int fill) {
+// Fill (percent) of fixed-capacity bins: the mean m of a bin whose count of
+// randomly placed triplets (about Poisson, standard deviation sqrt(m)) stays
+// kSlotSigmas deviations below the capacity, m + kSlotSigmas*sqrt(m) = cap.
+constexpr double kSlotSigmas = 5.8;
+double slot_fill(int cap) {
+  const double r = 0.5 * (-kSlotSigmas + std::sqrt(kSlotSigmas * kSlotSigmas + 4.0 * cap));
+  return 100.0 * r * r / cap;
+}
+
+void set_width(Geom& g, int64_t L, int64_t N, int cap, double fill) {
   int64_t w = 1;
   if (L > 0) {
     const double target =
@@ -310,9 +319,9 @@ Geom make_geom(int64_t L, int64_t N, int cap, int force_mode, int blk,
   if (force_mode == 1 + kDense && fits_dense) g.mode = kDense;
   if (force_mode == 1 + kSlot && fits_slot) g.mode = kSlot;
   if (force_mode == 1 + kClaim) g.mode = kClaim;
-  // fixed places: fuller bins still (kSlotFill; a place overflows only far
+  // fixed places: fuller bins still (slot_fill: a place overflows only far
   // out in the tail of a bin's size)
-  if (g.mode == kSlot) set_width(g, L, N, cap, kSlotFill);
+  if (g.mode == kSlot) set_width(g, L, N, cap, slot_fill(cap));
   g.dense = g.mode == kDense;
   if (g.dense) {
     // tiles x bins count matrix: at most kDenseMatrix words, and while at
