@@ -922,13 +922,33 @@ const char* fsparse_status_string(int s) {
   }
 }
 
+// Workspace of a call with tuning tu, with room for the geometry of a refit
+// after fixed-capacity places overflow.
+static size_t workspace_bytes_for(int64_t len, int64_t ncols, int32_t nb, fsparse_dtype dt,
+                           const Tuning& tu) {
+  return std::max(make_layout(len, ncols, nb, esize_of(dt), tu).total,
+                  make_layout(len, ncols, nb, esize_of(dt), tu, true).total);
+}
+
+// Tuning of the new triplets' own assembly in delayed assembly: bins of at
+// most 2048 entries (512 threads a workgroup).  Appended triplets are a part
+// of the input whose density can vary across their columns (the growing
+// region of a mesh, say); the fixed-capacity fill at 2048 entries (88%)
+// leaves them a wider relative margin than 4096-entry bins (91%), which on
+// the last tenth of fem3d_100 overflowed and took the counted redo.
+static Tuning append_tuning() {
+  Tuning tu = tuning();
+  if (tu.cap > 2048) {
+    tu.cap = 2048;
+    tu.cblock = 512;
+  }
+  return tu;
+}
+
 size_t fsparse_workspace_bytes(int64_t len, int64_t ncols, int32_t nb,
                                fsparse_dtype dt) {
   if (len < 0 || ncols < 0 || nb < 1 || check_dt(dt) != FSPARSE_OK) return 0;
-  // room for the geometry of a refit after fixed-capacity places overflow
-  const Tuning tu = tuning();
-  return std::max(make_layout(len, ncols, nb, esize_of(dt), tu).total,
-                  make_layout(len, ncols, nb, esize_of(dt), tu, true).total);
+  return workspace_bytes_for(len, ncols, nb, dt, tuning());
 }
 
 // Default dimensions; with f64, ii and jj point to doubles (an index that is
@@ -998,7 +1018,8 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
                              hipStream_t stream, int src,
                              const fsp::Expand* ex,
                              const void* si = nullptr, void* piS = nullptr,
-                             bool keep_order = false, Layout* lo_out = nullptr) {
+                             bool keep_order = false, Layout* lo_out = nullptr,
+                             const Tuning* tu_in = nullptr) {
   if (info) {
     info->m = m;
     info->n = n;
@@ -1014,7 +1035,7 @@ static fsparse_status assemble_impl(const int32_t* ii, const int32_t* jj,
     if (info) info->nnz = len;
     return FSPARSE_E_CAPACITY;
   }
-  Tuning tu = tuning();
+  Tuning tu = tu_in ? *tu_in : tuning();
   Layout lo = make_layout(len, n, 1, esize_of(dt), tu);
   if (nosync && lo.g.mode == kSlot) {
     tu.bmode = 1 + kClaim;
@@ -1522,7 +1543,7 @@ size_t fsparse_append_workspace_bytes(int64_t nnzA, int64_t len, int64_t n,
   // the larger of the two paths: merge (plain calls) and re-assembly of all
   // the pairs as triplets (plans, dropped zeros)
   const size_t w = fsparse_workspace_bytes(nnzA + len, n, 1, dt);
-  const size_t wm = fsparse_workspace_bytes(len, n, 1, dt);
+  const size_t wm = workspace_bytes_for(len, n, 1, dt, append_tuning());
   if (!w || !wm) return 0;
   return std::max(append_head(nnzA + len, dt) + w, merge_layout(len, n, n, dt).head + wm);
 }
@@ -1656,10 +1677,12 @@ static fsparse_status append_merge(const int32_t* jcA, const int32_t* irA,
   // B: the new triplets alone, ordered, with their sorted order kept
   Layout lo{};
   fsparse_info ib{};
+  const Tuning tb = append_tuning();
   fsparse_status st = assemble_impl(ii, jjB, ss, dt, len, m, nB, 0, FSPARSE_ORDERED, jcB,
                                     nB + 1, irB, prB, std::max<int64_t>(len, 1), slotB,
                                     ws2, ws_bytes - ml.head, nullptr, &ib, stream,
-                                    fsp::kIdxI32, nullptr, nullptr, nullptr, true, &lo);
+                                    fsp::kIdxI32, nullptr, nullptr, nullptr, true, &lo,
+                                    &tb);
   if (st != FSPARSE_OK) return st;
   const int32_t* permB = at<int32_t>(ws2, lo.perm);
   const int32_t* segB = at<int32_t>(ws2, lo.seg);
