@@ -273,3 +273,24 @@ def test_uneven_column_density_refit(fs, cap):
     ii = rng.integers(1, m + 1, jj.size).astype(np.int32)
     ss = rng.standard_normal(jj.size)
     check(fs, ii, jj, ss, m, n)
+
+
+@pytest.mark.parametrize("sv", ["binned", "by_k"])
+def test_uneven_density_refit_at_4096(fs, sv):
+    # the shipped shape of the mesh inputs (4096-entry fixed-capacity bins,
+    # 1024 threads), with values binned or read by k: bins sized for the
+    # average density overflow where the columns are ten times denser, and
+    # the call redoes the placement counted
+    fs.set_tuning(chunk_cap=4096, chunk_block=1024, bin_mode="slot",
+                  slot_values=sv)
+    try:
+        rng = np.random.default_rng(21)
+        n, m = 100_000, 5000
+        jj = np.concatenate([rng.integers(1, n // 2 + 1, 100_000),
+                             rng.integers(n // 2 + 1, n + 1, 1_000_000)])
+        jj = jj[rng.permutation(jj.size)].astype(np.int32)
+        ii = rng.integers(1, m + 1, jj.size).astype(np.int32)
+        ss = rng.standard_normal(jj.size)
+        check(fs, ii, jj, ss, m, n)
+    finally:
+        fs.set_tuning(reset=True)
