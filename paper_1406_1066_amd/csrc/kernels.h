@@ -2349,7 +2349,7 @@ __global__ void k_batched_jcs(const int32_t* __restrict__ jcg,
   }
   int64_t first = col_off[lo], start = first + lo, next = col_off[lo + 1] + lo + 1;
   int32_t jb = jcg[first];
-  for (; idx < p1; idx += stride) {
+  while (idx < p1) {
     while (idx >= next) {
       ++lo;
       first = col_off[lo];
@@ -2357,7 +2357,19 @@ __global__ void k_batched_jcs(const int32_t* __restrict__ jcg,
       next = col_off[lo + 1] + lo + 1;
       jb = jcg[first];
     }
-    jcS[idx] = jcg[first + (idx - start)] - jb;
+    if (idx + 3 * stride < min(p1, next)) {
+      // four positions of one matrix: their loads in flight together
+      const int32_t* src = jcg + first + (idx - start);
+      const int32_t v0 = src[0], v1 = src[stride], v2 = src[2 * stride], v3 = src[3 * stride];
+      jcS[idx] = v0 - jb;
+      jcS[idx + stride] = v1 - jb;
+      jcS[idx + 2 * stride] = v2 - jb;
+      jcS[idx + 3 * stride] = v3 - jb;
+      idx += 4 * stride;
+    } else {
+      jcS[idx] = jcg[first + (idx - start)] - jb;
+      idx += stride;
+    }
   }
 }
 
